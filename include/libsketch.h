@@ -1,0 +1,139 @@
+/*
+ * libsketch: structured random sketching on AMD Instinct MI355X (gfx950).
+ *
+ * Implements the sketching step and the least-squares / low-rank drivers of
+ * Camano, Epperly, Meyer, Tropp, "Faster Linear Algebra Algorithms with
+ * Structured Random Matrices" (arXiv 2508.21189).
+ *
+ * Orientation. A sketch is the short-fat matrix S (d x n); the paper's test
+ * matrix is Omega = S^T (n x d). sketch_apply computes S A (the paper's
+ * Psi^T A, Alg. 3 line 2); sketch_apply_T computes A S^T (the paper's
+ * A Omega, Alg. 1 line 2).
+ *
+ * Conventions for every entry point:
+ *   - Matrix pointers are DEVICE pointers owned by the caller, unless a
+ *     parameter says "host". Scalars and info structs are host memory.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream)
+ *     and is asynchronous unless the function says it synchronizes.
+ *   - Return value: 0 = success; negative = error, nothing was written to
+ *     the outputs and sketch_last_error() (thread-local) explains why;
+ *     positive = warning, the outputs are valid (see each function).
+ *   - Non-finite inputs are propagated, not checked.
+ *   - A sketch handle is immutable after creation; concurrent calls with
+ *     the same handle on different streams are safe except that calls
+ *     passing ws = NULL share the handle's internal workspace and must be
+ *     serialized by the caller.
+ */
+#ifndef LIBSKETCH_H
+#define LIBSKETCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sk_sketch* sketch_t;
+
+/* Sketch kinds. */
+enum {
+  SK_SPARSESTACK = 0, /* Def. 1.5: d rows in zeta blocks of d/zeta; one +-1/sqrt(zeta) per block per column */
+  SK_GAUSSIAN = 1,    /* Def. 1.4: iid N(0, 1/d) entries */
+  SK_SRTT = 2,        /* eq. (1.1) with a uniform restriction: (1/sqrt(d)) R H D, H = Walsh-Hadamard */
+  SK_IDENTITY_TEST = 99 /* S = I (d = n); exists to test the drivers against exact least squares */
+};
+
+/* Element types. */
+enum { SK_F64 = 0, SK_F32 = 1, SK_BF16 = 2 };
+/* Matrix layouts. */
+enum { SK_ROW_MAJOR = 0, SK_COL_MAJOR = 1 };
+/* Status codes. */
+enum {
+  SK_OK = 0,
+  SK_E_INVAL = -1,  /* invalid argument */
+  SK_E_NOMEM = -2,  /* device allocation failed */
+  SK_E_HIP = -3,    /* HIP runtime error */
+  SK_E_NOTSUP = -4, /* combination not supported */
+  SK_W_RANKDEF = 1, /* warning: the sketched matrix is numerically rank deficient */
+  SK_W_NOCONV = 2   /* warning: the iteration limit was reached before the tolerance */
+};
+
+/*
+ * Create a sketch S (d x n) on the current HIP device.
+ *   kind  SK_SPARSESTACK: requires 1 <= zeta <= d and d % zeta == 0.
+ *         The bucket s_it in [0, d/zeta) and sign rho_it of column i,
+ *         block t are drawn from Philox4x32-10 (Salmon et al., SC'11) with
+ *         key = seed and counter (i mod 2^32, i >> 32, t / 4, 1), word t % 4:
+ *         rho = +1 iff bit 0 is 0; s = ((word >> 1) * (d/zeta)) >> 31.
+ *         Row t*(d/zeta) + s of S holds rho/sqrt(zeta) (Def. 1.5).
+ *   kind  SK_GAUSSIAN: zeta ignored; entries from Philox + Box-Muller.
+ *   kind  SK_SRTT: zeta ignored; requires d <= 2^ceil(log2 n).
+ *   kind  SK_IDENTITY_TEST: requires d == n.
+ * Nothing about S is stored beyond its parameters (and, for SRTT, the d
+ * sampled row indices): entries are regenerated from the seed on demand.
+ * Returns NULL on error (see sketch_last_error). Synchronizes the device.
+ */
+sketch_t sketch_create(int kind, int64_t d, int64_t n, int zeta, uint64_t seed);
+
+/* Release a handle and its internal workspace. NULL is accepted. */
+int sketch_destroy(sketch_t S);
+
+/* Thread-local description of the last error (never NULL). */
+const char* sketch_last_error(void);
+
+/* Read back the parameters of a handle (any pointer may be NULL). */
+int sketch_info(sketch_t S, int* kind, int64_t* d, int64_t* n, int* zeta, uint64_t* seed);
+
+/*
+ * SA = S A.
+ *   A   n x m matrix of dtype_in (SK_F64, SK_F32 or SK_BF16), layout
+ *       SK_ROW_MAJOR (element (i,c) at A[i*lda + c], lda >= m).
+ *   SA  d x m row-major (element (j,c) at SA[j*ldsa + c], ldsa >= m) of
+ *       dtype_out: SK_F64 or SK_F32. F64 input accumulates in F64; F32 and
+ *       BF16 inputs accumulate in F32 (BF16 values are exact in F32).
+ *   ws  device workspace of ws_bytes >= sketch_workspace_size(...), or NULL
+ *       to use a workspace owned by the handle.
+ * The result is deterministic: the same inputs give bitwise identical SA on
+ * every run (no atomics; fixed summation order).
+ */
+int sketch_apply(sketch_t S, int dtype_in, int layout, int64_t m, const void* A, int64_t lda,
+                 int dtype_out, void* SA, int64_t ldsa, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Y = A S^T (the paper's A Omega): A is rows x n row-major (lda >= n) of
+ * dtype_in, Y is rows x d row-major (ldy >= d) of dtype_out.
+ */
+int sketch_apply_T(sketch_t S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out,
+                   void* Y, int64_t ldy, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes needed by sketch_apply (op 0) or sketch_apply_T (op 1). */
+int sketch_workspace_size(sketch_t S, int op, int dtype_in, int64_t m, size_t* bytes);
+
+/*
+ * Z = S^T Y (adjoint; a test helper): Y is d x m row-major F64 (ldy >= m),
+ * Z is n x m row-major F64 (ldz >= m). SparseStack only.
+ */
+int sketch_adjoint(sketch_t S, int64_t m, const double* Y, int64_t ldy, double* Z, int64_t ldz, void* stream);
+
+/*
+ * Export the SparseStack pattern computed by the device hash:
+ * bucket[i*zeta + t] = s_it (int32), sign[i*zeta + t] = rho_it (int8, +-1).
+ */
+int sketch_pattern(sketch_t S, int32_t* bucket, int8_t* sign, void* stream);
+
+/*
+ * Kernel timing (measurement support, not part of any algorithm).
+ *   mode 1: enable and reset; mode 0: disable and reset (both synchronize
+ *   the device); mode 2: query. While enabled, every call through the handle
+ *   records a HIP event pair on its stream around its dominant kernel (the
+ *   sketch kernel of sketch_apply / sketch_apply_T). A query waits for the
+ *   recorded events and returns the summed elapsed milliseconds and the
+ *   number of timed launches (either pointer may be NULL).
+ */
+int sketch_timing(sketch_t S, int mode, double* total_ms, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBSKETCH_H */

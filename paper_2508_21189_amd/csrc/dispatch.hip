@@ -1,0 +1,109 @@
+// Sketch-kind dispatch for sketch_apply / sketch_apply_T, plus small helpers.
+#include "sk_drivers.hpp"
+
+#include <algorithm>
+
+namespace sk {
+
+template <typename Ti, typename To>
+__global__ void convert_kernel(const Ti* __restrict__ in, int64_t ldi, To* __restrict__ out, int64_t ldo,
+                               int64_t rows, int64_t cols) {
+  const int64_t total = rows * cols;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = idx / cols, c = idx - r * cols;
+    out[r * ldo + c] = (To)in[r * ldi + c];
+  }
+}
+
+template <typename To>
+__global__ void convert_bf16_kernel(const uint16_t* __restrict__ in, int64_t ldi, To* __restrict__ out, int64_t ldo,
+                                    int64_t rows, int64_t cols) {
+  const int64_t total = rows * cols;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = idx / cols, c = idx - r * cols;
+    out[r * ldo + c] = (To)bf16_to_f32(in[r * ldi + c]);
+  }
+}
+
+int launch_convert(int dtype_in, const void* in, int64_t ldi, int dtype_out, void* out, int64_t ldo, int64_t rows,
+                   int64_t cols, hipStream_t st) {
+  const int64_t total = rows * cols;
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 8192));
+  if (dtype_out != SK_F64 && dtype_out != SK_F32) {
+    set_error("convert: output must be F64 or F32");
+    return SK_E_NOTSUP;
+  }
+#define SK_CONV(TI, TO) \
+  hipLaunchKernelGGL((convert_kernel<TI, TO>), dim3(blocks), dim3(256), 0, st, (const TI*)in, ldi, (TO*)out, ldo, rows, cols)
+  if (dtype_in == SK_F64 && dtype_out == SK_F64) SK_CONV(double, double);
+  else if (dtype_in == SK_F64 && dtype_out == SK_F32) SK_CONV(double, float);
+  else if (dtype_in == SK_F32 && dtype_out == SK_F64) SK_CONV(float, double);
+  else if (dtype_in == SK_F32 && dtype_out == SK_F32) SK_CONV(float, float);
+  else if (dtype_out == SK_F64)
+    hipLaunchKernelGGL((convert_bf16_kernel<double>), dim3(blocks), dim3(256), 0, st, (const uint16_t*)in, ldi,
+                       (double*)out, ldo, rows, cols);
+  else
+    hipLaunchKernelGGL((convert_bf16_kernel<float>), dim3(blocks), dim3(256), 0, st, (const uint16_t*)in, ldi,
+                       (float*)out, ldo, rows, cols);
+#undef SK_CONV
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+int apply_workspace(const sk_sketch* S, int op, int dtype_in, int64_t m, size_t* bytes) {
+  *bytes = 0;
+  if (op == 0 && S->kind == SK_SPARSESTACK) {
+    RowsPlan p;
+    // alignment is unknown here: plan for the 16-byte path (same partial size)
+    int rc = plan_rows(S, dtype_in, m, nullptr, m, &p);
+    if (rc != SK_OK) {
+      // fall back to a size estimate independent of alignment
+      p.n_chunks = 256;
+      p.partial_bytes = (size_t)p.n_chunks * S->d * m * (dtype_in == SK_F64 ? 8 : 4);
+    }
+    *bytes = p.partial_bytes;
+  }
+  return SK_OK;
+}
+
+int apply_dispatch(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t lda, int dtype_out, void* SA,
+                   int64_t ldsa, void* ws, size_t ws_bytes, hipStream_t st) {
+  switch (S->kind) {
+    case SK_IDENTITY_TEST:
+      return launch_convert(dtype_in, A, lda, dtype_out, SA, ldsa, S->n, m, st);
+    case SK_SPARSESTACK: {
+      RowsPlan p;
+      int rc = plan_rows(S, dtype_in, m, A, lda, &p);
+      if (rc != SK_OK) return rc;
+      void* w = ws;
+      if (w) {
+        if (ws_bytes < p.partial_bytes) {
+          set_error("sketch_apply: workspace too small (see sketch_workspace_size)");
+          return SK_E_INVAL;
+        }
+      } else {
+        rc = handle_workspace(S, p.partial_bytes, &w);
+        if (rc != SK_OK) return rc;
+      }
+      return launch_rows_apply(S, p, dtype_in, m, A, lda, dtype_out, SA, ldsa, w, st);
+    }
+    default:
+      set_error("sketch_apply: this sketch kind is not available yet");
+      return SK_E_NOTSUP;
+  }
+}
+
+int apply_T_dispatch(sk_sketch* S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out, void* Y,
+                     int64_t ldy, void* ws, size_t ws_bytes, hipStream_t st) {
+  (void)ws;
+  (void)ws_bytes;
+  if (S->kind == SK_IDENTITY_TEST) return launch_convert(dtype_in, A, lda, dtype_out, Y, ldy, rows, S->n, st);
+  set_error("sketch_apply_T: this sketch kind is not available yet");
+  return SK_E_NOTSUP;
+}
+
+void drivers_release(sk_sketch* S) { (void)S; }
+
+}  // namespace sk

@@ -1,0 +1,130 @@
+// Shared definitions for the libsketch HIP sources (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/libsketch.h"
+
+namespace sk {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). One call maps a 128-bit
+// counter and a 64-bit key to 128 random bits; entries of every sketch are
+// pure functions of (seed, index), so any thread can produce any entry.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+// Fourth counter word: separates the independent streams drawn from one seed.
+constexpr uint32_t kTagSparseStack = 1;
+constexpr uint32_t kTagSrttSign = 2;
+constexpr uint32_t kTagSrttSample = 3;
+constexpr uint32_t kTagGauss = 4;
+
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+__host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint64_t p0 = (uint64_t)kPhiloxM0 * c.x;
+    uint64_t p1 = (uint64_t)kPhiloxM1 * c.z;
+    U4 n;
+    n.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+    n.y = (uint32_t)p1;
+    n.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+    n.w = (uint32_t)p0;
+    c = n;
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+  }
+  return c;
+}
+
+__host__ __device__ inline uint32_t word_of(const U4& v, int j) {
+  return j == 0 ? v.x : (j == 1 ? v.y : (j == 2 ? v.z : v.w));
+}
+
+// SparseStack code of one (column i, block t): bucket in [0, nb) and a sign bit
+// (1 = negative). Bits: sign = bit 0 of the word; bucket = ((word >> 1) * nb) >> 31.
+__host__ __device__ inline uint32_t ss_bucket(uint32_t word, uint32_t nb) {
+  return (uint32_t)(((uint64_t)(word >> 1) * nb) >> 31);
+}
+__host__ __device__ inline uint32_t ss_negative(uint32_t word) { return word & 1u; }
+
+// ---------------------------------------------------------------------------
+// bf16 <-> f32 (bf16 is the upper half of an IEEE f32; widening is exact).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline float bf16_to_f32(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  __builtin_memcpy(&f, &u, 4);
+  return f;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side helpers shared by the API and the launchers.
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define SK_HIP(expr)                                       \
+  do {                                                     \
+    hipError_t _e = (expr);                                \
+    if (_e != hipSuccess) return ::sk::hip_fail(_e, #expr); \
+  } while (0)
+
+inline size_t dtype_size(int dt) { return dt == SK_F64 ? 8 : (dt == SK_F32 ? 4 : 2); }
+inline double inv_sqrt_host(double x) { return 1.0 / __builtin_sqrt(x); }
+
+}  // namespace sk
+
+// The handle. Immutable after sketch_create except for the cached workspace.
+struct sk_sketch {
+  int kind = 0;
+  int64_t d = 0, n = 0;
+  int zeta = 1;
+  uint64_t seed = 0;
+  int64_t nb = 0;  // SparseStack buckets per block (d / zeta)
+  int device = 0;
+  uint32_t k0 = 0, k1 = 0;
+  // SRTT: padded length 2^p >= n and the d sampled rows (device, sorted).
+  int64_t npad = 0;
+  int log2npad = 0;
+  int64_t* d_sample = nullptr;
+  std::vector<int64_t> h_sample;
+  // internal workspace (used when the caller passes ws = NULL)
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  // optional timing of the dominant kernel of each call (sketch_timing)
+  mutable bool timing = false;
+  mutable std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+};
+
+namespace sk {
+// Records an event pair around the dominant kernel when timing is enabled.
+struct KernelTimer {
+  const sk_sketch* S;
+  hipStream_t st;
+  hipEvent_t e1 = nullptr;
+  KernelTimer(const sk_sketch* s, hipStream_t stream) : S(s), st(stream) {
+    if (S->timing) {
+      hipEvent_t e0;
+      if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+        (void)hipEventRecord(e0, st);
+        S->events.push_back({e0, e1});
+      } else {
+        e1 = nullptr;
+      }
+    }
+  }
+  ~KernelTimer() {
+    if (e1) (void)hipEventRecord(e1, st);
+  }
+};
+}  // namespace sk

@@ -1,0 +1,24 @@
+// Dispatch layer between the C-ABI and the kernel launchers.
+#pragma once
+#include "sk_launch.hpp"
+
+namespace sk {
+
+int handle_workspace(sk_sketch* S, size_t bytes, void** out);
+
+// Bytes of workspace needed by sketch_apply (op 0) or sketch_apply_T (op 1).
+int apply_workspace(const sk_sketch* S, int op, int dtype_in, int64_t m, size_t* bytes);
+
+int apply_dispatch(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t lda, int dtype_out, void* SA,
+                   int64_t ldsa, void* ws, size_t ws_bytes, hipStream_t st);
+int apply_T_dispatch(sk_sketch* S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out, void* Y,
+                     int64_t ldy, void* ws, size_t ws_bytes, hipStream_t st);
+
+// out (rows x cols, ldo) = (Tout) in (rows x cols, ldi); any dtype pair.
+int launch_convert(int dtype_in, const void* in, int64_t ldi, int dtype_out, void* out, int64_t ldo, int64_t rows,
+                   int64_t cols, hipStream_t st);
+
+// Frees driver-owned device memory attached to a handle.
+void drivers_release(sk_sketch* S);
+
+}  // namespace sk

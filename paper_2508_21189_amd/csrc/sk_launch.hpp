@@ -1,0 +1,35 @@
+// Kernel launchers shared between translation units (host side).
+#pragma once
+#include "sk_common.hpp"
+
+namespace sk {
+
+// Plan of the row-mode SparseStack apply (SA = S A, A row-major n x m).
+struct RowsPlan {
+  int C = 64;            // columns per slab (lanes per wave that hold data)
+  int n_slabs = 1;
+  int R = 128;           // rows per LDS sub-tile
+  int W = 16;            // waves per workgroup
+  int bpg = 1;           // sketch blocks handled by one workgroup
+  int n_groups = 1;      // workgroups sharing one A tile (zeta / bpg, rounded up)
+  int H = 1;             // bucket ranges per block (one wave each)
+  int per_range = 1;     // buckets per range
+  int n_chunks = 1;      // row chunks
+  int64_t rows_per_chunk = 0;
+  int load_bytes = 16;   // 16 or 4: width of the direct global->LDS loads
+  int jb = 64;           // accumulator slots compiled into the kernel
+  size_t lds_bytes = 0;
+  size_t partial_bytes = 0;
+};
+
+// Chooses the plan; returns SK_OK or SK_E_NOTSUP (and sets the error).
+int plan_rows(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t lda, RowsPlan* plan);
+
+int launch_rows_apply(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64_t m, const void* A,
+                      int64_t lda, int dtype_out, void* SA, int64_t ldsa, void* ws, hipStream_t st);
+
+int launch_pattern(const sk_sketch* S, int32_t* bucket, int8_t* sign, hipStream_t st);
+int launch_adjoint(const sk_sketch* S, int64_t m, const double* Y, int64_t ldy, double* Z, int64_t ldz,
+                   hipStream_t st);
+
+}  // namespace sk

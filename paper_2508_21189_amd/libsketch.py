@@ -1,0 +1,172 @@
+"""Python binding of libsketch (ctypes). Argument marshalling only.
+
+Every computation runs in the HIP library (libsketch.so, built for gfx950 by
+paper_2508_21189_amd.build). PyTorch tensors supply device memory and the
+current stream; nothing here computes a result. If the library is missing the
+import fails loudly: there is no fallback path.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libsketch.so")
+
+SK_SPARSESTACK, SK_GAUSSIAN, SK_SRTT, SK_IDENTITY_TEST = 0, 1, 2, 99
+SK_F64, SK_F32, SK_BF16 = 0, 1, 2
+SK_ROW_MAJOR, SK_COL_MAJOR = 0, 1
+SK_OK, SK_E_INVAL, SK_E_NOMEM, SK_E_HIP, SK_E_NOTSUP = 0, -1, -2, -3, -4
+SK_W_RANKDEF, SK_W_NOCONV = 1, 2
+
+KINDS = {"sparsestack": SK_SPARSESTACK, "gaussian": SK_GAUSSIAN, "srtt": SK_SRTT, "identity": SK_IDENTITY_TEST}
+_DT = {torch.float64: SK_F64, torch.float32: SK_F32, torch.bfloat16: SK_BF16}
+_TORCH = {SK_F64: torch.float64, SK_F32: torch.float32, SK_BF16: torch.bfloat16}
+
+_lib = None
+
+_i64 = ctypes.c_int64
+_vp = ctypes.c_void_p
+
+
+class SketchError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libsketch error %d: %s" % (code, msg))
+        self.code = code
+
+
+def load():
+    """Load libsketch.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libsketch.so not built: run `python -m paper_2508_21189_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.sketch_create.restype = _vp
+    lib.sketch_create.argtypes = [ctypes.c_int, _i64, _i64, ctypes.c_int, ctypes.c_uint64]
+    lib.sketch_destroy.argtypes = [_vp]
+    lib.sketch_last_error.restype = ctypes.c_char_p
+    lib.sketch_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_uint64)]
+    lib.sketch_apply.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _i64, _vp, _i64, ctypes.c_int, _vp, _i64, _vp,
+                                 ctypes.c_size_t, _vp]
+    lib.sketch_apply_T.argtypes = [_vp, ctypes.c_int, _i64, _vp, _i64, ctypes.c_int, _vp, _i64, _vp,
+                                   ctypes.c_size_t, _vp]
+    lib.sketch_workspace_size.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _i64, ctypes.POINTER(ctypes.c_size_t)]
+    lib.sketch_adjoint.argtypes = [_vp, _i64, _vp, _i64, _vp, _i64, _vp]
+    lib.sketch_pattern.argtypes = [_vp, _vp, _vp, _vp]
+    lib.sketch_timing.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
+    _bind_drivers(lib)
+    _lib = lib
+    return lib
+
+
+def _bind_drivers(lib):
+    """Argument types of the driver entry points (present once built)."""
+    for name, args in _DRIVER_SIGS.items():
+        fn = getattr(lib, name, None)
+        if fn is not None:
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+
+
+_DRIVER_SIGS = {}
+
+
+def exported_symbols():
+    """Names the header declares; used by the load test."""
+    return ["sketch_create", "sketch_destroy", "sketch_last_error", "sketch_info", "sketch_apply", "sketch_apply_T",
+            "sketch_workspace_size", "sketch_adjoint", "sketch_pattern", "sketch_timing"] + list(_DRIVER_SIGS)
+
+
+def last_error():
+    return load().sketch_last_error().decode()
+
+
+def check(rc):
+    if rc < 0:
+        raise SketchError(rc, last_error())
+    return rc
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Sketch:
+    """Owns a libsketch handle: sketch_create(kind, d, n, zeta, seed)."""
+
+    def __init__(self, kind, d, n, zeta=1, seed=0):
+        lib = load()
+        k = KINDS[kind] if isinstance(kind, str) else int(kind)
+        h = lib.sketch_create(k, int(d), int(n), int(zeta), ctypes.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF))
+        if not h:
+            raise SketchError(SK_E_INVAL, last_error())
+        self.h = ctypes.c_void_p(h)
+        self.kind, self.d, self.n, self.zeta, self.seed = k, int(d), int(n), int(zeta), int(seed)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().sketch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_size(self, op, dtype, m):
+        b = ctypes.c_size_t(0)
+        check(load().sketch_workspace_size(self.h, int(op), _DT[dtype], int(m), ctypes.byref(b)))
+        return b.value
+
+    def apply(self, A, out_dtype=None, out=None, ws=None, stream=None):
+        """SA = S @ A for a row-major (n x m) CUDA tensor A (float64/float32/bfloat16)."""
+        assert A.is_cuda and A.dim() == 2 and A.shape[0] == self.n and A.stride(1) == 1
+        m = A.shape[1]
+        odt = out_dtype or (torch.float64 if A.dtype == torch.float64 else torch.float32)
+        if out is None:
+            out = torch.empty((self.d, m), dtype=odt, device=A.device)
+        assert out.shape == (self.d, m) and out.stride(1) == 1 and out.dtype == odt
+        wsp, wsb = (None, 0) if ws is None else (_ptr(ws), ws.numel() * ws.element_size())
+        check(load().sketch_apply(self.h, _DT[A.dtype], SK_ROW_MAJOR, m, _ptr(A), A.stride(0), _DT[odt], _ptr(out),
+                                  out.stride(0), wsp, wsb, _stream(stream)))
+        return out
+
+    def apply_T(self, A, out_dtype=None, out=None, stream=None):
+        """Y = A @ S^T for a row-major (rows x n) CUDA tensor A."""
+        assert A.is_cuda and A.dim() == 2 and A.shape[1] == self.n and A.stride(1) == 1
+        rows = A.shape[0]
+        odt = out_dtype or (torch.float64 if A.dtype == torch.float64 else torch.float32)
+        if out is None:
+            out = torch.empty((rows, self.d), dtype=odt, device=A.device)
+        check(load().sketch_apply_T(self.h, _DT[A.dtype], rows, _ptr(A), A.stride(0), _DT[odt], _ptr(out),
+                                    out.stride(0), None, 0, _stream(stream)))
+        return out
+
+    def adjoint(self, Y, stream=None):
+        """Z = S^T @ Y (float64, SparseStack only)."""
+        assert Y.is_cuda and Y.dtype == torch.float64 and Y.shape[0] == self.d and Y.stride(1) == 1
+        Z = torch.empty((self.n, Y.shape[1]), dtype=torch.float64, device=Y.device)
+        check(load().sketch_adjoint(self.h, Y.shape[1], _ptr(Y), Y.stride(0), _ptr(Z), Z.stride(0), _stream(stream)))
+        return Z
+
+    def timing(self, mode):
+        """sketch_timing: 1 enable/reset, 0 disable/reset, 2 query -> (total_ms, launches)."""
+        ms, cnt = ctypes.c_double(0), _i64(0)
+        check(load().sketch_timing(self.h, int(mode), ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value
+
+    def pattern(self, device="cuda", stream=None):
+        """(bucket int32 [n, zeta], sign int8 [n, zeta]) from the device hash."""
+        b = torch.empty((self.n, self.zeta), dtype=torch.int32, device=device)
+        s = torch.empty((self.n, self.zeta), dtype=torch.int8, device=device)
+        check(load().sketch_pattern(self.h, _ptr(b), _ptr(s), _stream(stream)))
+        return b, s

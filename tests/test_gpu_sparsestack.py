@@ -1,0 +1,140 @@
+"""GPU parity of the SparseStack hot path against the oracle (through the C-ABI).
+
+  * the device hash reproduces the oracle's (bucket, sign) pattern bit for bit;
+  * applying S to identity columns recovers every entry of S bit for bit;
+  * SA matches the oracle element by element within the summation bound
+    |SA_gpu - SA_ref| <= (c_j + 8) * u * (|S||A|)_jc, where c_j is the number
+    of rows in bucket j and u the unit roundoff of the accumulation type
+    (2^-53 for float64, 2^-24 for float32), on ragged shapes, several tiles,
+    zeta in {1, 4, 8}, one bucket per block (d = zeta), and float32 / bfloat16
+    inputs (compared with the oracle applied to the same rounded values);
+  * results are bitwise reproducible run to run;
+  * S^T (adjoint) matches the oracle and satisfies <SA, Y> = <A, S^T Y>;
+  * at the full 4,194,304 x 200 float64 shape, sampled columns match the
+    oracle computed column by column.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import sketches as sk
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2508_21189_amd import libsketch
+    libsketch.load()
+    return libsketch
+
+
+def _bound(A64, d, zeta, seed, u):
+    """(c_j + 8) * u * (|S||A|) from the oracle's pattern."""
+    n = A64.shape[0]
+    Sabs = abs(sk.sparsestack_csr(n, d, zeta, seed))
+    SA_abs = Sabs @ np.abs(A64)
+    cnt = np.asarray((Sabs != 0).sum(axis=1)).ravel()
+    return (cnt[:, None] + 8.0) * u * SA_abs
+
+
+def _check(gpu, ref, bound):
+    err = np.abs(gpu - ref)
+    ratio = np.max(err / np.maximum(bound, 1e-300))
+    assert np.all(err <= bound), "max err/bound = %g" % ratio
+    return ratio
+
+
+@pytest.mark.parametrize("n,d,zeta,seed", [(1000, 40, 4, 1), (4099, 800, 8, 7), (70000, 200, 4, 3),
+                                          (12345, 17, 1, 5), (3000, 5, 5, 9)])
+def test_pattern_bit_exact(lib, n, d, zeta, seed):
+    S = lib.Sketch("sparsestack", d, n, zeta, seed)
+    b, s = S.pattern()
+    rb, rs = sk.sparsestack_pattern(n, d, zeta, seed)
+    assert np.array_equal(b.cpu().numpy(), rb.astype(np.int32))
+    assert np.array_equal(s.cpu().numpy(), rs)
+
+
+@pytest.mark.parametrize("n,d,zeta", [(300, 40, 4), (1024, 64, 8), (777, 16, 1), (513, 6, 6)])
+def test_apply_identity_recovers_S_bitwise(lib, n, d, zeta):
+    S = lib.Sketch("sparsestack", d, n, zeta, 42)
+    I = torch.eye(n, dtype=torch.float64, device="cuda")
+    got = S.apply(I).cpu().numpy()
+    want = sk.sparsestack_dense(n, d, zeta, 42)
+    assert np.array_equal(got, want)
+
+
+CASES = [
+    (20000, 50, 200, 4, 11),   # workload 1 shape
+    (1037, 7, 40, 4, 2),       # ragged rows, narrow
+    (5000, 65, 96, 8, 3),      # two column slabs (64 + 1)
+    (3001, 129, 800, 8, 4),    # three slabs, 100 buckets per block
+    (2500, 33, 8, 8, 5),       # one bucket per block (d = zeta)
+    (4096, 20, 64, 1, 6),      # CountSketch
+    (300, 1, 30, 3, 7),        # single column (the right-hand side)
+    (9000, 200, 800, 8, 8),    # workload 2 column count, several row tiles
+]
+
+
+@pytest.mark.parametrize("n,m,d,zeta,seed", CASES)
+def test_apply_f64_parity(lib, n, m, d, zeta, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, m)) * np.logspace(0, -3, m)
+    S = lib.Sketch("sparsestack", d, n, zeta, seed)
+    got = S.apply(torch.from_numpy(A).cuda()).cpu().numpy()
+    ref = sk.sparsestack_apply(A, d, zeta, seed)
+    _check(got, ref, _bound(A, d, zeta, seed, 2.0 ** -53))
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("n,m,d,zeta,seed", [(20000, 64, 200, 4, 1), (6007, 100, 2000, 8, 2),
+                                             (3000, 16, 64, 8, 3), (1000, 500, 400, 8, 4)])
+def test_apply_lowprec_parity(lib, dtype, n, m, d, zeta, seed):
+    rng = np.random.default_rng(seed)
+    A = torch.from_numpy(rng.standard_normal((n, m))).cuda().to(torch.float32).to(dtype)
+    A64 = A.to(torch.float64).cpu().numpy()  # the exact values the kernel reads
+    S = lib.Sketch("sparsestack", d, n, zeta, seed)
+    for odt in (torch.float32, torch.float64):
+        got = S.apply(A, out_dtype=odt).to(torch.float64).cpu().numpy()
+        ref = sk.sparsestack_apply(A64, d, zeta, seed)
+        # float32 accumulation, plus the final rounding to float32 output
+        _check(got, ref, _bound(A64, d, zeta, seed, 2.0 ** -24) + 2.0 ** -24 * np.abs(ref))
+
+
+def test_bitwise_reproducible(lib):
+    rng = np.random.default_rng(0)
+    A = torch.from_numpy(rng.standard_normal((50000, 200))).cuda()
+    S = lib.Sketch("sparsestack", 800, 50000, 8, 123)
+    r1 = S.apply(A)
+    for _ in range(5):
+        assert torch.equal(S.apply(A), r1)
+
+
+def test_adjoint(lib):
+    rng = np.random.default_rng(1)
+    n, d, zeta, m = 3000, 96, 8, 5
+    S = lib.Sketch("sparsestack", d, n, zeta, 77)
+    Y = torch.from_numpy(rng.standard_normal((d, m))).cuda()
+    Z = S.adjoint(Y).cpu().numpy()
+    np.testing.assert_allclose(Z, sk.sparsestack_adjoint(Y.cpu().numpy(), n, zeta, 77), rtol=1e-14, atol=1e-14)
+    X = torch.from_numpy(rng.standard_normal((n, m))).cuda()
+    lhs = float((S.apply(X) * Y).sum())
+    rhs = float((X.cpu() * torch.from_numpy(Z)).sum())
+    assert abs(lhs - rhs) < 1e-11 * max(1.0, abs(lhs))
+
+
+def test_full_size_sampled_columns(lib):
+    """4,194,304 x 200 float64 (the coherent workload), d = 800, zeta = 8."""
+    from paper_2508_21189_amd import inputs
+    n, m, d, zeta, seed = 1 << 22, 200, 800, 8, 2000
+    A, b, _, _ = inputs.coherent(n, m, exponent=8.0, seed=200)
+    S = lib.Sketch("sparsestack", d, n, zeta, seed)
+    SA = S.apply(A).cpu().numpy()
+    for c in (0, 57, 199):
+        col = A[:, c].cpu().numpy()[:, None]
+        ref = sk.sparsestack_apply(col, d, zeta, seed)
+        _check(SA[:, c:c + 1], ref, _bound(col, d, zeta, seed, 2.0 ** -53))
+    Sb = S.apply(b[:, None].contiguous()).cpu().numpy()
+    ref = sk.sparsestack_apply(b.cpu().numpy()[:, None], d, zeta, seed)
+    _check(Sb, ref, _bound(b.cpu().numpy()[:, None], d, zeta, seed, 2.0 ** -53))
