@@ -62,8 +62,9 @@ int apply_workspace(const sk_sketch* S, int op, int dtype_in, int64_t m, size_t*
       // fall back to a size estimate independent of alignment
       p.n_chunks = 256;
       p.partial_bytes = (size_t)p.n_chunks * S->d * m * (dtype_in == SK_F64 ? 8 : 4);
+      p.plan_bytes = (size_t)((S->n + 15) / 16 + 1) * S->zeta * (2 * (S->nb + 1) + 64);
     }
-    *bytes = p.partial_bytes;
+    *bytes = p.partial_bytes + p.plan_bytes;
   }
   return SK_OK;
 }
@@ -79,12 +80,12 @@ int apply_dispatch(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t
       if (rc != SK_OK) return rc;
       void* w = ws;
       if (w) {
-        if (ws_bytes < p.partial_bytes) {
+        if (ws_bytes < p.partial_bytes + p.plan_bytes) {
           set_error("sketch_apply: workspace too small (see sketch_workspace_size)");
           return SK_E_INVAL;
         }
       } else {
-        rc = handle_workspace(S, p.partial_bytes, &w);
+        rc = handle_workspace(S, p.partial_bytes + p.plan_bytes, &w);
         if (rc != SK_OK) return rc;
       }
       return launch_rows_apply(S, p, dtype_in, m, A, lda, dtype_out, SA, ldsa, w, st);

@@ -5,7 +5,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/libsketch.h"
+#include "libsketch.h"
 
 namespace sk {
 

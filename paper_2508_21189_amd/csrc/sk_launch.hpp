@@ -19,7 +19,10 @@ struct RowsPlan {
   int load_bytes = 16;   // 16 or 4: width of the direct global->LDS loads
   int jb = 64;           // accumulator slots compiled into the kernel
   size_t lds_bytes = 0;
-  size_t partial_bytes = 0;
+  size_t partial_bytes = 0;  // workspace: per-chunk partial sums
+  size_t plan_bytes = 0;     // workspace: per-tile bucket plans
+  int64_t n_tiles = 0;
+  int rec_bytes = 0, lst_off = 0;
 };
 
 // Chooses the plan; returns SK_OK or SK_E_NOTSUP (and sets the error).

@@ -4,18 +4,24 @@
 // each block t, so SA[t*nb + s, c] = (1/sqrt(zeta)) * sum_{i: s_it = s} rho_it A[i, c].
 //
 // Design (gfx950, one HBM pass over A):
-//  * A workgroup owns a row chunk x a column slab (<= 64 columns, one per lane)
-//    x a group of blocks. It streams its rows through LDS in sub-tiles of R
-//    rows, double-buffered with direct global->LDS loads, so the prefetch of
-//    tile k+1 costs no VGPRs and overlaps the work on tile k.
-//  * For each sub-tile the Philox hash gives (bucket, sign) of every row and
-//    block; one wave per block counting-sorts the rows by bucket (stable, via
-//    wave ballots: no atomics, so the order is deterministic).
+//  * Plan kernel: for every tile of R rows and every block t, the Philox hash
+//    gives (bucket, sign) of each row and one wave counting-sorts the rows by
+//    bucket (stable, via wave ballots: no atomics). The result, bucket offsets
+//    and the sorted row list, is a few KB per tile; it is computed once and
+//    read by every workgroup that covers the tile.
+//  * Sketch kernel: a workgroup owns a row chunk x a column slab (<= 64
+//    columns, one per lane) x a group of blocks. It streams its rows through
+//    LDS in tiles of R rows together with the tiles' plans, double-buffered
+//    with direct global->LDS loads, so the prefetch of tile k+1 costs no VGPRs
+//    and overlaps the work on tile k.
 //  * Each wave owns one block and a contiguous range of its buckets and keeps
-//    one accumulator per bucket per lane in registers. It walks its buckets in
-//    order and, for each, the sorted rows of that bucket: all 64 lanes read
-//    the same row (a broadcast list entry) at consecutive columns (conflict-free
-//    LDS reads) and add +-value into the bucket's register.
+//    one accumulator per bucket per lane in registers. The first row of every
+//    bucket is added by fully unrolled, branch-free code (an empty bucket reads
+//    a zero row), so the LDS reads are independent and pipeline; the further
+//    rows of a bucket (a third of all rows when a tile holds one or two rows
+//    per bucket) are compacted into a short per-wave list and added behind one
+//    uniform test per bucket. All 64 lanes read one row at consecutive
+//    columns: LDS reads are conflict-free.
 //  * At the end of the chunk the accumulators go to a partial buffer
 //    [chunk][d][m]; a second kernel sums the partials in chunk order and scales
 //    by 1/sqrt(zeta). Summation order is fixed, so results are bitwise
@@ -27,16 +33,158 @@
 
 namespace sk {
 
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+__device__ inline void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Direct global->LDS loads: each lane's bytes land at LDS address
+// M0 + lane * width. They are issued from inline assembly so that the
+// compiler's memory-counter bookkeeping does not make every later LDS access
+// wait for them (it cannot tell that they target the other tile buffer); the
+// kernel waits for them explicitly (wait_dma) before the barrier that
+// publishes the tile. M0 is saved and restored around the load.
+__device__ inline void dma_to_lds16(const void* gsrc, uint32_t lds_addr) {
+  uint32_t saved;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\t"
+      "s_mov_b32 m0, %1\n\t"
+      "global_load_lds_dwordx4 %2, off\n\t"
+      "s_mov_b32 m0, %0"
+      : "=&s"(saved)
+      : "s"(lds_addr), "v"(gsrc)
+      : "memory");
+}
+__device__ inline void dma_to_lds4(const void* gsrc, uint32_t lds_addr) {
+  uint32_t saved;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\t"
+      "s_mov_b32 m0, %1\n\t"
+      "global_load_lds_dword %2, off\n\t"
+      "s_mov_b32 m0, %0"
+      : "=&s"(saved)
+      : "s"(lds_addr), "v"(gsrc)
+      : "memory");
+}
+__device__ inline uint32_t lds_addr_of(const void* p) {
+  return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const void*)p;
+}
+
+// ---------------------------------------------------------------------------
+// Plan kernel
+// ---------------------------------------------------------------------------
+struct PlanArgs {
+  int64_t n;
+  int R, zeta, nb, nbits;
+  uint32_t k0, k1;
+  unsigned char* out;  // [tiles][zeta] records of rec_bytes
+  int rec_bytes, lst_off;
+};
+
+// Record of (tile, block t): u16 off[nb + 1] (bucket s holds list entries
+// [off[s], off[s+1])), then at lst_off u16 lst[R]: the tile's rows sorted by
+// bucket, stable, each entry row << 2 | first << 1 | negative, where `first`
+// marks the first row of its bucket.
+__global__ void __launch_bounds__(1024) ss_plan_kernel(PlanArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nthreads = blockDim.x, nwaves = nthreads >> 6;
+  const int R = a.R, nb = a.nb, zeta = a.zeta;
+  const int64_t tile = blockIdx.x;
+  const int64_t r0 = tile * R;
+  const int rv = (int)min((int64_t)R, a.n - r0);
+  uint16_t* codes = (uint16_t*)smem;                          // [zeta][R]
+  uint16_t* rnk = codes + (size_t)zeta * R;                   // [zeta][R]
+  uint32_t* cnts = (uint32_t*)(rnk + (size_t)zeta * R + ((zeta * R) & 1));  // [zeta][nb + 1]
+
+  // Hash: one Philox call gives the words of blocks 4g .. 4g+3 of one row.
+  const int ng = (zeta + 3) / 4;
+  for (int pi = tid; pi < rv * ng; pi += nthreads) {
+    const int g = pi / rv, r = pi - g * rv;
+    const uint64_t i = (uint64_t)(r0 + r);
+    const U4 w = philox4x32_10(U4{(uint32_t)i, (uint32_t)(i >> 32), (uint32_t)g, kTagSparseStack}, a.k0, a.k1);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int t = 4 * g + j;
+      if (t < zeta) {
+        const uint32_t word = word_of(w, j);
+        codes[t * R + r] = (uint16_t)((ss_bucket(word, (uint32_t)nb) << 1) | ss_negative(word));
+      }
+    }
+  }
+  lds_barrier();
+
+  // Stable counting sort of block t's rows by bucket, one wave per block.
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (int t = wave; t < zeta; t += nwaves) {
+    uint32_t* cnt = cnts + t * (nb + 1);
+    const uint16_t* cd = codes + t * R;
+    uint16_t* rk = rnk + t * R;
+    for (int s = lane; s <= nb; s += 64) cnt[s] = 0;
+    for (int c0 = 0; c0 < rv; c0 += 64) {
+      const int r = c0 + lane;
+      const bool valid = r < rv;
+      const uint32_t s = valid ? (uint32_t)(cd[r] >> 1) : 0u;
+      uint64_t mask = __ballot(valid);
+      for (int b = 0; b < a.nbits; ++b) {
+        const bool bit = (s >> b) & 1u;
+        const uint64_t mb = __ballot(bit);
+        mask &= bit ? mb : ~mb;
+      }
+      const uint32_t rank = (uint32_t)__popcll(mask & below);
+      const uint32_t base = valid ? cnt[s] : 0u;
+      if (valid) rk[r] = (uint16_t)(base + rank);
+      if (valid && rank == 0) cnt[s] = base + (uint32_t)__popcll(mask);
+    }
+    // exclusive scan of the counts
+    const int per = (nb + 63) / 64;
+    const int sb = lane * per;
+    uint32_t loc = 0;
+    for (int k = 0; k < per; ++k)
+      if (sb + k < nb) loc += cnt[sb + k];
+    uint32_t inc = loc;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += y;
+    }
+    unsigned char* rec = a.out + (tile * zeta + t) * (int64_t)a.rec_bytes;
+    uint16_t* gof = (uint16_t*)rec;
+    uint16_t* glst = (uint16_t*)(rec + a.lst_off);
+    uint32_t run = inc - loc;
+    for (int k = 0; k < per; ++k) {
+      if (sb + k < nb) {
+        const uint32_t c = cnt[sb + k];
+        cnt[sb + k] = run;
+        gof[sb + k] = (uint16_t)run;
+        run += c;
+      }
+    }
+    if (lane == 63) gof[nb] = (uint16_t)inc;
+    // scatter (stable: rank order = row order within a bucket)
+    for (int c0 = 0; c0 < rv; c0 += 64) {
+      const int r = c0 + lane;
+      if (r < rv) {
+        const uint32_t code = cd[r];
+        const uint32_t rkr = rk[r];
+        glst[cnt[code >> 1] + rkr] = (uint16_t)(((uint32_t)r << 2) | ((rkr == 0u) << 1) | (code & 1u));
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sketch kernel
+// ---------------------------------------------------------------------------
 struct RowsArgs {
   const unsigned char* A;
   int64_t lda_bytes;
   int64_t n, m, d;
   int C, n_slabs, R, bpg, n_groups, H, per_range, n_chunks;
   int64_t rows_per_chunk;
-  int zeta, nb, nbits;
-  uint32_t k0, k1;
+  int zeta, nb;
+  const unsigned char* plan;
+  int rec_bytes, lst_off;
   void* P;
-  int off_codes, off_rnk, off_off, off_lists, tile_bytes;
+  int buf_stride, off_zero, off_plan, plan_dma_bytes, off_xtra;
 };
 
 template <typename Tin>
@@ -44,43 +192,44 @@ struct InType;
 template <>
 struct InType<double> {
   using acc = double;
-  __device__ static double load(const unsigned char* p) { return *(const double*)p; }
 };
 template <>
 struct InType<float> {
   using acc = float;
-  __device__ static float load(const unsigned char* p) { return *(const float*)p; }
 };
 template <>
 struct InType<uint16_t> {  // bf16
   using acc = float;
-  __device__ static float load(const unsigned char* p) { return bf16_to_f32(*(const uint16_t*)p); }
 };
 
-__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-__device__ inline void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
-
-__device__ inline __attribute__((address_space(3))) void* as_lds(void* p) {
-  return (__attribute__((address_space(3))) void*)p;
-}
+// acc += (+-1) * tile value. An entry carries the LDS address of a row
+// (bits 0..30; a multiple of the 64-column row size, so the lane's column
+// offset `base` can be OR-ed in) and the sign (bit 31). The address is one
+// v_and_or; the +-1.0 multiplier is another (masks live in VGPRs).
+typedef __attribute__((address_space(3))) const unsigned char* lds_cptr;
 
 template <typename Tin>
-__device__ inline typename InType<Tin>::acc load_signed(const unsigned char* p, uint32_t neg);
+__device__ inline void fma_entry(typename InType<Tin>::acc& acc, uint32_t base, uint32_t e, uint32_t vmask,
+                                 uint32_t vsgn, uint32_t vone);
 template <>
-__device__ inline double load_signed<double>(const unsigned char* p, uint32_t neg) {
-  uint64_t u = *(const uint64_t*)p;
-  u ^= (uint64_t)neg << 63;
-  return __builtin_bit_cast(double, u);
+__device__ inline void fma_entry<double>(double& acc, uint32_t base, uint32_t e, uint32_t vmask, uint32_t vsgn,
+                                         uint32_t vone) {
+  const double v = *(const __attribute__((address_space(3))) double*)(lds_cptr)(uintptr_t)((e & vmask) | base);
+  const uint64_t sg = (uint64_t)((e & vsgn) | vone) << 32;
+  acc = __builtin_fma(__builtin_bit_cast(double, sg), v, acc);
 }
 template <>
-__device__ inline float load_signed<float>(const unsigned char* p, uint32_t neg) {
-  uint32_t u = *(const uint32_t*)p;
-  return __builtin_bit_cast(float, u ^ (neg << 31));
+__device__ inline void fma_entry<float>(float& acc, uint32_t base, uint32_t e, uint32_t vmask, uint32_t vsgn,
+                                        uint32_t vone) {
+  const float v = *(const __attribute__((address_space(3))) float*)(lds_cptr)(uintptr_t)((e & vmask) | base);
+  acc = __builtin_fmaf(__builtin_bit_cast(float, (e & vsgn) | vone), v, acc);
 }
 template <>
-__device__ inline float load_signed<uint16_t>(const unsigned char* p, uint32_t neg) {
-  uint32_t u = (uint32_t)(*(const uint16_t*)p) ^ (neg << 15);
-  return __builtin_bit_cast(float, u << 16);
+__device__ inline void fma_entry<uint16_t>(float& acc, uint32_t base, uint32_t e, uint32_t vmask, uint32_t vsgn,
+                                           uint32_t vone) {
+  const uint16_t h =
+      *(const __attribute__((address_space(3))) uint16_t*)(lds_cptr)(uintptr_t)((e & vmask) | base);
+  acc = __builtin_fmaf(__builtin_bit_cast(float, (e & vsgn) | vone), bf16_to_f32(h), acc);
 }
 
 template <typename Tin, int JB, int LB>
@@ -88,20 +237,23 @@ __global__ void __launch_bounds__(1024) ss_rows_kernel(RowsArgs a) {
   using Tacc = typename InType<Tin>::acc;
   constexpr int ES = sizeof(Tin);
   constexpr int ROWB = 64 * ES;  // LDS bytes per tile row (64 columns)
+  static_assert(JB <= 64, "one bucket per lane");
+  // The kernel declares no static LDS, so this dynamic segment starts at LDS
+  // address 0 and every tile row starts at a multiple of ROWB.
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nthreads = blockDim.x, nwaves = nthreads >> 6;
 
-  // Work item. Workgroup ids L, L+8, ... run on the same XCD (dispatch is
-  // round-robin over the 8 XCDs), so the n_groups workgroups that share one
-  // A tile are given ids 8 apart and find it in the same L2.
-  const int L = blockIdx.x, xcd = L & 7, q = L >> 3;
-  const int group = q % a.n_groups;
-  const int rest = (q / a.n_groups) * 8 + xcd;
-  const int slab = rest % a.n_slabs;
-  const int chunk = rest / a.n_slabs;
+  // Work item. Dispatch is round-robin over the 8 XCDs (id L runs on XCD
+  // L % 8), so all column slabs and block groups of one row chunk get ids
+  // 8 apart: they run together on one XCD and share its L2 for the plans and
+  // the cache lines that straddle slab boundaries.
+  const int L = blockIdx.x, xcd = L & 7, q8 = L >> 3;
+  const int group = q8 % a.n_groups;
+  const int slab = (q8 / a.n_groups) % a.n_slabs;
+  const int chunk = (q8 / (a.n_groups * a.n_slabs)) * 8 + xcd;
   if (chunk >= a.n_chunks) return;
 
   const int t0 = group * a.bpg;
@@ -114,11 +266,6 @@ __global__ void __launch_bounds__(1024) ss_rows_kernel(RowsArgs a) {
   const int nsub = r_end > r_begin ? (int)((r_end - r_begin + a.R - 1) / a.R) : 0;
   const int R = a.R, nb = a.nb;
 
-  uint16_t* codes = (uint16_t*)(smem + a.off_codes);  // [bpg][R]: bucket << 1 | negative
-  uint16_t* rnk = (uint16_t*)(smem + a.off_rnk);      // [bpg][R]: rank of the row in its bucket
-  uint32_t* offs = (uint32_t*)(smem + a.off_off);     // [bpg][nb + 1]: counts, then offsets
-  uint16_t* lists = (uint16_t*)(smem + a.off_lists);  // [bpg][R]: row << 1 | negative, by bucket
-
   const int tl = wave / a.H, hr = wave - (wave / a.H) * a.H;
   const bool walker = tl < bpg;
   const int s_begin = hr * a.per_range;
@@ -128,10 +275,16 @@ __global__ void __launch_bounds__(1024) ss_rows_kernel(RowsArgs a) {
 #pragma unroll
   for (int j = 0; j < JB; ++j) acc[j] = 0;
 
+  // zero rows (empty buckets read them), one after each tile buffer
+  for (int i = tid; i < 2 * (ROWB / 4); i += nthreads) {
+    const int b = i / (ROWB / 4);
+    ((uint32_t*)(smem + b * a.buf_stride + a.off_zero))[i - b * (ROWB / 4)] = 0u;
+  }
+
   auto issue_loads = [&](int st, int buf) {
     const int64_t r0 = r_begin + (int64_t)st * R;
     const int rv = (int)min((int64_t)R, r_end - r0);
-    unsigned char* dst = smem + buf * a.tile_bytes;
+    unsigned char* dst = smem + buf * a.buf_stride;
     const int n_instr = R * ROWB / (64 * LB);
     for (int k = wave; k < n_instr; k += nwaves) {
       const int byte = (k * 64 + lane) * LB;
@@ -139,146 +292,79 @@ __global__ void __launch_bounds__(1024) ss_rows_kernel(RowsArgs a) {
       const int cb = byte - row * ROWB;
       const unsigned char* src = a.A;  // in-bounds stand-in for padding lanes
       if (row < rv && cb < slab_bytes) src = a.A + (r0 + row) * a.lda_bytes + col0 * ES + cb;
+      const uint32_t la = (uint32_t)__builtin_amdgcn_readfirstlane((int)lds_addr_of(dst + k * 64 * LB));
       if constexpr (LB == 16)
-        __builtin_amdgcn_global_load_lds((const void*)src, as_lds(dst + k * 64 * LB), 16, 0, 0);
+        dma_to_lds16(src, la);
       else
-        __builtin_amdgcn_global_load_lds((const void*)src, as_lds(dst + k * 64 * LB), 4, 0, 0);
+        dma_to_lds4(src, la);
+    }
+    // the tile's plan records for this group's blocks (contiguous)
+    const unsigned char* psrc = a.plan + ((r0 / R) * a.zeta + t0) * (int64_t)a.rec_bytes;
+    unsigned char* pdst = dst + a.off_plan;
+    for (int k = wave; k * 1024 < a.plan_dma_bytes; k += nwaves) {
+      const uint32_t la = (uint32_t)__builtin_amdgcn_readfirstlane((int)lds_addr_of(pdst + k * 1024));
+      dma_to_lds16(psrc + k * 1024 + lane * 16, la);
     }
   };
 
   if (nsub > 0) issue_loads(0, 0);
   for (int st = 0; st < nsub; ++st) {
     const int buf = st & 1;
-    const int64_t r0 = r_begin + (int64_t)st * R;
-    const int rv = (int)min((int64_t)R, r_end - r0);
     wait_dma();
-    lds_barrier();  // tile st is in LDS; everyone finished walking tile st-1
+    lds_barrier();  // tile st and its plan are in LDS; everyone finished tile st-1
     if (st + 1 < nsub) issue_loads(st + 1, buf ^ 1);
 
-    // Hash: one Philox call gives the words of blocks 4g .. 4g+3 of one row.
-    {
-      const int g0 = t0 >> 2, g1 = (t0 + bpg - 1) >> 2;
-      for (int g = g0; g <= g1; ++g) {
-        for (int r = tid; r < rv; r += nthreads) {
-          const uint64_t i = (uint64_t)(r0 + r);
-          const U4 w =
-              philox4x32_10(U4{(uint32_t)i, (uint32_t)(i >> 32), (uint32_t)g, kTagSparseStack}, a.k0, a.k1);
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int t = 4 * g + j;
-            if (t >= t0 && t < t0 + bpg) {
-              const uint32_t word = word_of(w, j);
-              codes[(t - t0) * R + r] = (uint16_t)((ss_bucket(word, (uint32_t)nb) << 1) | ss_negative(word));
-            }
-          }
-        }
-      }
-    }
-    lds_barrier();
-
-    // Stable counting sort of the rows of block `wave` by bucket.
-    if (wave < bpg) {
-      uint32_t* cnt = offs + wave * (nb + 1);
-      const uint16_t* cd = codes + wave * R;
-      uint16_t* rk = rnk + wave * R;
-      for (int s = lane; s <= nb; s += 64) cnt[s] = 0;
-      const uint64_t below = (1ull << lane) - 1ull;
-      for (int c0 = 0; c0 < rv; c0 += 64) {
-        const int r = c0 + lane;
-        const bool valid = r < rv;
-        const uint32_t s = valid ? (uint32_t)(cd[r] >> 1) : 0u;
-        uint64_t mask = __ballot(valid);
-        for (int b = 0; b < a.nbits; ++b) {
-          const bool bit = (s >> b) & 1u;
-          const uint64_t mb = __ballot(bit);
-          mask &= bit ? mb : ~mb;
-        }
-        const uint32_t rank = (uint32_t)__popcll(mask & below);
-        const uint32_t base = valid ? cnt[s] : 0u;
-        if (valid) rk[r] = (uint16_t)(base + rank);
-        if (valid && rank == 0) cnt[s] = base + (uint32_t)__popcll(mask);
-      }
-      // exclusive scan of the counts
-      const int per = (nb + 63) / 64;
-      const int sb = lane * per;
-      uint32_t loc = 0;
-      for (int k = 0; k < per; ++k)
-        if (sb + k < nb) loc += cnt[sb + k];
-      uint32_t inc = loc;
-      for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(inc, o, 64);
-        if (lane >= o) inc += y;
-      }
-      uint32_t run = inc - loc;
-      for (int k = 0; k < per; ++k) {
-        if (sb + k < nb) {
-          const uint32_t c = cnt[sb + k];
-          cnt[sb + k] = run;
-          run += c;
-        }
-      }
-      if (lane == 63) cnt[nb] = inc;
-      // scatter list entries
-      uint16_t* lst = lists + wave * R;
-      for (int c0 = 0; c0 < rv; c0 += 64) {
-        const int r = c0 + lane;
-        if (r < rv) {
-          const uint32_t code = cd[r];
-          const uint32_t pos = cnt[code >> 1] + rk[r];
-          lst[pos] = (uint16_t)(((uint32_t)r << 1) | (code & 1u));
-        }
-      }
-    }
-    lds_barrier();
-
-    // Segmented reduction: wave (block tl, buckets [s_begin, s_begin + s_cnt)).
-    // The wave's list entries (<= 128) and bucket offsets (<= 128) are packed
-    // two u16 per lane into VGPRs and read back with v_readlane, so a row costs
-    // one LDS read (the value) and a few scalar-operand VALU ops.
+    // Segmented reduction. Wave (block tl, buckets [s_begin, s_begin + s_cnt)):
+    // lane j describes bucket s_begin + j.
     if (walker) {
-      // Opaque copy: keeps the per-bucket tests below inside the loop instead
-      // of letting them be hoisted as 64 live lane masks.
-      int s_cnt_l = s_cnt;
-      asm volatile("" : "+s"(s_cnt_l));
-      const uint16_t* lst = lists + tl * R;
-      const uint32_t* of = offs + tl * (nb + 1);
-      const unsigned char* tb = smem + buf * a.tile_bytes + lane * ES;
-      const int ebase = __builtin_amdgcn_readfirstlane((int)of[s_begin]);
-      const int eend = __builtin_amdgcn_readfirstlane((int)of[s_begin + s_cnt_l]);
-      const int nw = eend - ebase;
-      uint32_t vo, ve;
-      {
-        const int j0 = 2 * lane, j1 = 2 * lane + 1;
-        const uint32_t o0 = j0 <= s_cnt_l ? of[s_begin + j0] - ebase : 0u;
-        const uint32_t o1 = j1 <= s_cnt_l ? of[s_begin + j1] - ebase : 0u;
-        vo = o0 | (o1 << 16);
+      int sc = s_cnt;
+      asm volatile("" : "+s"(sc));
+      const unsigned char* pl = smem + buf * a.buf_stride + a.off_plan + tl * a.rec_bytes;
+      const uint16_t* of = (const uint16_t*)pl;
+      const uint16_t* lst = (const uint16_t*)(pl + a.lst_off);
+      const uint32_t bufaddr = lds_addr_of(smem + buf * a.buf_stride);
+      const uint32_t zaddr = lds_addr_of(smem + buf * a.buf_stride + a.off_zero);
+      const uint32_t base = (uint32_t)(lane * ES);
+      uint32_t vmask = 0x7fffffffu, vsgn = 0x80000000u;
+      uint32_t vone = sizeof(Tacc) == 8 ? 0x3FF00000u : 0x3F800000u;
+      asm volatile("" : "+v"(vmask), "+v"(vsgn), "+v"(vone));
+      auto entry = [&](uint32_t v) { return (bufaddr + (v >> 2) * ROWB) | (v << 31); };
+      uint32_t kbeg = 0, kcnt = 0;
+      if (lane < sc) {
+        kbeg = of[s_begin + lane];
+        kcnt = (uint32_t)of[s_begin + lane + 1] - kbeg;
       }
-      // entry window: entries [wb, wb + 128) of this wave, two per lane
-      int wb = 0;
-      auto load_window = [&](int from) {
-        const int j0 = from + 2 * lane, j1 = j0 + 1;
-        const uint32_t e0 = j0 < nw ? lst[ebase + j0] : 0u;
-        const uint32_t e1 = j1 < nw ? lst[ebase + j1] : 0u;
-        ve = e0 | (e1 << 16);
-      };
-      load_window(0);
-      int kb = 0;
+      const uint32_t e0 = kcnt >= 1 ? entry(lst[kbeg]) : zaddr;
+      // first rows of all buckets: unrolled and branch-free (lanes past the
+      // wave's range, like empty buckets, point at the zero row)
+      // (groups of four: the loads of a group overlap; the scheduling
+      // barrier keeps the compiler from hoisting every load and spilling)
 #pragma unroll
       for (int j = 0; j < JB; ++j) {
-        if (j < s_cnt_l) {
-          const uint32_t wo = (uint32_t)__builtin_amdgcn_readlane((int)vo, (j + 1) >> 1);
-          const int ke = (int)(((j + 1) & 1) ? (wo >> 16) : (wo & 0xffffu));
-          for (int k = kb; k < ke; ++k) {
-            if (k - wb >= 128) {  // rare: more than 128 rows for this wave
-              wb = k;
-              load_window(wb);
-            }
-            const int kk = k - wb;
-            const uint32_t we = (uint32_t)__builtin_amdgcn_readlane((int)ve, kk >> 1);
-            const uint32_t e = (kk & 1) ? (we >> 16) : (we & 0xffffu);
-            acc[j] += load_signed<Tin>(tb + (e >> 1) * ROWB, e & 1u);
+        fma_entry<Tin>(acc[j], base, (uint32_t)__builtin_amdgcn_readlane((int)e0, j), vmask, vsgn, vone);
+        asm volatile("" : "+v"(acc[j]));  // the add happens here, not sunk into the code below
+        if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+
+      // further rows: the remaining list entries of each bucket with two or
+      // more rows, two rows at a time (one uniform test per bucket)
+      const uint64_t m2 = __ballot(kcnt >= 2);
+#pragma unroll
+      for (int j = 0; j < JB; ++j) {
+        if ((m2 >> j) & 1ull) {
+          const int kb = __builtin_amdgcn_readlane((int)kbeg, j) + 1;
+          const int ke = kb - 1 + __builtin_amdgcn_readlane((int)kcnt, j);
+          int k = kb;
+          for (; k + 1 < ke; k += 2) {
+            const uint32_t va = (uint32_t)__builtin_amdgcn_readfirstlane((int)lst[k]);
+            const uint32_t vb = (uint32_t)__builtin_amdgcn_readfirstlane((int)lst[k + 1]);
+            fma_entry<Tin>(acc[j], base, entry(va), vmask, vsgn, vone);
+            fma_entry<Tin>(acc[j], base, entry(vb), vmask, vsgn, vone);
           }
-          kb = ke;
+          if (k < ke)
+            fma_entry<Tin>(acc[j], base, entry((uint32_t)__builtin_amdgcn_readfirstlane((int)lst[k])), vmask, vsgn,
+                           vone);
         }
       }
     }
@@ -356,13 +442,45 @@ __global__ void ss_adjoint_kernel(int64_t n, int64_t m, int zeta, uint32_t nb, u
 // Host side
 // ---------------------------------------------------------------------------
 static size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+static size_t align1k(size_t x) { return (x + 1023) & ~(size_t)1023; }
 
 static int env_int(const char* name, int dflt) {
   const char* v = std::getenv(name);
   return v ? std::atoi(v) : dflt;
 }
 
-static int jb_for(int dtype_in) { return dtype_in == SK_F64 ? 50 : 64; }
+// Plan record of one (tile, block): u16 offsets [nb + 1], then u16 list [R].
+static void plan_record(int R, int64_t nb, int* rec_bytes, int* lst_off) {
+  *lst_off = (int)align16((size_t)(nb + 1) * 2);
+  *rec_bytes = (int)align16((size_t)*lst_off + (size_t)R * 2);
+}
+
+// LDS layout of the sketch kernel. Per buffer (x2): R tile rows, one zero
+// row, the plan records of the group's blocks (padded to whole 1 KB load
+// instructions).
+struct RowsLds {
+  size_t tile, zero, plan, plan_dma, buf_stride, xtra, total;
+};
+static RowsLds rows_lds(int es, int R, int bpg, int rec_bytes, int W) {
+  RowsLds l;
+  l.tile = (size_t)R * 64 * es;
+  l.zero = l.tile;
+  l.plan = align16(l.zero + (size_t)64 * es);
+  l.plan_dma = align1k((size_t)bpg * rec_bytes);
+  l.buf_stride = align16(l.plan + l.plan_dma);
+  l.xtra = 2 * l.buf_stride;
+  l.total = l.xtra;
+  (void)W;
+  return l;
+}
+
+// Accumulator slots compiled into the kernel variants (per lane, per wave).
+static int jb_max(int dtype_in) { return dtype_in == SK_F64 ? 50 : 64; }
+static int jb_variant(int dtype_in, int per_range) {
+  if (per_range <= 16) return 16;
+  if (per_range <= 32) return 32;
+  return jb_max(dtype_in);
+}
 
 int plan_rows(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t lda, RowsPlan* p) {
   const int es = (int)dtype_size(dtype_in);
@@ -372,8 +490,8 @@ int plan_rows(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_
     set_error("SparseStack row apply supports at most 16384 buckets per block");
     return SK_E_NOTSUP;
   }
-  p->jb = jb_for(dtype_in);
-  const int Hmin = (int)((nb + p->jb - 1) / p->jb);
+  const int jmax = jb_max(dtype_in);
+  const int Hmin = (int)((nb + jmax - 1) / jmax);
   if (Hmin > 16) {
     set_error("SparseStack row apply: d/zeta too large for the register-resident accumulators");
     return SK_E_NOTSUP;
@@ -389,6 +507,7 @@ int plan_rows(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_
   }
   p->W = p->bpg * p->H;
   p->per_range = (int)((nb + p->H - 1) / p->H);
+  p->jb = jb_variant(dtype_in, p->per_range);
 
   // direct global->LDS load width
   const uintptr_t ap = (uintptr_t)A;
@@ -409,32 +528,17 @@ int plan_rows(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_
   p->C = C;
   p->n_slabs = (int)((m + C - 1) / C);
 
-  // sub-tile rows: 64 KB per buffer, shrunk until the LDS plan fits
+  // tile rows: 64 KB per buffer, shrunk until the LDS plan fits
   int R = env_int("SKETCH_TILE_ROWS", 65536 / (64 * es));
-  const int tile_cap = 160 * 1024;
+  const size_t lds_cap = 160 * 1024;
   for (;;) {
-    const size_t tile = (size_t)R * 64 * es;
-    size_t off = 2 * tile;
-    const size_t codes = off;
-    off = align16(off + (size_t)p->bpg * R * 2);
-    const size_t rk = off;
-    off = align16(off + (size_t)p->bpg * R * 2);
-    const size_t of = off;
-    off = align16(off + (size_t)p->bpg * (nb + 1) * 4);
-    const size_t li = off;
-    off = align16(off + (size_t)p->bpg * R * 2);
-    if (off <= (size_t)tile_cap || R <= 16) {
-      p->R = R;
-      p->lds_bytes = off;
-      (void)codes;
-      (void)rk;
-      (void)of;
-      (void)li;
-      break;
-    }
+    plan_record(R, nb, &p->rec_bytes, &p->lst_off);
+    if (rows_lds(es, R, p->bpg, p->rec_bytes, p->W).total <= lds_cap || R <= 16) break;
     R /= 2;
   }
-  if (p->lds_bytes > (size_t)tile_cap) {
+  p->R = R;
+  p->lds_bytes = rows_lds(es, R, p->bpg, p->rec_bytes, p->W).total;
+  if (p->lds_bytes > lds_cap) {
     set_error("sketch_apply: LDS plan does not fit");
     return SK_E_NOTSUP;
   }
@@ -447,14 +551,40 @@ int plan_rows(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_
   rpc = ((rpc + p->R - 1) / p->R) * p->R;
   p->rows_per_chunk = rpc;
   p->n_chunks = (int)((n + rpc - 1) / rpc);
+  p->n_tiles = (n + p->R - 1) / p->R;
   const size_t accb = dtype_in == SK_F64 ? 8 : 4;
   p->partial_bytes = align16((size_t)p->n_chunks * S->d * m * accb);
+  // the last tile's DMA may read up to one padded record span past its end
+  p->plan_bytes = align16((size_t)p->n_tiles * zeta * p->rec_bytes) + align1k((size_t)p->bpg * p->rec_bytes);
+  return SK_OK;
+}
+
+static int launch_plan(const sk_sketch* S, const RowsPlan& p, void* plan, hipStream_t st) {
+  PlanArgs a;
+  a.n = S->n;
+  a.R = p.R;
+  a.zeta = S->zeta;
+  a.nb = (int)S->nb;
+  int nbits = 0;
+  while ((1ll << nbits) < S->nb) ++nbits;
+  a.nbits = nbits;
+  a.k0 = S->k0;
+  a.k1 = S->k1;
+  a.out = (unsigned char*)plan;
+  a.rec_bytes = p.rec_bytes;
+  a.lst_off = p.lst_off;
+  const int threads = 64 * std::min(16, S->zeta);
+  const size_t codes = (size_t)S->zeta * p.R * 2;
+  const size_t lds = align16(2 * codes + 4) + (size_t)S->zeta * (S->nb + 1) * 4;
+  SK_HIP(hipFuncSetAttribute((const void*)ss_plan_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(ss_plan_kernel, dim3((unsigned)p.n_tiles), dim3(threads), lds, st, a);
+  SK_HIP(hipGetLastError());
   return SK_OK;
 }
 
 template <typename Tin, int JB, int LB>
 static int launch_rows_t(const sk_sketch* S, const RowsPlan& p, int64_t m, const void* A, int64_t lda, void* P,
-                         hipStream_t st) {
+                         const void* plan, hipStream_t st) {
   RowsArgs a;
   const int es = sizeof(Tin);
   a.A = (const unsigned char*)A;
@@ -473,24 +603,17 @@ static int launch_rows_t(const sk_sketch* S, const RowsPlan& p, int64_t m, const
   a.rows_per_chunk = p.rows_per_chunk;
   a.zeta = S->zeta;
   a.nb = (int)S->nb;
-  int nbits = 0;
-  while ((1ll << nbits) < S->nb) ++nbits;
-  a.nbits = nbits;
-  a.k0 = S->k0;
-  a.k1 = S->k1;
+  a.plan = (const unsigned char*)plan;
+  a.rec_bytes = p.rec_bytes;
+  a.lst_off = p.lst_off;
   a.P = P;
-  const size_t tile = (size_t)p.R * 64 * es;
-  size_t off = 2 * tile;
-  a.tile_bytes = (int)tile;
-  a.off_codes = (int)off;
-  off = align16(off + (size_t)p.bpg * p.R * 2);
-  a.off_rnk = (int)off;
-  off = align16(off + (size_t)p.bpg * p.R * 2);
-  a.off_off = (int)off;
-  off = align16(off + (size_t)p.bpg * (S->nb + 1) * 4);
-  a.off_lists = (int)off;
-  const int64_t pairs = (int64_t)p.n_chunks * p.n_slabs;
-  const int64_t grid = ((pairs + 7) / 8) * 8 * p.n_groups;
+  const RowsLds l = rows_lds(es, p.R, p.bpg, p.rec_bytes, p.W);
+  a.buf_stride = (int)l.buf_stride;
+  a.off_zero = (int)l.zero;
+  a.off_plan = (int)l.plan;
+  a.plan_dma_bytes = (int)l.plan_dma;
+  a.off_xtra = (int)l.xtra;
+  const int64_t grid = ((int64_t)(p.n_chunks + 7) / 8) * 8 * p.n_slabs * p.n_groups;
   auto kern = ss_rows_kernel<Tin, JB, LB>;
   SK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes));
   {
@@ -514,26 +637,40 @@ static int launch_reduce(const RowsPlan& p, const sk_sketch* S, int64_t m, const
   return SK_OK;
 }
 
+template <typename Tin>
+static int launch_rows_jb(const sk_sketch* S, const RowsPlan& p, int64_t m, const void* A, int64_t lda, void* P,
+                          const void* plan, hipStream_t st) {
+  constexpr int JMAX = sizeof(Tin) == 8 ? 50 : 64;
+  if (p.load_bytes == 16) {
+    if (p.jb == 16) return launch_rows_t<Tin, 16, 16>(S, p, m, A, lda, P, plan, st);
+    if (p.jb == 32) return launch_rows_t<Tin, 32, 16>(S, p, m, A, lda, P, plan, st);
+    return launch_rows_t<Tin, JMAX, 16>(S, p, m, A, lda, P, plan, st);
+  }
+  if (p.jb == 16) return launch_rows_t<Tin, 16, 4>(S, p, m, A, lda, P, plan, st);
+  if (p.jb == 32) return launch_rows_t<Tin, 32, 4>(S, p, m, A, lda, P, plan, st);
+  return launch_rows_t<Tin, JMAX, 4>(S, p, m, A, lda, P, plan, st);
+}
+
+// Workspace: partials, then the plan records.
 int launch_rows_apply(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64_t m, const void* A, int64_t lda,
                       int dtype_out, void* SA, int64_t ldsa, void* ws, hipStream_t st) {
-  int rc;
-  if (dtype_in == SK_F64) {
-    rc = p.load_bytes == 16 ? launch_rows_t<double, 50, 16>(S, p, m, A, lda, ws, st)
-                            : launch_rows_t<double, 50, 4>(S, p, m, A, lda, ws, st);
-  } else if (dtype_in == SK_F32) {
-    rc = p.load_bytes == 16 ? launch_rows_t<float, 64, 16>(S, p, m, A, lda, ws, st)
-                            : launch_rows_t<float, 64, 4>(S, p, m, A, lda, ws, st);
-  } else {
-    rc = p.load_bytes == 16 ? launch_rows_t<uint16_t, 64, 16>(S, p, m, A, lda, ws, st)
-                            : launch_rows_t<uint16_t, 64, 4>(S, p, m, A, lda, ws, st);
-  }
+  void* P = ws;
+  void* plan = (unsigned char*)ws + p.partial_bytes;
+  int rc = launch_plan(S, p, plan, st);
+  if (rc != SK_OK) return rc;
+  if (dtype_in == SK_F64)
+    rc = launch_rows_jb<double>(S, p, m, A, lda, P, plan, st);
+  else if (dtype_in == SK_F32)
+    rc = launch_rows_jb<float>(S, p, m, A, lda, P, plan, st);
+  else
+    rc = launch_rows_jb<uint16_t>(S, p, m, A, lda, P, plan, st);
   if (rc != SK_OK) return rc;
   if (dtype_in == SK_F64) {
-    if (dtype_out == SK_F64) return launch_reduce<double, double>(p, S, m, ws, SA, ldsa, st);
-    return launch_reduce<double, float>(p, S, m, ws, SA, ldsa, st);
+    if (dtype_out == SK_F64) return launch_reduce<double, double>(p, S, m, P, SA, ldsa, st);
+    return launch_reduce<double, float>(p, S, m, P, SA, ldsa, st);
   }
-  if (dtype_out == SK_F64) return launch_reduce<float, double>(p, S, m, ws, SA, ldsa, st);
-  return launch_reduce<float, float>(p, S, m, ws, SA, ldsa, st);
+  if (dtype_out == SK_F64) return launch_reduce<float, double>(p, S, m, P, SA, ldsa, st);
+  return launch_reduce<float, float>(p, S, m, P, SA, ldsa, st);
 }
 
 int launch_pattern(const sk_sketch* S, int32_t* bucket, int8_t* sign, hipStream_t st) {

@@ -74,6 +74,7 @@ CASES = [
     (4096, 20, 64, 1, 6),      # CountSketch
     (300, 1, 30, 3, 7),        # single column (the right-hand side)
     (9000, 200, 800, 8, 8),    # workload 2 column count, several row tiles
+    (200000, 50, 200, 4, 9),   # many sub-tiles per row chunk (both LDS buffers in use)
 ]
 
 
@@ -89,7 +90,8 @@ def test_apply_f64_parity(lib, n, m, d, zeta, seed):
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
 @pytest.mark.parametrize("n,m,d,zeta,seed", [(20000, 64, 200, 4, 1), (6007, 100, 2000, 8, 2),
-                                             (3000, 16, 64, 8, 3), (1000, 500, 400, 8, 4)])
+                                             (3000, 16, 64, 8, 3), (1000, 500, 400, 8, 4),
+                                             (100000, 64, 400, 8, 5)])
 def test_apply_lowprec_parity(lib, dtype, n, m, d, zeta, seed):
     rng = np.random.default_rng(seed)
     A = torch.from_numpy(rng.standard_normal((n, m))).cuda().to(torch.float32).to(dtype)
