@@ -7,8 +7,8 @@
  *
  * Orientation. A sketch is the short-fat matrix S (d x n); the paper's test
  * matrix is Omega = S^T (n x d). sketch_apply computes S A (the paper's
- * Psi^T A, Alg. 3 line 2); sketch_apply_T computes A S^T (the paper's
- * A Omega, Alg. 1 line 2).
+ * Psi^T A, the sketching step of Alg. 3); sketch_apply_T computes A S^T
+ * (the paper's A Omega, the sketching step of Alg. 1).
  *
  * Conventions for every entry point:
  *   - Matrix pointers are DEVICE pointers owned by the caller, unless a
@@ -132,6 +132,71 @@ int sketch_pattern(sketch_t S, int32_t* bucket, int8_t* sign, void* stream);
  *   number of timed launches (either pointer may be NULL).
  */
 int sketch_timing(sketch_t S, int mode, double* total_ms, int64_t* count);
+
+/* ------------------------------------------------------------------------
+ * Least-squares drivers: min_x ||A x - b||_2 for a tall A (n x m, n = the
+ * sketch's n, row-major F64, lda >= m) with full column rank. S must have
+ * d >= m rows. Each call synchronizes `stream` before returning; device
+ * memory comes from a buffer owned by the handle (calls through one handle
+ * must be serialized). x is a device vector of m doubles.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+  int rank;              /* numerical rank r of S A (the rank test of Alg. 3) */
+  double sigma_max;      /* largest singular value of S A */
+  double sigma_min_kept; /* r-th singular value of S A */
+  double t_sketch_ms;    /* device time of the sketch of A and b */
+  double t_total_ms;     /* device time of the whole solve */
+} sk_solve_info;
+
+/*
+ * Sketch-and-solve (Alg. 3): x = argmin ||S (A x - b)|| with the rank
+ * truncation of Alg. 3: the SVD S A = U diag(s) V^T is obtained from a
+ * Householder QR S [A b] = Q [R c; 0 *] and a one-sided Jacobi SVD of R;
+ * r = #{i : s_i > 5 eps s_1} with eps = 2^-52;
+ * x = V_r diag(s_r)^-1 U_r^T c. Needs m <= 1024.
+ * Returns SK_W_RANKDEF when r < m (x is then the truncated solution).
+ * info may be NULL.
+ */
+int lstsq_sketch_solve(sketch_t S, int64_t m, const double* A, int64_t lda, const double* b, double* x,
+                       sk_solve_info* info, void* stream);
+
+typedef struct {
+  int iters;            /* LSQR iterations taken */
+  int converged;        /* 1 if the stopping test held */
+  double rnorm_est;     /* LSQR's recurrence estimate of ||b - A x|| */
+  double arnorm_est;    /* estimate of ||(A R^-1)^T (b - A x)|| */
+  double anorm_est;     /* estimate of ||A R^-1||_F */
+  double t_sketch_ms;   /* device time of the sketch of A and b */
+  double t_qr_ms;       /* QR of the sketch, R^-1 and the warm start */
+  double t_lsqr_ms;     /* the LSQR iterations and the final back-substitution */
+  double t_total_ms;    /* device time of the whole solve */
+} sk_lsqr_info;
+
+/*
+ * Sketch-and-precondition, the high-accuracy least-squares solver named in
+ * Sec. 1.3 (remark after Thm. 1.4): QR of the sketch S A = Q R (Householder,
+ * F64), the warm start x0 = R^-1 Q^T S b, then LSQR (Paige & Saunders 1982)
+ * on min ||A R^-1 y - (b - A x0)|| in F64, and x = x0 + R^-1 y.
+ * Stopping test (checked every iteration): ||r|| <= tol ||r0|| or
+ * ||(A R^-1)^T r|| <= tol ||A R^-1||_F,est ||r||. maxit bounds the
+ * iterations (SK_W_NOCONV when reached first).
+ * Mixed precision: A_sketch (may be NULL) is a copy of A of dtype
+ * sketch_dtype (SK_F64/SK_F32/SK_BF16, row-major, lda_sketch >= m) that is
+ * sketched instead of A; the sketch accumulates in F32 for F32/BF16 input
+ * and everything after it is F64. warm_start = 0 starts from x0 = 0.
+ * Needs m <= 512. info may be NULL.
+ */
+int lstsq_sketch_precond(sketch_t S, int64_t m, const double* A, int64_t lda, int sketch_dtype,
+                         const void* A_sketch, int64_t lda_sketch, const double* b, double* x, double tol,
+                         int maxit, int warm_start, sk_lsqr_info* info, void* stream);
+
+/*
+ * *resnorm (host) = ||b - A x||_2 in F64, with A (n x m) as above and the
+ * handle supplying n and the workspace. Needs m <= 512. Synchronizes.
+ */
+int lstsq_residual(sketch_t S, int64_t m, const double* A, int64_t lda, const double* b, const double* x,
+                   double* resnorm, void* stream);
 
 #ifdef __cplusplus
 }

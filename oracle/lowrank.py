@@ -8,7 +8,7 @@ import numpy as np
 
 
 def rsvd_from_sketch(A, Y):
-    """Alg. 1 after line 2: Q = orth(Y); B = Q^T A; [Uh, s, V] = svd_econ(B); U = Q Uh."""
+    """Alg. 1 after the sketch Y = A Omega: Q = orth(Y); B = Q^T A; [Uh, s, V] = svd_econ(B); U = Q Uh."""
     A = np.asarray(A, dtype=np.float64)
     Q, _ = np.linalg.qr(np.asarray(Y, dtype=np.float64), mode="reduced")
     B = Q.T @ A

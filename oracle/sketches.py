@@ -107,7 +107,7 @@ def sparsestack_apply_rows(A_rows, row_ids, d, zeta, seed):
 
 
 def sparsestack_apply_T(A, d, zeta, seed):
-    """Y = A @ S^T for a wide A (rows x n): the paper's A Omega (Alg. 1, line 2)."""
+    """Y = A @ S^T for a wide A (rows x n): the paper's A Omega (the sketching step of Alg. 1)."""
     A = np.asarray(A, dtype=np.float64)
     Spm = sparsestack_csr(A.shape[1], d, zeta, seed, scaled=False)
     return (Spm @ A.T).T * inv_sqrt(zeta)

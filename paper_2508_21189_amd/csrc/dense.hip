@@ -1,0 +1,256 @@
+// Dense FP64 kernels for the least-squares drivers (gfx950):
+//   * blocked Householder QR of a d x k column-major matrix W (the sketched
+//     system [SA | Sb] transposed to columns); one workgroup factors a panel
+//     and builds the compact-WY factor T; one workgroup per trailing column
+//     applies Q_panel^T = I - V T^T V^T;
+//   * explicit inverse of the upper-triangular R (the preconditioner);
+//   * row-block reductions for LSQR (see lsqr.hip) live in their own file.
+#include "sk_dense.hpp"
+
+#include <algorithm>
+
+namespace sk {
+
+constexpr int kPanel = 32;  // panel width of the blocked QR
+
+// Block-wide sum of one double per thread (blockDim.x a multiple of 64, <= 1024).
+__device__ inline double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0;
+  for (int w = 0; w < nw; ++w) s += red[w];  // fixed order: deterministic
+  return s;
+}
+
+// W (column-major, column c at W + c*ldw) := [M^T-columns | rhs]: column c < k0
+// is column c of the row-major d x k0 matrix M, column k0 is the vector r.
+__global__ void to_columns_kernel(const double* __restrict__ M, int64_t ldm, const double* __restrict__ r, int64_t d,
+                                  int k0, double* __restrict__ W, int64_t ldw) {
+  const int64_t total = d * (k0 + (r ? 1 : 0));
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = idx / d, i = idx - c * d;
+    W[c * ldw + i] = c < k0 ? M[i * ldm + c] : r[i];
+  }
+}
+
+// Householder factorization of panel columns [k, k + nbp) of W (d rows), in
+// place: R on and above the diagonal, the reflector vectors v (unit leading
+// entry implicit) below it. tau[k + j] and T (nbp x nbp, upper, row-major)
+// with Q_panel = H_k ... H_{k+nbp-1} = I - V T V^T. LAPACK's sign convention:
+// beta = -sign(alpha) * ||x||, tau = (beta - alpha) / beta, v = x / (alpha - beta).
+__global__ void __launch_bounds__(1024) hh_panel_kernel(double* __restrict__ W, int64_t ldw, int64_t d, int k,
+                                                        int nbp, double* __restrict__ tau, double* __restrict__ T) {
+  __shared__ double red[16];
+  __shared__ double sh_scal[4];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int jj = 0; jj < nbp; ++jj) {
+    const int c = k + jj;
+    double* x = W + (int64_t)c * ldw;
+    // sigma^2 = ||x[c+1:]||^2
+    double part = 0;
+    for (int64_t i = c + 1 + tid; i < d; i += nt) part += x[i] * x[i];
+    const double sig2 = block_sum(part, red);
+    if (tid == 0) {
+      const double alpha = x[c];
+      double t = 0, beta = alpha, scale = 0;
+      if (sig2 > 0) {
+        beta = -copysign(sqrt(alpha * alpha + sig2), alpha);
+        t = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      sh_scal[0] = t;
+      sh_scal[1] = beta;
+      sh_scal[2] = scale;
+      tau[c] = t;
+    }
+    __syncthreads();
+    const double t = sh_scal[0], beta = sh_scal[1], scale = sh_scal[2];
+    if (t != 0)
+      for (int64_t i = c + 1 + tid; i < d; i += nt) x[i] *= scale;
+    __syncthreads();
+    if (tid == 0) x[c] = beta;
+    // apply H_c = I - t v v^T to the remaining panel columns
+    for (int j2 = jj + 1; j2 < nbp && t != 0; ++j2) {
+      double* y = W + (int64_t)(k + j2) * ldw;
+      double p = 0;
+      for (int64_t i = c + 1 + tid; i < d; i += nt) p += x[i] * y[i];
+      const double wv = block_sum(p, red) + y[c];  // v_c = 1
+      const double f = t * wv;
+      for (int64_t i = c + 1 + tid; i < d; i += nt) y[i] -= f * x[i];
+      if (tid == 0) y[c] -= f;
+      __syncthreads();
+    }
+    __syncthreads();
+  }
+  // T: column i gets T[0:i, i] = -tau_i * T[0:i, 0:i] * (V[:, 0:i]^T v_i), T[i][i] = tau_i
+  for (int i = 0; i < nbp; ++i) {
+    const int ci = k + i;
+    const double ti = tau[ci];
+    const double* vi = W + (int64_t)ci * ldw;
+    for (int j = 0; j < i; ++j) {
+      const int cj = k + j;
+      const double* vj = W + (int64_t)cj * ldw;
+      // v_j^T v_i over rows >= ci (v_i is zero above ci, v_i[ci] = 1)
+      double p = 0;
+      for (int64_t r = ci + 1 + tid; r < d; r += nt) p += vj[r] * vi[r];
+      const double dot = block_sum(p, red) + vj[ci];  // row ci: v_i = 1, v_j = W[cj][ci]
+      if (tid == 0) T[j * kPanel + i] = -ti * dot;    // temporarily the vector t_j
+      __syncthreads();
+    }
+    if (tid == 0) {
+      // T[0:i, i] = T[0:i, 0:i] (upper) * t, in increasing row order: row j
+      // reads t_l (l >= j), which later rows have not yet overwritten
+      for (int j = 0; j < i; ++j) {
+        double s = 0;
+        for (int l = j; l < i; ++l) s += T[j * kPanel + l] * T[l * kPanel + i];
+        T[j * kPanel + i] = s;
+      }
+      T[i * kPanel + i] = ti;
+    }
+    __syncthreads();
+  }
+}
+
+// Trailing update of one column y (index k + nbp + blockIdx.x) of W:
+// y <- y - V T^T V^T y, with V the panel's reflectors (rows >= k).
+__global__ void __launch_bounds__(256) hh_trail_kernel(double* __restrict__ W, int64_t ldw, int64_t d, int k, int nbp,
+                                                       int first_col, const double* __restrict__ T) {
+  __shared__ double red[4][kPanel];
+  __shared__ double z[kPanel], z2[kPanel];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* y = W + (int64_t)(first_col + blockIdx.x) * ldw;
+  const double* V = W + (int64_t)k * ldw;
+  // z = V^T y
+  double acc[kPanel];
+#pragma unroll
+  for (int p = 0; p < kPanel; ++p) acc[p] = 0;
+  for (int64_t i = k + tid; i < d; i += blockDim.x) {
+    const double yi = y[i];
+    const int64_t rel = i - k;
+#pragma unroll
+    for (int p = 0; p < kPanel; ++p) {
+      if (p < nbp) {
+        const double vip = rel > p ? V[(int64_t)p * ldw + i] : (rel == p ? 1.0 : 0.0);
+        acc[p] += vip * yi;
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < kPanel; ++p) {
+    double v = acc[p];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) red[wave][p] = v;
+  }
+  __syncthreads();
+  if (tid < nbp) z[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+  __syncthreads();
+  // z2 = T^T z  (T upper: (T^T z)_p = sum_{q <= p} T[q][p] z_q)
+  if (tid < nbp) {
+    double s = 0;
+    for (int q = 0; q <= tid; ++q) s += T[q * kPanel + tid] * z[q];
+    z2[tid] = s;
+  }
+  __syncthreads();
+  // y -= V z2
+  for (int64_t i = k + tid; i < d; i += blockDim.x) {
+    const int64_t rel = i - k;
+    double s = 0;
+    for (int p = 0; p < nbp; ++p) {
+      const double vip = rel > p ? V[(int64_t)p * ldw + i] : (rel == p ? 1.0 : 0.0);
+      s += vip * z2[p];
+    }
+    y[i] -= s;
+  }
+}
+
+// R (k x k row-major, upper) and c = (Q^T rhs)[0:k] from the factored W.
+__global__ void extract_r_kernel(const double* __restrict__ W, int64_t ldw, int k, int has_rhs,
+                                 double* __restrict__ R, double* __restrict__ c) {
+  const int64_t total = (int64_t)k * k;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = idx / k, col = idx - r * k;
+    R[idx] = col >= r ? W[col * ldw + r] : 0.0;
+  }
+  if (has_rhs)
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < k; r += (int64_t)gridDim.x * blockDim.x)
+      c[r] = W[(int64_t)k * ldw + r];
+}
+
+// Rinv = R^{-1} for upper-triangular R (k x k row-major). One wave per column j:
+// X[j][j] = 1/R[j][j]; X[i][j] = -(sum_{l=i+1..j} R[i][l] X[l][j]) / R[i][i].
+__global__ void __launch_bounds__(64) trinv_upper_kernel(const double* __restrict__ R, int k, double* __restrict__ X) {
+  const int j = blockIdx.x, lane = threadIdx.x;
+  for (int i = lane; i < k; i += 64) X[(int64_t)i * k + j] = 0.0;
+  __syncthreads();
+  if (lane == 0) X[(int64_t)j * k + j] = 1.0 / R[(int64_t)j * k + j];
+  __syncthreads();
+  for (int i = j - 1; i >= 0; --i) {
+    double s = 0;
+    for (int l = i + 1 + lane; l <= j; l += 64) s += R[(int64_t)i * k + l] * X[(int64_t)l * k + j];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) X[(int64_t)i * k + j] = -s / R[(int64_t)i * k + i];
+    __syncthreads();
+  }
+}
+
+__global__ void fill_kernel(double* __restrict__ x, int64_t n, double value) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = value;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+int qr_columns(double* W, int64_t ldw, int64_t d, int k, int extra_cols, double* tau, double* Tbuf, hipStream_t st) {
+  for (int c = 0; c < k; c += kPanel) {
+    const int nbp = std::min(kPanel, k - c);
+    double* T = Tbuf + (size_t)(c / kPanel) * kPanel * kPanel;
+    hipLaunchKernelGGL(hh_panel_kernel, dim3(1), dim3(1024), 0, st, W, ldw, d, c, nbp, tau, T);
+    SK_HIP(hipGetLastError());
+    const int first = c + nbp;
+    const int ntrail = k + extra_cols - first;
+    if (ntrail > 0) {
+      hipLaunchKernelGGL(hh_trail_kernel, dim3(ntrail), dim3(256), 0, st, W, ldw, d, c, nbp, first, T);
+      SK_HIP(hipGetLastError());
+    }
+  }
+  return SK_OK;
+}
+
+int launch_to_columns(const double* M, int64_t ldm, const double* r, int64_t d, int k0, double* W, int64_t ldw,
+                      hipStream_t st) {
+  const int64_t total = d * (k0 + (r ? 1 : 0));
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
+  hipLaunchKernelGGL(to_columns_kernel, dim3(blocks), dim3(256), 0, st, M, ldm, r, d, k0, W, ldw);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+int launch_extract_r(const double* W, int64_t ldw, int k, int has_rhs, double* R, double* c, hipStream_t st) {
+  const int64_t total = (int64_t)k * k;
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
+  hipLaunchKernelGGL(extract_r_kernel, dim3(blocks), dim3(256), 0, st, W, ldw, k, has_rhs, R, c);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+int launch_fill(double* x, int64_t n, double value, hipStream_t st) {
+  if (n <= 0) return SK_OK;
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(256), 0, st, x, n, value);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+int launch_trinv(const double* R, int k, double* X, hipStream_t st) {
+  hipLaunchKernelGGL(trinv_upper_kernel, dim3(k), dim3(64), 0, st, R, k, X);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+}  // namespace sk

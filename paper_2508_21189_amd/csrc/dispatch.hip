@@ -69,6 +69,18 @@ int apply_workspace(const sk_sketch* S, int op, int dtype_in, int64_t m, size_t*
   return SK_OK;
 }
 
+int apply_workspace_for(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t lda, size_t* bytes) {
+  *bytes = 0;
+  if (S->kind == SK_SPARSESTACK) {
+    RowsPlan p;
+    int rc = plan_rows(S, dtype_in, m, A, lda, &p);
+    if (rc != SK_OK) return rc;
+    *bytes = p.partial_bytes + p.plan_bytes;
+    return SK_OK;
+  }
+  return apply_workspace(S, 0, dtype_in, m, bytes);
+}
+
 int apply_dispatch(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t lda, int dtype_out, void* SA,
                    int64_t ldsa, void* ws, size_t ws_bytes, hipStream_t st) {
   switch (S->kind) {
@@ -105,6 +117,5 @@ int apply_T_dispatch(sk_sketch* S, int dtype_in, int64_t rows, const void* A, in
   return SK_E_NOTSUP;
 }
 
-void drivers_release(sk_sketch* S) { (void)S; }
 
 }  // namespace sk

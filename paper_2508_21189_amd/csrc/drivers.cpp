@@ -1,0 +1,324 @@
+// Least-squares drivers on top of the sketch apply:
+//   * lstsq_sketch_solve      sketch-and-solve (Alg. 3): QR of [S A | S b],
+//                             SVD of the triangular factor, truncated solve;
+//   * lstsq_sketch_precond    sketch-and-precondition: QR of the sketch,
+//                             warm start R^-1 Q^T S b, LSQR on A R^-1 in FP64;
+//   * lstsq_residual          ||b - A x|| in FP64 (one fused pass).
+// All device memory comes from one handle-owned buffer carved per call.
+#include <algorithm>
+#include <cmath>
+
+#include "sk_dense.hpp"
+#include "sk_drivers.hpp"
+#include "sk_lsqr.hpp"
+
+namespace sk {
+
+namespace {
+
+// Bump allocator over a device buffer (sizes only when base is null).
+struct Carver {
+  char* base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    const size_t o = (off + 255) & ~size_t(255);
+    off = o + std::max<size_t>(1, count) * sizeof(T);
+    return base ? reinterpret_cast<T*>(base + o) : nullptr;
+  }
+};
+
+int driver_workspace(sk_sketch* S, size_t bytes, char** out) {
+  if (S->dws_bytes < bytes) {
+    if (S->dws) {
+      SK_HIP(hipDeviceSynchronize());
+      SK_HIP(hipFree(S->dws));
+      S->dws = nullptr;
+      S->dws_bytes = 0;
+    }
+    void* p = nullptr;
+    SK_HIP(hipMalloc(&p, bytes));
+    S->dws = p;
+    S->dws_bytes = bytes;
+  }
+  if (!S->h_pinned) SK_HIP(hipHostMalloc(&S->h_pinned, 4096, hipHostMallocDefault));
+  *out = static_cast<char*>(S->dws);
+  return SK_OK;
+}
+
+// Event pairs marking the phases of one driver call.
+struct Phases {
+  hipEvent_t ev[6] = {};
+  int n = 0;
+  hipStream_t st;
+  explicit Phases(hipStream_t s) : st(s) {}
+  int mark() {
+    if (n >= 6) return SK_OK;
+    SK_HIP(hipEventCreate(&ev[n]));
+    SK_HIP(hipEventRecord(ev[n], st));
+    ++n;
+    return SK_OK;
+  }
+  double ms(int a, int b) const {
+    float t = 0;
+    if (a < n && b < n && hipEventElapsedTime(&t, ev[a], ev[b]) == hipSuccess) return t;
+    return 0.0;
+  }
+  ~Phases() {
+    for (int i = 0; i < n; ++i) (void)hipEventDestroy(ev[i]);
+  }
+};
+
+#define SK_TRY(expr)            \
+  do {                          \
+    int _rc = (expr);           \
+    if (_rc < 0) return _rc;    \
+  } while (0)
+
+struct SketchBufs {
+  double* SA;
+  double* Sb;
+  void* aws;
+  size_t aws_bytes;
+  double* W;
+  double* tau;
+  double* Tbuf;
+  double* R;
+  double* c;
+};
+
+int sketch_bufs(Carver& cv, const sk_sketch* S, int k, int dts, const void* As, int64_t ldas, const double* b,
+                SketchBufs* B) {
+  size_t wa = 0, wb = 0;
+  SK_TRY(apply_workspace_for(S, dts, k, As, ldas, &wa));
+  SK_TRY(apply_workspace_for(S, SK_F64, 1, b, 1, &wb));
+  const int64_t d = S->d;
+  B->SA = cv.take<double>((size_t)d * k);
+  B->Sb = cv.take<double>((size_t)d);
+  B->aws_bytes = std::max(wa, wb);
+  B->aws = cv.take<char>(B->aws_bytes);
+  B->W = cv.take<double>((size_t)d * (k + 1));
+  B->tau = cv.take<double>((size_t)k);
+  B->Tbuf = cv.take<double>((size_t)((k + 31) / 32) * 32 * 32);
+  B->R = cv.take<double>((size_t)k * k);
+  B->c = cv.take<double>((size_t)k);
+  return SK_OK;
+}
+
+// S A (any input precision, F64 result), S b, and the Householder QR of
+// [S A | S b]: R (k x k) and c = (Q^T S b)[0:k].
+int sketch_and_factor(sk_sketch* S, int k, int dts, const void* As, int64_t ldas, const double* b, const SketchBufs& B,
+                      Phases& ph, hipStream_t st) {
+  const int64_t d = S->d;
+  SK_TRY(apply_dispatch(S, dts, k, As, ldas, SK_F64, B.SA, k, B.aws, B.aws_bytes, st));
+  SK_TRY(apply_dispatch(S, SK_F64, 1, b, 1, SK_F64, B.Sb, 1, B.aws, B.aws_bytes, st));
+  SK_TRY(ph.mark());
+  SK_TRY(launch_to_columns(B.SA, k, B.Sb, d, k, B.W, d, st));
+  SK_TRY(qr_columns(B.W, d, d, k, 1, B.tau, B.Tbuf, st));
+  SK_TRY(launch_extract_r(B.W, d, k, 1, B.R, B.c, st));
+  return SK_OK;
+}
+
+bool dtype_ok(int dt) { return dt == SK_F64 || dt == SK_F32 || dt == SK_BF16; }
+
+}  // namespace
+
+void drivers_release(sk_sketch* S) {
+  if (S->dws) (void)hipFree(S->dws);
+  if (S->h_pinned) (void)hipHostFree(S->h_pinned);
+  S->dws = nullptr;
+  S->h_pinned = nullptr;
+  S->dws_bytes = 0;
+}
+
+}  // namespace sk
+
+using namespace sk;
+
+extern "C" {
+
+int lstsq_sketch_solve(sketch_t S, int64_t m, const double* A, int64_t lda, const double* b, double* x,
+                       sk_solve_info* info, void* stream) {
+  if (!S || !A || !b || !x || m < 1 || lda < m) {
+    set_error("lstsq_sketch_solve: invalid argument");
+    return SK_E_INVAL;
+  }
+  if (S->d < m || m > 1024) {
+    set_error("lstsq_sketch_solve: need m <= d and m <= 1024");
+    return SK_E_INVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int k = (int)m;
+  Carver cv;
+  SketchBufs B;
+  SK_TRY(sketch_bufs(cv, S, k, SK_F64, A, lda, b, &B));
+  double* U = cv.take<double>((size_t)k * k);
+  double* V = cv.take<double>((size_t)k * k);
+  double* sv = cv.take<double>((size_t)k);
+  double* work = cv.take<double>((size_t)2 * k * k);
+  double* z = cv.take<double>((size_t)k);
+  int* rank = cv.take<int>(1);
+  char* base = nullptr;
+  SK_TRY(driver_workspace(S, cv.off, &base));
+  Carver cv2{base, 0};
+  SK_TRY(sketch_bufs(cv2, S, k, SK_F64, A, lda, b, &B));
+  U = cv2.take<double>((size_t)k * k);
+  V = cv2.take<double>((size_t)k * k);
+  sv = cv2.take<double>((size_t)k);
+  work = cv2.take<double>((size_t)2 * k * k);
+  z = cv2.take<double>((size_t)k);
+  rank = cv2.take<int>(1);
+
+  Phases ph(st);
+  SK_TRY(ph.mark());
+  SK_TRY(sketch_and_factor(S, k, SK_F64, A, lda, b, B, ph, st));
+  SK_TRY(launch_jacobi_svd(B.R, k, U, sv, V, work, st));
+  SK_TRY(launch_svd_solve(U, sv, V, B.c, k, std::ldexp(1.0, -52), x, z, rank, st));
+  SK_TRY(ph.mark());
+  char* hp = static_cast<char*>(S->h_pinned);
+  SK_HIP(hipMemcpyAsync(hp, rank, sizeof(int), hipMemcpyDeviceToHost, st));
+  SK_HIP(hipMemcpyAsync(hp + 8, sv, sizeof(double), hipMemcpyDeviceToHost, st));
+  SK_HIP(hipStreamSynchronize(st));
+  const int r = *reinterpret_cast<int*>(hp);
+  if (r > 0) {
+    SK_HIP(hipMemcpyAsync(hp + 16, sv + (r - 1), sizeof(double), hipMemcpyDeviceToHost, st));
+    SK_HIP(hipStreamSynchronize(st));
+  }
+  if (info) {
+    info->rank = r;
+    info->sigma_max = *reinterpret_cast<double*>(hp + 8);
+    info->sigma_min_kept = r > 0 ? *reinterpret_cast<double*>(hp + 16) : 0.0;
+    info->t_sketch_ms = ph.ms(0, 1);
+    info->t_total_ms = ph.ms(0, 2);
+  }
+  return r < k ? SK_W_RANKDEF : SK_OK;
+}
+
+int lstsq_sketch_precond(sketch_t S, int64_t m, const double* A, int64_t lda, int sketch_dtype, const void* A_sketch,
+                         int64_t lda_sketch, const double* b, double* x, double tol, int maxit, int warm_start,
+                         sk_lsqr_info* info, void* stream) {
+  if (!S || !A || !b || !x || m < 1 || lda < m || !(tol >= 0.0) || maxit < 0) {
+    set_error("lstsq_sketch_precond: invalid argument");
+    return SK_E_INVAL;
+  }
+  if (S->d < m || m > 512) {
+    set_error("lstsq_sketch_precond: need m <= d and m <= 512");
+    return SK_E_INVAL;
+  }
+  if (A_sketch && (!dtype_ok(sketch_dtype) || lda_sketch < m)) {
+    set_error("lstsq_sketch_precond: A_sketch needs dtype F64/F32/BF16 and lda_sketch >= m");
+    return SK_E_INVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int k = (int)m;
+  const int64_t n = S->n;
+  const void* As = A_sketch ? A_sketch : (const void*)A;
+  const int dts = A_sketch ? sketch_dtype : SK_F64;
+  const int64_t ldas = A_sketch ? lda_sketch : lda;
+  const int groups = lsqr_pass_groups(n);
+
+  double *Rinv, *x0, *v, *wd, *y, *wv, *tmp, *u, *part;
+  LsqrDev* sd;
+  SketchBufs B;
+  auto carve = [&](Carver& cv) -> int {
+    SK_TRY(sketch_bufs(cv, S, k, dts, As, ldas, b, &B));
+    Rinv = cv.take<double>((size_t)k * k);
+    x0 = cv.take<double>((size_t)k);
+    v = cv.take<double>((size_t)k);
+    wd = cv.take<double>((size_t)k);
+    y = cv.take<double>((size_t)k);
+    wv = cv.take<double>((size_t)k);
+    tmp = cv.take<double>((size_t)2 * k);
+    u = cv.take<double>((size_t)n);
+    part = cv.take<double>((size_t)(groups + 1) * (k + 1));
+    sd = cv.take<LsqrDev>(1);
+    return SK_OK;
+  };
+  Carver cv;
+  SK_TRY(carve(cv));
+  char* base = nullptr;
+  SK_TRY(driver_workspace(S, cv.off, &base));
+  Carver cv2{base, 0};
+  SK_TRY(carve(cv2));
+  double* qv = part + (size_t)groups * (k + 1);
+
+  Phases ph(st);
+  SK_TRY(ph.mark());                                                // 0
+  SK_TRY(sketch_and_factor(S, k, dts, As, ldas, b, B, ph, st));     // 1: after the sketch
+  SK_TRY(launch_trinv(B.R, k, Rinv, st));
+  if (warm_start)
+    SK_TRY(launch_rinv_vec(Rinv, k, B.c, x0, st));
+  else
+    SK_TRY(launch_fill(x0, k, 0.0, st));
+  SK_TRY(ph.mark());                                                // 2: after QR
+  SK_HIP(hipMemcpyAsync(u, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  SK_TRY(launch_lsqr_setup(sd, tol, maxit, st));
+  SK_TRY(launch_lsqr_pass(A, lda, n, k, x0, &sd->coef, nullptr, u, part, st));
+  SK_TRY(launch_lsqr_init(sd, qv, Rinv, k, v, wd, y, wv, tmp, st));
+  LsqrDev* hs = static_cast<LsqrDev*>(S->h_pinned);
+  const int batch = 4;
+  for (int it = 0;;) {
+    SK_HIP(hipMemcpyAsync(hs, sd, sizeof(LsqrDev), hipMemcpyDeviceToHost, st));
+    SK_HIP(hipStreamSynchronize(st));
+    if (hs->done || it >= maxit) break;
+    const int nb = std::min(batch, maxit - it);
+    for (int j = 0; j < nb; ++j) {
+      SK_TRY(launch_lsqr_pass(A, lda, n, k, wv, &sd->coef, &sd->done, u, part, st));
+      SK_TRY(launch_lsqr_step(sd, qv, Rinv, k, v, wd, y, wv, tmp, st));
+    }
+    it += nb;
+  }
+  SK_TRY(launch_lsqr_finish(Rinv, k, x0, y, x, st));
+  SK_TRY(ph.mark());                                                // 3: solution written
+  SK_HIP(hipStreamSynchronize(st));
+  if (info) {
+    info->iters = hs->iters;
+    info->converged = hs->converged;
+    info->rnorm_est = hs->rnorm;
+    info->arnorm_est = hs->arnorm;
+    info->anorm_est = hs->anorm;
+    info->t_sketch_ms = ph.ms(0, 1);
+    info->t_qr_ms = ph.ms(1, 2);
+    info->t_lsqr_ms = ph.ms(2, 3);
+    info->t_total_ms = ph.ms(0, 3);
+  }
+  return hs->converged ? SK_OK : SK_W_NOCONV;
+}
+
+int lstsq_residual(sketch_t S, int64_t m, const double* A, int64_t lda, const double* b, const double* x,
+                   double* resnorm, void* stream) {
+  if (!S || !A || !b || !x || !resnorm || m < 1 || lda < m) {
+    set_error("lstsq_residual: invalid argument");
+    return SK_E_INVAL;
+  }
+  if (m > 512) {
+    set_error("lstsq_residual: need m <= 512");
+    return SK_E_INVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = S->n;
+  const int k = (int)m;
+  const int groups = lsqr_pass_groups(n);
+  double *u, *part, *coef;
+  auto carve = [&](Carver& cv) {
+    u = cv.take<double>((size_t)n);
+    part = cv.take<double>((size_t)(groups + 1) * (k + 1));
+    coef = cv.take<double>(1);
+  };
+  Carver cv;
+  carve(cv);
+  char* base = nullptr;
+  SK_TRY(driver_workspace(S, cv.off, &base));
+  Carver cv2{base, 0};
+  carve(cv2);
+  SK_HIP(hipMemcpyAsync(u, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  SK_TRY(launch_fill(coef, 1, -1.0, st));
+  SK_TRY(launch_lsqr_pass(A, lda, n, k, x, coef, nullptr, u, part, st));
+  double* hp = static_cast<double*>(S->h_pinned);
+  SK_HIP(hipMemcpyAsync(hp, part + (size_t)groups * (k + 1) + k, sizeof(double), hipMemcpyDeviceToHost, st));
+  SK_HIP(hipStreamSynchronize(st));
+  *resnorm = std::sqrt(*hp);
+  return SK_OK;
+}
+
+}  // extern "C"

@@ -101,6 +101,11 @@ struct sk_sketch {
   // internal workspace (used when the caller passes ws = NULL)
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  // driver workspace (least-squares and low-rank drivers) and a pinned host
+  // block for reading back their scalars
+  void* dws = nullptr;
+  size_t dws_bytes = 0;
+  void* h_pinned = nullptr;
   // optional timing of the dominant kernel of each call (sketch_timing)
   mutable bool timing = false;
   mutable std::vector<std::pair<hipEvent_t, hipEvent_t>> events;

@@ -1,0 +1,28 @@
+// Dense FP64 building blocks of the least-squares and low-rank drivers.
+#pragma once
+#include "sk_common.hpp"
+
+namespace sk {
+
+// W (column-major, ldw) := columns of the row-major d x k0 matrix M, then r (if non-null).
+int launch_to_columns(const double* M, int64_t ldm, const double* r, int64_t d, int k0, double* W, int64_t ldw,
+                      hipStream_t st);
+// Blocked Householder QR of the first k columns of W (d x (k + extra_cols),
+// column-major), applying Q^T to the extra columns as well. tau: k entries;
+// Tbuf: ceil(k/32) * 32 * 32 doubles.
+int qr_columns(double* W, int64_t ldw, int64_t d, int k, int extra_cols, double* tau, double* Tbuf, hipStream_t st);
+// R (k x k row-major, upper) and c = first k entries of the (transformed) column k.
+int launch_extract_r(const double* W, int64_t ldw, int k, int has_rhs, double* R, double* c, hipStream_t st);
+// X = R^{-1} (k x k row-major, upper).
+int launch_trinv(const double* R, int k, double* X, hipStream_t st);
+// One-sided Jacobi SVD of a k x k row-major matrix R: R = U diag(s) V^T with
+// s descending. U, V: k x k row-major. work: 2 k^2 doubles.
+int launch_jacobi_svd(const double* R, int k, double* U, double* s, double* V, double* work, hipStream_t st);
+// x = V_r diag(s_r)^{-1} U_r^T c with r = #{s_i > 5 eps s_1} (written to
+// *rank_out, device). z: k doubles of scratch.
+int launch_svd_solve(const double* U, const double* s, const double* V, const double* c, int k, double eps, double* x,
+                     double* z, int* rank_out, hipStream_t st);
+// x[0:n) = value
+int launch_fill(double* x, int64_t n, double value, hipStream_t st);
+
+}  // namespace sk

@@ -9,6 +9,9 @@ int handle_workspace(sk_sketch* S, size_t bytes, void** out);
 // Bytes of workspace needed by sketch_apply (op 0) or sketch_apply_T (op 1).
 int apply_workspace(const sk_sketch* S, int op, int dtype_in, int64_t m, size_t* bytes);
 
+// Exact workspace bytes of sketch_apply for this A (alignment-dependent plan).
+int apply_workspace_for(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t lda, size_t* bytes);
+
 int apply_dispatch(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t lda, int dtype_out, void* SA,
                    int64_t ldsa, void* ws, size_t ws_bytes, hipStream_t st);
 int apply_T_dispatch(sk_sketch* S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out, void* Y,

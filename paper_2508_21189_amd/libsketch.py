@@ -71,7 +71,29 @@ def _bind_drivers(lib):
             fn.restype = ctypes.c_int
 
 
-_DRIVER_SIGS = {}
+class SolveInfo(ctypes.Structure):
+    """sk_solve_info."""
+    _fields_ = [("rank", ctypes.c_int), ("sigma_max", ctypes.c_double), ("sigma_min_kept", ctypes.c_double),
+                ("t_sketch_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
+
+
+class LsqrInfo(ctypes.Structure):
+    """sk_lsqr_info."""
+    _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int), ("rnorm_est", ctypes.c_double),
+                ("arnorm_est", ctypes.c_double), ("anorm_est", ctypes.c_double), ("t_sketch_ms", ctypes.c_double),
+                ("t_qr_ms", ctypes.c_double), ("t_lsqr_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
+
+
+def _as_dict(st):
+    return {name: getattr(st, name) for name, _ in st._fields_}
+
+
+_DRIVER_SIGS = {
+    "lstsq_sketch_solve": [_vp, _i64, _vp, _i64, _vp, _vp, ctypes.POINTER(SolveInfo), _vp],
+    "lstsq_sketch_precond": [_vp, _i64, _vp, _i64, ctypes.c_int, _vp, _i64, _vp, _vp, ctypes.c_double, ctypes.c_int,
+                             ctypes.c_int, ctypes.POINTER(LsqrInfo), _vp],
+    "lstsq_residual": [_vp, _i64, _vp, _i64, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp],
+}
 
 
 def exported_symbols():
@@ -170,3 +192,46 @@ class Sketch:
         s = torch.empty((self.n, self.zeta), dtype=torch.int8, device=device)
         check(load().sketch_pattern(self.h, _ptr(b), _ptr(s), _stream(stream)))
         return b, s
+
+    # -- least-squares drivers -------------------------------------------------
+    def _check_system(self, A, b):
+        assert A.is_cuda and A.dtype == torch.float64 and A.dim() == 2 and A.shape[0] == self.n
+        assert A.stride(1) == 1
+        assert b.is_cuda and b.dtype == torch.float64 and b.shape == (self.n,) and b.is_contiguous()
+
+    def lstsq_solve(self, A, b, stream=None):
+        """Sketch-and-solve: returns (x, status, info dict)."""
+        self._check_system(A, b)
+        m = A.shape[1]
+        x = torch.empty(m, dtype=torch.float64, device=A.device)
+        info = SolveInfo()
+        rc = check(load().lstsq_sketch_solve(self.h, m, _ptr(A), A.stride(0), _ptr(b), _ptr(x), ctypes.byref(info),
+                                             _stream(stream)))
+        return x, rc, _as_dict(info)
+
+    def lstsq_precond(self, A, b, tol=1e-10, maxit=100, warm_start=True, A_sketch=None, stream=None):
+        """Sketch-and-precondition LSQR: returns (x, status, info dict).
+
+        A_sketch: optional float32/bfloat16/float64 copy of A that is sketched instead of A.
+        """
+        self._check_system(A, b)
+        m = A.shape[1]
+        x = torch.empty(m, dtype=torch.float64, device=A.device)
+        info = LsqrInfo()
+        if A_sketch is not None:
+            assert A_sketch.is_cuda and A_sketch.shape == A.shape and A_sketch.stride(1) == 1
+            sdt, sp, sld = _DT[A_sketch.dtype], _ptr(A_sketch), A_sketch.stride(0)
+        else:
+            sdt, sp, sld = SK_F64, None, 0
+        rc = check(load().lstsq_sketch_precond(self.h, m, _ptr(A), A.stride(0), sdt, sp, sld, _ptr(b), _ptr(x),
+                                               float(tol), int(maxit), int(bool(warm_start)), ctypes.byref(info),
+                                               _stream(stream)))
+        return x, rc, _as_dict(info)
+
+    def residual(self, A, b, x, stream=None):
+        """||b - A x||_2 computed on the device in float64."""
+        self._check_system(A, b)
+        out = ctypes.c_double(0)
+        check(load().lstsq_residual(self.h, A.shape[1], _ptr(A), A.stride(0), _ptr(b), _ptr(x), ctypes.byref(out),
+                                    _stream(stream)))
+        return out.value

@@ -52,3 +52,31 @@ def test_null_handle_calls_fail_cleanly():
                                  ctypes.c_size_t, ctypes.c_void_p]
     assert lib.sketch_apply(None, 0, 0, 4, None, 4, 0, None, 4, None, 0, None) == -1
     assert lib.sketch_destroy(None) == 0
+
+
+def _header_struct_fields(name):
+    src = open(os.path.join(ROOT, "include", "libsketch.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct\s*\{([^}]*)\}\s*%s\s*;" % name, src).group(1)
+    return [(t.strip(), f.strip()) for t, f in re.findall(r"(int|double)\s+(\w+)\s*;", body)]
+
+
+@pytest.mark.parametrize("cname,pyname", [("sk_solve_info", "SolveInfo"), ("sk_lsqr_info", "LsqrInfo")])
+def test_info_structs_match_header(cname, pyname):
+    import ctypes as ct
+    from paper_2508_21189_amd import libsketch
+    st = getattr(libsketch, pyname)
+    want = [(f, {"int": ct.c_int, "double": ct.c_double}[t]) for t, f in _header_struct_fields(cname)]
+    assert [(f, t) for f, t in st._fields_] == want
+
+
+def test_driver_null_handle_fails_cleanly():
+    from paper_2508_21189_amd import libsketch
+    lib = libsketch.load()
+    info = libsketch.LsqrInfo()
+    rc = lib.lstsq_sketch_precond(None, 4, None, 4, 0, None, 0, None, None, 1e-10, 10, 1, ctypes.byref(info), None)
+    assert rc == libsketch.SK_E_INVAL
+    assert lib.lstsq_sketch_solve(None, 4, None, 4, None, None, None, None) == libsketch.SK_E_INVAL
+    out = ctypes.c_double(0)
+    assert lib.lstsq_residual(None, 4, None, 4, None, None, ctypes.byref(out), None) == libsketch.SK_E_INVAL
+    assert "invalid" in libsketch.last_error()
