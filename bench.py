@@ -4,13 +4,18 @@
 Workload (the coherent least-squares configuration): A is 4,194,304 x 200
 float64 with Pareto(1.5) row factors, 1% of rows spiked x1e3 and column
 scaling with condition number 1e8; S is a SparseStack with d = 800 rows in
-zeta = 8 blocks. A step is one SA = S A (sketch kernel + partial reduction)
-with A resident in HBM. The reported value is the whole step's algorithmic
-throughput: (n*m*8 + d*m*8) bytes / step time.
+zeta = 8 blocks. A step is one SA = S A (bucket-plan pass, sketch kernel and
+partial reduction) with A resident in HBM. The reported value is the whole
+step's algorithmic throughput: (n*m*8 + d*m*8) bytes / step time.
 
 The JSON line also carries
   roofline      the sketch kernel's own average duration (HIP events on its
                 stream), as a fraction of the 8 TB/s HBM peak;
+  lsqr          sketch-and-precondition solves of the same system to
+                tol = 1e-10 (LSQR's least-squares test), with the sketch read
+                from the float64 A, a float32 copy and a bfloat16 copy: wall
+                time per solve (median), iterations, the sketch / QR / LSQR
+                split, and the LSQR iteration's HBM roofline;
   cpu_baseline  the plain CPU oracle timed on a bounded row sample of the
                 same matrix on this host.
 """
@@ -69,6 +74,47 @@ def cpu_baseline(A_dev, rows):
                       "median of 3 runs, %.2f s each" % (rows, N, t)}
 
 
+def lsqr_variants(libsketch, torch, A, b, reps, tol=1e-10):
+    """Median wall time of lstsq_sketch_precond per sketch input precision."""
+    import statistics
+    S = libsketch.Sketch("sparsestack", D, N, ZETA, SKETCH_SEED)
+    out = {}
+    for name, dt in (("f64", None), ("f32", torch.float32), ("bf16", torch.bfloat16)):
+        As = A.to(dt) if dt is not None else None
+        S.lstsq_precond(A, b, tol=tol, maxit=300, A_sketch=As)  # warm-up (workspace, code objects)
+        walls, infos = [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, rc, info = S.lstsq_precond(A, b, tol=tol, maxit=300, A_sketch=As)
+            torch.cuda.synchronize()
+            walls.append((time.perf_counter() - t0) * 1e3)
+            infos.append(info)
+        res = S.residual(A, b, x)
+        med = statistics.median(walls)
+        it = infos[-1]
+        per_iter = statistics.median(i["t_lsqr_ms"] / max(1, i["iters"]) for i in infos)
+        out[name] = {"solve_ms": round(med, 3), "status": rc, "iters": it["iters"], "converged": it["converged"],
+                     "t_sketch_ms": round(statistics.median(i["t_sketch_ms"] for i in infos), 3),
+                     "t_qr_ms": round(statistics.median(i["t_qr_ms"] for i in infos), 3),
+                     "t_lsqr_ms": round(statistics.median(i["t_lsqr_ms"] for i in infos), 3),
+                     "lsqr_ms_per_iter": round(per_iter, 4),
+                     "resnorm": res, "rnorm_est": it["rnorm_est"]}
+        print("bench: lsqr %s %.2f ms, %d iterations" % (name, med, it["iters"]), file=sys.stderr, flush=True)
+        del As
+    f64 = out["f64"]
+    per_iter = f64["lsqr_ms_per_iter"]
+    it_bytes = N * M * 8
+    out["tol"] = tol
+    out["speedup_vs_f64"] = {k: round(f64["solve_ms"] / out[k]["solve_ms"], 3) for k in ("f32", "bf16")}
+    out["roofline_iteration"] = {"bound": "hbm", "achieved": round(it_bytes / (per_iter * 1e-3) / 1e9, 2),
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": round(it_bytes / (per_iter * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                 "alg_bytes_per_iteration": it_bytes,
+                                 "note": "one fused pass over A per iteration plus the small step kernels"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +122,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-rows", type=int, default=1 << 20)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain device copy of A (a kernel of known traffic, for counter calibration)")
+    ap.add_argument("--lsqr-reps", type=int, default=3, help="timed solves per sketch precision (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -132,6 +181,12 @@ def main():
                      "kernel": "ss_rows_kernel<double>", "kernel_avg_ms": round(kern_avg_ms, 4),
                      "alg_bytes_per_launch": alg_bytes},
     }
+    if args.copy_probe:
+        Acopy = A.clone()  # reads and writes n*m*8 bytes
+        torch.cuda.synchronize()
+        del Acopy
+    if args.lsqr_reps > 0:
+        rec["lsqr"] = lsqr_variants(libsketch, torch, A, b, args.lsqr_reps)
     if not args.no_cpu:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(A, args.cpu_rows)

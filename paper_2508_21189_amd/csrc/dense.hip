@@ -39,22 +39,34 @@ __global__ void to_columns_kernel(const double* __restrict__ M, int64_t ldm, con
 
 // Householder factorization of panel columns [k, k + nbp) of W (d rows), in
 // place: R on and above the diagonal, the reflector vectors v (unit leading
-// entry implicit) below it. tau[k + j] and T (nbp x nbp, upper, row-major)
-// with Q_panel = H_k ... H_{k+nbp-1} = I - V T V^T. LAPACK's sign convention:
-// beta = -sign(alpha) * ||x||, tau = (beta - alpha) / beta, v = x / (alpha - beta).
+// entry implicit) below it. tau[k + j] and T (nbp x nbp, upper, row-major,
+// stride kPanel) with Q_panel = H_k ... H_{k+nbp-1} = I - V T V^T. LAPACK's
+// sign convention: beta = -sign(alpha) ||x||, tau = (beta - alpha) / beta,
+// v = x / (alpha - beta).
+// Per column two block-wide reductions: ||x below the diagonal||^2, then in
+// one pass over the panel rows all the products the column needs: v^T y for
+// the later panel columns (their update) and v_q^T v for the earlier
+// reflectors (the Gram entries that build T).
 __global__ void __launch_bounds__(1024) hh_panel_kernel(double* __restrict__ W, int64_t ldw, int64_t d, int k,
                                                         int nbp, double* __restrict__ tau, double* __restrict__ T) {
-  __shared__ double red[16];
+  __shared__ double red[16][kPanel + 1];
+  __shared__ double vals[kPanel];
+  __shared__ double G[kPanel][kPanel + 1];  // G[q][j] = v_q^T v_j, q < j
+  __shared__ double Ts[kPanel][kPanel + 1];
+  __shared__ double taus[kPanel];
   __shared__ double sh_scal[4];
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
   for (int jj = 0; jj < nbp; ++jj) {
     const int c = k + jj;
     double* x = W + (int64_t)c * ldw;
-    // sigma^2 = ||x[c+1:]||^2
     double part = 0;
     for (int64_t i = c + 1 + tid; i < d; i += nt) part += x[i] * x[i];
-    const double sig2 = block_sum(part, red);
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+    if (lane == 0) red[wave][0] = part;
+    __syncthreads();
     if (tid == 0) {
+      double sig2 = 0;
+      for (int w = 0; w < nw; ++w) sig2 += red[w][0];
       const double alpha = x[c];
       double t = 0, beta = alpha, scale = 0;
       if (sig2 > 0) {
@@ -66,52 +78,64 @@ __global__ void __launch_bounds__(1024) hh_panel_kernel(double* __restrict__ W, 
       sh_scal[1] = beta;
       sh_scal[2] = scale;
       tau[c] = t;
+      taus[jj] = t;
     }
     __syncthreads();
-    const double t = sh_scal[0], beta = sh_scal[1], scale = sh_scal[2];
-    if (t != 0)
-      for (int64_t i = c + 1 + tid; i < d; i += nt) x[i] *= scale;
+    const double t = sh_scal[0], scale = sh_scal[2];
+    // v below the diagonal, and all panel products in the same sweep
+    double acc[kPanel];
+#pragma unroll
+    for (int q = 0; q < kPanel; ++q) acc[q] = 0;
+    for (int64_t i = c + 1 + tid; i < d; i += nt) {
+      double vi = x[i];
+      if (t != 0) {
+        vi *= scale;
+        x[i] = vi;
+      }
+#pragma unroll
+      for (int q = 0; q < kPanel; ++q)
+        if (q < nbp && q != jj) acc[q] += vi * W[(int64_t)(k + q) * ldw + i];
+    }
+#pragma unroll
+    for (int q = 0; q < kPanel; ++q) {
+      double v = acc[q];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (lane == 0) red[wave][q] = v;
+    }
     __syncthreads();
-    if (tid == 0) x[c] = beta;
-    // apply H_c = I - t v v^T to the remaining panel columns
-    for (int j2 = jj + 1; j2 < nbp && t != 0; ++j2) {
-      double* y = W + (int64_t)(k + j2) * ldw;
-      double p = 0;
-      for (int64_t i = c + 1 + tid; i < d; i += nt) p += x[i] * y[i];
-      const double wv = block_sum(p, red) + y[c];  // v_c = 1
-      const double f = t * wv;
-      for (int64_t i = c + 1 + tid; i < d; i += nt) y[i] -= f * x[i];
-      if (tid == 0) y[c] -= f;
-      __syncthreads();
+    if (tid < nbp && tid != jj) {
+      double sacc = W[(int64_t)(k + tid) * ldw + c];  // row c: v_c = 1
+      for (int w = 0; w < nw; ++w) sacc += red[w][tid];
+      vals[tid] = sacc;
+      if (tid < jj) G[tid][jj] = sacc;
+    }
+    if (tid == 0) x[c] = sh_scal[1];
+    __syncthreads();
+    // apply H_c = I - t v v^T to the later panel columns
+    if (t != 0) {
+      for (int q = jj + 1; q < nbp; ++q) {
+        const double f = t * vals[q];
+        double* y = W + (int64_t)(k + q) * ldw;
+        for (int64_t i = c + 1 + tid; i < d; i += nt) y[i] -= f * x[i];
+        if (tid == 0) y[c] -= f;
+      }
     }
     __syncthreads();
   }
-  // T: column i gets T[0:i, i] = -tau_i * T[0:i, 0:i] * (V[:, 0:i]^T v_i), T[i][i] = tau_i
+  // T: T[i][i] = tau_i; T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
   for (int i = 0; i < nbp; ++i) {
-    const int ci = k + i;
-    const double ti = tau[ci];
-    const double* vi = W + (int64_t)ci * ldw;
-    for (int j = 0; j < i; ++j) {
-      const int cj = k + j;
-      const double* vj = W + (int64_t)cj * ldw;
-      // v_j^T v_i over rows >= ci (v_i is zero above ci, v_i[ci] = 1)
-      double p = 0;
-      for (int64_t r = ci + 1 + tid; r < d; r += nt) p += vj[r] * vi[r];
-      const double dot = block_sum(p, red) + vj[ci];  // row ci: v_i = 1, v_j = W[cj][ci]
-      if (tid == 0) T[j * kPanel + i] = -ti * dot;    // temporarily the vector t_j
-      __syncthreads();
+    if (tid < i) {
+      double s2 = 0;
+      for (int l = tid; l < i; ++l) s2 += Ts[tid][l] * G[l][i];
+      Ts[tid][i] = -taus[i] * s2;
     }
-    if (tid == 0) {
-      // T[0:i, i] = T[0:i, 0:i] (upper) * t, in increasing row order: row j
-      // reads t_l (l >= j), which later rows have not yet overwritten
-      for (int j = 0; j < i; ++j) {
-        double s = 0;
-        for (int l = j; l < i; ++l) s += T[j * kPanel + l] * T[l * kPanel + i];
-        T[j * kPanel + i] = s;
-      }
-      T[i * kPanel + i] = ti;
-    }
+    if (tid == i) Ts[i][i] = taus[i];
+    if (tid > i && tid < nbp) Ts[tid][i] = 0.0;
     __syncthreads();
+  }
+  for (int idx = tid; idx < nbp * nbp; idx += nt) {
+    const int r = idx / nbp, cc = idx - r * nbp;
+    T[r * kPanel + cc] = Ts[r][cc];
   }
 }
 
@@ -181,20 +205,29 @@ __global__ void extract_r_kernel(const double* __restrict__ W, int64_t ldw, int 
       c[r] = W[(int64_t)k * ldw + r];
 }
 
-// Rinv = R^{-1} for upper-triangular R (k x k row-major). One wave per column j:
-// X[j][j] = 1/R[j][j]; X[i][j] = -(sum_{l=i+1..j} R[i][l] X[l][j]) / R[i][i].
-__global__ void __launch_bounds__(64) trinv_upper_kernel(const double* __restrict__ R, int k, double* __restrict__ X) {
+// X = R^{-1} for upper-triangular R (k x k row-major), and XT = X^T. One
+// wave per column j: X[j][j] = 1/R[j][j]; for i = j-1 down to 0,
+// X[i][j] = -(sum_{l=i+1..j} R[i][l] X[l][j]) / R[i][i]. The column is built
+// in LDS and written to both X (column j) and XT (row j).
+__global__ void __launch_bounds__(64) trinv_upper_kernel(const double* __restrict__ R, int k, double* __restrict__ X,
+                                                         double* __restrict__ XT) {
+  extern __shared__ double col[];
   const int j = blockIdx.x, lane = threadIdx.x;
-  for (int i = lane; i < k; i += 64) X[(int64_t)i * k + j] = 0.0;
+  for (int i = lane; i < k; i += 64) col[i] = 0.0;
   __syncthreads();
-  if (lane == 0) X[(int64_t)j * k + j] = 1.0 / R[(int64_t)j * k + j];
+  if (lane == 0) col[j] = 1.0 / R[(int64_t)j * k + j];
   __syncthreads();
   for (int i = j - 1; i >= 0; --i) {
+    const double* Ri = R + (int64_t)i * k;
     double s = 0;
-    for (int l = i + 1 + lane; l <= j; l += 64) s += R[(int64_t)i * k + l] * X[(int64_t)l * k + j];
+    for (int l = i + 1 + lane; l <= j; l += 64) s += Ri[l] * col[l];
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) X[(int64_t)i * k + j] = -s / R[(int64_t)i * k + i];
+    if (lane == 0) col[i] = -s / Ri[i];
     __syncthreads();
+  }
+  for (int i = lane; i < k; i += 64) {
+    X[(int64_t)i * k + j] = col[i];
+    XT[(int64_t)j * k + i] = col[i];
   }
 }
 
@@ -247,8 +280,8 @@ int launch_fill(double* x, int64_t n, double value, hipStream_t st) {
   return SK_OK;
 }
 
-int launch_trinv(const double* R, int k, double* X, hipStream_t st) {
-  hipLaunchKernelGGL(trinv_upper_kernel, dim3(k), dim3(64), 0, st, R, k, X);
+int launch_trinv(const double* R, int k, double* X, double* XT, hipStream_t st) {
+  hipLaunchKernelGGL(trinv_upper_kernel, dim3(k), dim3(64), (size_t)k * sizeof(double), st, R, k, X, XT);
   SK_HIP(hipGetLastError());
   return SK_OK;
 }

@@ -217,18 +217,18 @@ int lstsq_sketch_precond(sketch_t S, int64_t m, const double* A, int64_t lda, in
   const int64_t ldas = A_sketch ? lda_sketch : lda;
   const int groups = lsqr_pass_groups(n);
 
-  double *Rinv, *x0, *v, *wd, *y, *wv, *tmp, *u, *part;
+  double *Rinv, *RinvT, *x0, *v, *wd, *y, *wv, *u, *part;
   LsqrDev* sd;
   SketchBufs B;
   auto carve = [&](Carver& cv) -> int {
     SK_TRY(sketch_bufs(cv, S, k, dts, As, ldas, b, &B));
     Rinv = cv.take<double>((size_t)k * k);
+    RinvT = cv.take<double>((size_t)k * k);
     x0 = cv.take<double>((size_t)k);
     v = cv.take<double>((size_t)k);
     wd = cv.take<double>((size_t)k);
     y = cv.take<double>((size_t)k);
     wv = cv.take<double>((size_t)k);
-    tmp = cv.take<double>((size_t)2 * k);
     u = cv.take<double>((size_t)n);
     part = cv.take<double>((size_t)(groups + 1) * (k + 1));
     sd = cv.take<LsqrDev>(1);
@@ -245,7 +245,7 @@ int lstsq_sketch_precond(sketch_t S, int64_t m, const double* A, int64_t lda, in
   Phases ph(st);
   SK_TRY(ph.mark());                                                // 0
   SK_TRY(sketch_and_factor(S, k, dts, As, ldas, b, B, ph, st));     // 1: after the sketch
-  SK_TRY(launch_trinv(B.R, k, Rinv, st));
+  SK_TRY(launch_trinv(B.R, k, Rinv, RinvT, st));
   if (warm_start)
     SK_TRY(launch_rinv_vec(Rinv, k, B.c, x0, st));
   else
@@ -254,7 +254,7 @@ int lstsq_sketch_precond(sketch_t S, int64_t m, const double* A, int64_t lda, in
   SK_HIP(hipMemcpyAsync(u, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
   SK_TRY(launch_lsqr_setup(sd, tol, maxit, st));
   SK_TRY(launch_lsqr_pass(A, lda, n, k, x0, &sd->coef, nullptr, u, part, st));
-  SK_TRY(launch_lsqr_init(sd, qv, Rinv, k, v, wd, y, wv, tmp, st));
+  SK_TRY(launch_lsqr_init(sd, qv, Rinv, RinvT, k, v, wd, y, wv, st));
   LsqrDev* hs = static_cast<LsqrDev*>(S->h_pinned);
   const int batch = 4;
   for (int it = 0;;) {
@@ -264,7 +264,7 @@ int lstsq_sketch_precond(sketch_t S, int64_t m, const double* A, int64_t lda, in
     const int nb = std::min(batch, maxit - it);
     for (int j = 0; j < nb; ++j) {
       SK_TRY(launch_lsqr_pass(A, lda, n, k, wv, &sd->coef, &sd->done, u, part, st));
-      SK_TRY(launch_lsqr_step(sd, qv, Rinv, k, v, wd, y, wv, tmp, st));
+      SK_TRY(launch_lsqr_step(sd, qv, Rinv, RinvT, k, v, wd, y, wv, st));
     }
     it += nb;
   }

@@ -99,15 +99,53 @@ __global__ void __launch_bounds__(256) lsqr_pass_kernel(const double* __restrict
   }
 }
 
-// out[j] = sum_g part[g][j], g in increasing order.
-__global__ void reduce_cols_kernel(const double* __restrict__ part, int ngroups, int width, const int* __restrict__ donep,
-                                   double* __restrict__ out) {
+// out[j] = sum_g part[g][j]: one workgroup per column j; thread t sums
+// g = t, t + 256, ... in order, then a fixed-order tree (deterministic).
+__global__ void __launch_bounds__(256) reduce_cols_kernel(const double* __restrict__ part, int ngroups, int width,
+                                                          const int* __restrict__ donep, double* __restrict__ out) {
   if (donep && *donep) return;
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < width; j += gridDim.x * blockDim.x) {
-    double s = 0;
-    for (int g = 0; g < ngroups; ++g) s += part[(int64_t)g * width + j];
-    out[j] = s;
+  __shared__ double red[4];
+  const int j = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double s = 0;
+  for (int g = tid; g < ngroups; g += 256) s += part[(int64_t)g * width + j];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) red[wave] = s;
+  __syncthreads();
+  if (tid == 0) out[j] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// out_j = sum_i M[i][j] x_i for a triangular k x k row-major M (k <= 512):
+// UPPER: M[i][j] = 0 for i > j; else M[i][j] = 0 for i < j. Waves take
+// rows i = wave, wave + 16, ...; lanes take columns; the per-wave partial
+// sums are added in wave order. xs and part live in LDS; out may be global.
+template <bool UPPER>
+__device__ inline void tri_cols(const double* __restrict__ M, int k, const double* xs, double* out, double* part) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  double acc[8];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) acc[p] = 0;
+  for (int i = wave; i < k; i += nw) {
+    const double xi = xs[i];
+    const double* row = M + (int64_t)i * k;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int j = lane + 64 * p;
+      const bool in = UPPER ? (j >= i && j < k) : (j <= i);
+      if (in) acc[p] += row[j] * xi;
+    }
   }
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const int j = lane + 64 * p;
+    if (j < k) part[wave * k + j] = acc[p];
+  }
+  __syncthreads();
+  for (int j = tid; j < k; j += blockDim.x) {
+    double sum = 0;
+    for (int w = 0; w < nw; ++w) sum += part[w * k + j];
+    out[j] = sum;
+  }
+  __syncthreads();
 }
 
 __device__ inline double wg_sum(double v, double* red) {
@@ -117,26 +155,12 @@ __device__ inline double wg_sum(double v, double* red) {
   if (lane == 0) red[wave] = v;
   __syncthreads();
   double s = 0;
-  for (int k = 0; k < nw; ++k) s += red[k];
+  for (int q = 0; q < nw; ++q) s += red[q];
   return s;
 }
 
-// t = Rinv^T x (Rinv upper k x k): t_j = sum_{i <= j} Rinv[i][j] x_i
-__device__ inline void rinv_t_apply(const double* Rinv, int k, const double* x, double* t) {
-  for (int j = threadIdx.x; j < k; j += blockDim.x) {
-    double s = 0;
-    for (int i = 0; i <= j; ++i) s += Rinv[(int64_t)i * k + j] * x[i];
-    t[j] = s;
-  }
-}
-// t = Rinv x: t_i = sum_{j >= i} Rinv[i][j] x_j
-__device__ inline void rinv_apply(const double* Rinv, int k, const double* x, double* t) {
-  for (int i = threadIdx.x; i < k; i += blockDim.x) {
-    double s = 0;
-    for (int j = i; j < k; ++j) s += Rinv[(int64_t)i * k + j] * x[j];
-    t[i] = s;
-  }
-}
+// LDS of the init / step kernels: part[16][k], xs[k], t1[k]
+inline size_t lsqr_step_lds(int k) { return (size_t)(16 * k + 2 * k) * sizeof(double); }
 
 // Constants of one solve; coef = -1 makes the first pass form A x0 - b.
 __global__ void lsqr_setup_kernel(LsqrDev* st, double tol, int maxit) {
@@ -151,30 +175,36 @@ __global__ void lsqr_setup_kernel(LsqrDev* st, double tol, int maxit) {
   }
 }
 
-// After the pass p0 = A x0 - b: q = A^T p0, pp = ||p0||^2 (in qv[m]).
+// After the pass p0 = A x0 - b: q = A^T p0, pp = ||p0||^2 (in qv[k]).
 // beta u1 = r0 = -p0; alpha v1 = Rinv^T A^T u1; w = v1; phibar = beta; rhobar = alpha.
-__global__ void __launch_bounds__(512) lsqr_init_kernel(LsqrDev* st, const double* __restrict__ qv,
-                                                        const double* __restrict__ Rinv, int k, double* __restrict__ v,
-                                                        double* __restrict__ wd, double* __restrict__ y,
-                                                        double* __restrict__ wv, double* __restrict__ tmp) {
-  __shared__ double red[8];
+__global__ void __launch_bounds__(1024) lsqr_init_kernel(LsqrDev* st, const double* __restrict__ qv,
+                                                         const double* __restrict__ Rinv,
+                                                         const double* __restrict__ RinvT, int k,
+                                                         double* __restrict__ v, double* __restrict__ wd,
+                                                         double* __restrict__ y, double* __restrict__ wv) {
+  extern __shared__ double lds[];
+  __shared__ double red[16];
+  double* part = lds;
+  double* xs = lds + 16 * k;
+  double* t1 = xs + k;
   const double beta = sqrt(qv[k]);
   const double sc = beta > 0 ? -1.0 / beta : 0.0;  // A^T u1 = -q / beta
-  for (int j = threadIdx.x; j < k; j += blockDim.x) tmp[j] = qv[j] * sc;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) xs[j] = qv[j] * sc;
   __syncthreads();
-  rinv_t_apply(Rinv, k, tmp, v);
-  __syncthreads();
-  double part = 0;
-  for (int j = threadIdx.x; j < k; j += blockDim.x) part += v[j] * v[j];
-  const double alpha = sqrt(wg_sum(part, red));
+  tri_cols<true>(Rinv, k, xs, t1, part);  // Rinv^T (A^T u1)
+  double pn = 0;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) pn += t1[j] * t1[j];
+  const double alpha = sqrt(wg_sum(pn, red));
   const double ia = alpha > 0 ? 1.0 / alpha : 0.0;
   for (int j = threadIdx.x; j < k; j += blockDim.x) {
-    v[j] *= ia;
-    wd[j] = v[j];
+    const double vj = t1[j] * ia;
+    xs[j] = vj;
+    v[j] = vj;
+    wd[j] = vj;
     y[j] = 0.0;
   }
   __syncthreads();
-  rinv_apply(Rinv, k, v, wv);
+  tri_cols<false>(RinvT, k, xs, wv, part);  // Rinv v1
   if (threadIdx.x == 0) {
     st->beta = beta;
     st->alpha = alpha;
@@ -187,34 +217,37 @@ __global__ void __launch_bounds__(512) lsqr_init_kernel(LsqrDev* st, const doubl
     st->iters = 0;
     st->converged = (beta == 0.0 || alpha == 0.0) ? 1 : 0;
     st->done = (st->converged || st->maxit <= 0) ? 1 : 0;
-    st->uscale = sc;                  // u1 = sc * (stored p0)
-    st->coef = -alpha * sc;           // next pass: p = A w - alpha u1
+    st->uscale = sc;         // u1 = sc * (stored p0)
+    st->coef = -alpha * sc;  // next pass: p = A w - alpha u1
   }
 }
 
-// One LSQR step after the pass: p = A w - alpha u_k stored, q = A^T p, pp = ||p||^2.
-__global__ void __launch_bounds__(512) lsqr_step_kernel(LsqrDev* st, const double* __restrict__ qv,
-                                                        const double* __restrict__ Rinv, int k, double* __restrict__ v,
-                                                        double* __restrict__ wd, double* __restrict__ y,
-                                                        double* __restrict__ wv, double* __restrict__ tmp) {
-  __shared__ double red[8];
-  __shared__ double sh[4];
+// One LSQR step after the pass p = A wv - alpha u_k (stored), q = A^T p, ||p||^2.
+__global__ void __launch_bounds__(1024) lsqr_step_kernel(LsqrDev* st, const double* __restrict__ qv,
+                                                         const double* __restrict__ Rinv,
+                                                         const double* __restrict__ RinvT, int k,
+                                                         double* __restrict__ v, double* __restrict__ wd,
+                                                         double* __restrict__ y, double* __restrict__ wv) {
+  extern __shared__ double lds[];
+  __shared__ double red[16];
+  __shared__ double sh[2];
   if (st->done) return;
+  double* part = lds;
+  double* xs = lds + 16 * k;
+  double* t1 = xs + k;
   const double alpha_old = st->alpha;
   const double beta = sqrt(qv[k]);
   const double ib = beta > 0 ? 1.0 / beta : 0.0;
-  // v_new = Rinv^T (q / beta) - beta v
-  for (int j = threadIdx.x; j < k; j += blockDim.x) tmp[j] = qv[j] * ib;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) xs[j] = qv[j] * ib;  // A^T u_{k+1}
   __syncthreads();
-  rinv_t_apply(Rinv, k, tmp, tmp + k);
-  __syncthreads();
-  double part = 0;
+  tri_cols<true>(Rinv, k, xs, t1, part);
+  double pn = 0;
   for (int j = threadIdx.x; j < k; j += blockDim.x) {
-    const double vn = tmp[k + j] - beta * v[j];
-    tmp[k + j] = vn;
-    part += vn * vn;
+    const double vn = t1[j] - beta * v[j];
+    t1[j] = vn;
+    pn += vn * vn;
   }
-  const double alpha = sqrt(wg_sum(part, red));
+  const double alpha = sqrt(wg_sum(pn, red));
   if (threadIdx.x == 0) {
     const double anorm2 = st->anorm2 + alpha_old * alpha_old + beta * beta;
     const double rhobar = st->rhobar, phibar = st->phibar;
@@ -245,13 +278,14 @@ __global__ void __launch_bounds__(512) lsqr_step_kernel(LsqrDev* st, const doubl
   const double f1 = sh[0], f2 = sh[1];
   const double ia = alpha > 0 ? 1.0 / alpha : 0.0;
   for (int j = threadIdx.x; j < k; j += blockDim.x) {
-    const double vn = tmp[k + j] * ia;
+    const double vn = t1[j] * ia;
     y[j] += f1 * wd[j];
     wd[j] = vn - f2 * wd[j];
     v[j] = vn;
+    xs[j] = vn;
   }
   __syncthreads();
-  rinv_apply(Rinv, k, v, wv);
+  tri_cols<false>(RinvT, k, xs, wv, part);  // Rinv v_{k+1}
 }
 
 // x = x0 + Rinv y
@@ -301,7 +335,7 @@ int launch_lsqr_pass(const double* A, int64_t lda, int64_t n, int m, const doubl
   }
 #undef SK_PASS
   SK_HIP(hipGetLastError());
-  hipLaunchKernelGGL(reduce_cols_kernel, dim3((m + 1 + 255) / 256), dim3(256), 0, st, part, groups, m + 1, donep,
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3(m + 1), dim3(256), 0, st, part, groups, m + 1, donep,
                      part + (int64_t)groups * (m + 1));
   SK_HIP(hipGetLastError());
   return SK_OK;
@@ -313,16 +347,20 @@ int launch_lsqr_setup(LsqrDev* sd, double tol, int maxit, hipStream_t st) {
   return SK_OK;
 }
 
-int launch_lsqr_init(LsqrDev* sd, const double* qv, const double* Rinv, int k, double* v, double* wd, double* y,
-                     double* wv, double* tmp, hipStream_t st) {
-  hipLaunchKernelGGL(lsqr_init_kernel, dim3(1), dim3(512), 0, st, sd, qv, Rinv, k, v, wd, y, wv, tmp);
+int launch_lsqr_init(LsqrDev* sd, const double* qv, const double* Rinv, const double* RinvT, int k, double* v,
+                     double* wd, double* y, double* wv, hipStream_t st) {
+  const size_t lds = lsqr_step_lds(k);
+  SK_HIP(hipFuncSetAttribute((const void*)lsqr_init_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(lsqr_init_kernel, dim3(1), dim3(1024), lds, st, sd, qv, Rinv, RinvT, k, v, wd, y, wv);
   SK_HIP(hipGetLastError());
   return SK_OK;
 }
 
-int launch_lsqr_step(LsqrDev* sd, const double* qv, const double* Rinv, int k, double* v, double* wd, double* y,
-                     double* wv, double* tmp, hipStream_t st) {
-  hipLaunchKernelGGL(lsqr_step_kernel, dim3(1), dim3(512), 0, st, sd, qv, Rinv, k, v, wd, y, wv, tmp);
+int launch_lsqr_step(LsqrDev* sd, const double* qv, const double* Rinv, const double* RinvT, int k, double* v,
+                     double* wd, double* y, double* wv, hipStream_t st) {
+  const size_t lds = lsqr_step_lds(k);
+  SK_HIP(hipFuncSetAttribute((const void*)lsqr_step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(lsqr_step_kernel, dim3(1), dim3(1024), lds, st, sd, qv, Rinv, RinvT, k, v, wd, y, wv);
   SK_HIP(hipGetLastError());
   return SK_OK;
 }

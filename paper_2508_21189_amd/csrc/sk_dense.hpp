@@ -13,8 +13,8 @@ int launch_to_columns(const double* M, int64_t ldm, const double* r, int64_t d, 
 int qr_columns(double* W, int64_t ldw, int64_t d, int k, int extra_cols, double* tau, double* Tbuf, hipStream_t st);
 // R (k x k row-major, upper) and c = first k entries of the (transformed) column k.
 int launch_extract_r(const double* W, int64_t ldw, int k, int has_rhs, double* R, double* c, hipStream_t st);
-// X = R^{-1} (k x k row-major, upper).
-int launch_trinv(const double* R, int k, double* X, hipStream_t st);
+// X = R^{-1} (k x k row-major, upper) and XT = X^T. k <= 8192.
+int launch_trinv(const double* R, int k, double* X, double* XT, hipStream_t st);
 // One-sided Jacobi SVD of a k x k row-major matrix R: R = U diag(s) V^T with
 // s descending. U, V: k x k row-major. work: 2 k^2 doubles.
 int launch_jacobi_svd(const double* R, int k, double* U, double* s, double* V, double* work, hipStream_t st);

@@ -23,6 +23,9 @@ struct RowsPlan {
   size_t plan_bytes = 0;     // workspace: per-tile bucket plans
   int64_t n_tiles = 0;
   int rec_bytes = 0, lst_off = 0;
+  // narrow inputs (m <= 4): lanes over buckets instead of columns
+  bool narrow = false;
+  int64_t tiles_per_chunk = 0;
 };
 
 // Chooses the plan; returns SK_OK or SK_E_NOTSUP (and sets the error).

@@ -23,11 +23,12 @@ int launch_lsqr_pass(const double* A, int64_t lda, int64_t n, int m, const doubl
 // Writes tol, maxit and the constants read by the first pass (coef = -1).
 int launch_lsqr_setup(LsqrDev* sd, double tol, int maxit, hipStream_t st);
 // From qv of the pass p0 = A x0 - b: beta u1, alpha v1, w = v1, wv = Rinv v1.
-int launch_lsqr_init(LsqrDev* sd, const double* qv, const double* Rinv, int k, double* v, double* wd, double* y,
-                     double* wv, double* tmp, hipStream_t st);
+// Rinv: R^{-1} (k x k row-major, upper); RinvT: its transpose. k <= 512.
+int launch_lsqr_init(LsqrDev* sd, const double* qv, const double* Rinv, const double* RinvT, int k, double* v,
+                     double* wd, double* y, double* wv, hipStream_t st);
 // One iteration from qv of the pass p = A wv - alpha u (no-op once done).
-int launch_lsqr_step(LsqrDev* sd, const double* qv, const double* Rinv, int k, double* v, double* wd, double* y,
-                     double* wv, double* tmp, hipStream_t st);
+int launch_lsqr_step(LsqrDev* sd, const double* qv, const double* Rinv, const double* RinvT, int k, double* v,
+                     double* wd, double* y, double* wv, hipStream_t st);
 // x = x0 + Rinv y
 int launch_lsqr_finish(const double* Rinv, int k, const double* x0, const double* y, double* x, hipStream_t st);
 // x = Rinv c

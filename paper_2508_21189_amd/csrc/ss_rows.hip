@@ -379,6 +379,89 @@ __global__ void __launch_bounds__(1024) ss_rows_kernel(RowsArgs a) {
   }
 }
 
+// Narrow inputs (m <= 4 columns, e.g. the right-hand side b): one lane per
+// output row of S (bucket s of block t) walks that bucket's list in the
+// tile's plan, so no lane idles on absent columns. A workgroup owns a chunk
+// of consecutive tiles; per tile it stages the rows' values (converted to
+// the accumulation type) and the tile's plan records in LDS. Sums run in
+// list order (row order) and chunks are added in order: deterministic.
+struct NarrowArgs {
+  const unsigned char* A;
+  int64_t lda_bytes, n, d;
+  int m, R, zeta, nb;
+  const unsigned char* plan;
+  int rec_bytes, lst_off;
+  int64_t n_tiles, tiles_per_chunk;
+  void* P;
+};
+
+template <typename Tin>
+__device__ inline typename InType<Tin>::acc load_in(const unsigned char* p);
+template <>
+__device__ inline double load_in<double>(const unsigned char* p) { return *(const double*)p; }
+template <>
+__device__ inline float load_in<float>(const unsigned char* p) { return *(const float*)p; }
+template <>
+__device__ inline float load_in<uint16_t>(const unsigned char* p) { return bf16_to_f32(*(const uint16_t*)p); }
+
+template <typename Tin, int MV>
+__global__ void __launch_bounds__(1024) ss_narrow_kernel(NarrowArgs a) {
+  using Tacc = typename InType<Tin>::acc;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  Tacc* vals = (Tacc*)smem;  // [R][MV]
+  unsigned char* pl = smem + (((size_t)a.R * MV * sizeof(Tacc) + 15) & ~(size_t)15);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t tb = (int64_t)blockIdx.x * a.tiles_per_chunk;
+  const int64_t te = min(a.n_tiles, tb + a.tiles_per_chunk);
+  Tacc acc[4][MV];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int c = 0; c < MV; ++c) acc[q][c] = 0;
+  const int es = (int)sizeof(Tin);
+  for (int64_t tile = tb; tile < te; ++tile) {
+    const int64_t r0 = tile * a.R;
+    const int rv = (int)min((int64_t)a.R, a.n - r0);
+    for (int idx = tid; idx < rv * a.m; idx += nt) {
+      const int row = idx / a.m, c = idx - row * a.m;
+      vals[row * MV + c] = load_in<Tin>(a.A + (r0 + row) * a.lda_bytes + (int64_t)c * es);
+    }
+    const uint4* src = (const uint4*)(a.plan + tile * a.zeta * (int64_t)a.rec_bytes);
+    uint4* dst = (uint4*)pl;
+    const int n16 = a.zeta * a.rec_bytes / 16;
+    for (int idx = tid; idx < n16; idx += nt) dst[idx] = src[idx];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t j = tid + (int64_t)q * nt;
+      if (j < a.d) {
+        const int t = (int)(j / a.nb), s = (int)(j - (int64_t)t * a.nb);
+        const unsigned char* rec = pl + t * a.rec_bytes;
+        const uint16_t* of = (const uint16_t*)rec;
+        const uint16_t* lst = (const uint16_t*)(rec + a.lst_off);
+        const int kb = of[s], ke = of[s + 1];
+        for (int k = kb; k < ke; ++k) {
+          const uint32_t e = lst[k];
+          const Tacc* vr = vals + (e >> 2) * MV;
+#pragma unroll
+          for (int c = 0; c < MV; ++c) acc[q][c] += (e & 1u) ? -vr[c] : vr[c];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  Tacc* P = (Tacc*)a.P;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t j = tid + (int64_t)q * nt;
+    if (j < a.d) {
+#pragma unroll
+      for (int c = 0; c < MV; ++c)
+        if (c < a.m) P[((int64_t)blockIdx.x * a.d + j) * a.m + c] = acc[q][c];
+    }
+  }
+}
+
 // SA[j, c] = scale * sum_w P[w][j][c], w in increasing order.
 template <typename Tacc, typename Tout>
 __global__ void reduce_partials_kernel(const Tacc* __restrict__ P, int n_chunks, int64_t d, int64_t m, Tacc scale,
@@ -482,10 +565,49 @@ static int jb_variant(int dtype_in, int per_range) {
   return jb_max(dtype_in);
 }
 
+// LDS of the narrow kernel (values + the tile's plan records) and of the plan
+// kernel for a tile of R rows.
+static size_t narrow_lds(int R, int accb, int zeta, int rec_bytes) {
+  return align16((size_t)R * 4 * accb) + (size_t)zeta * rec_bytes;
+}
+static size_t plan_lds(int R, int zeta, int64_t nb) {
+  return align16((size_t)2 * zeta * R * 2 + 4) + (size_t)zeta * (nb + 1) * 4;
+}
+
+static int plan_narrow(const sk_sketch* S, int dtype_in, int64_t m, RowsPlan* p) {
+  const size_t cap = 160 * 1024;
+  const int accb = dtype_in == SK_F64 ? 8 : 4;
+  int R = 2048;
+  for (;;) {
+    plan_record(R, S->nb, &p->rec_bytes, &p->lst_off);
+    if ((narrow_lds(R, accb, S->zeta, p->rec_bytes) <= cap && plan_lds(R, S->zeta, S->nb) <= cap) || R <= 64) break;
+    R /= 2;
+  }
+  if (narrow_lds(R, accb, S->zeta, p->rec_bytes) > cap || plan_lds(R, S->zeta, S->nb) > cap) {
+    set_error("sketch_apply: zeta * (d/zeta) too large for the narrow-input plan");
+    return SK_E_NOTSUP;
+  }
+  p->narrow = true;
+  p->R = R;
+  p->C = (int)m;
+  p->n_slabs = 1;
+  p->n_tiles = (S->n + R - 1) / R;
+  const int64_t target = env_int("SKETCH_WG_TARGET", 256);
+  int64_t tpc = std::max<int64_t>(1, (p->n_tiles + target - 1) / target);
+  p->tiles_per_chunk = tpc;
+  p->n_chunks = (int)((p->n_tiles + tpc - 1) / tpc);
+  p->rows_per_chunk = tpc * R;
+  p->lds_bytes = narrow_lds(R, accb, S->zeta, p->rec_bytes);
+  p->partial_bytes = align16((size_t)p->n_chunks * S->d * m * accb);
+  p->plan_bytes = align16((size_t)p->n_tiles * S->zeta * p->rec_bytes);
+  return SK_OK;
+}
+
 int plan_rows(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t lda, RowsPlan* p) {
   const int es = (int)dtype_size(dtype_in);
   const int zeta = S->zeta;
   const int64_t nb = S->nb;
+  if (m <= 4 && S->d <= 4096 && nb <= 16383) return plan_narrow(S, dtype_in, m, p);
   if (nb > 16384) {
     set_error("SparseStack row apply supports at most 16384 buckets per block");
     return SK_E_NOTSUP;
@@ -574,8 +696,7 @@ static int launch_plan(const sk_sketch* S, const RowsPlan& p, void* plan, hipStr
   a.rec_bytes = p.rec_bytes;
   a.lst_off = p.lst_off;
   const int threads = 64 * std::min(16, S->zeta);
-  const size_t codes = (size_t)S->zeta * p.R * 2;
-  const size_t lds = align16(2 * codes + 4) + (size_t)S->zeta * (S->nb + 1) * 4;
+  const size_t lds = plan_lds(p.R, S->zeta, S->nb);
   SK_HIP(hipFuncSetAttribute((const void*)ss_plan_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(ss_plan_kernel, dim3((unsigned)p.n_tiles), dim3(threads), lds, st, a);
   SK_HIP(hipGetLastError());
@@ -651,6 +772,43 @@ static int launch_rows_jb(const sk_sketch* S, const RowsPlan& p, int64_t m, cons
   return launch_rows_t<Tin, JMAX, 4>(S, p, m, A, lda, P, plan, st);
 }
 
+template <typename Tin, int MV>
+static int launch_narrow_t(const sk_sketch* S, const RowsPlan& p, int64_t m, const void* A, int64_t lda, void* P,
+                           const void* plan, hipStream_t st) {
+  NarrowArgs a;
+  a.A = (const unsigned char*)A;
+  a.lda_bytes = lda * (int64_t)sizeof(Tin);
+  a.n = S->n;
+  a.d = S->d;
+  a.m = (int)m;
+  a.R = p.R;
+  a.zeta = S->zeta;
+  a.nb = (int)S->nb;
+  a.plan = (const unsigned char*)plan;
+  a.rec_bytes = p.rec_bytes;
+  a.lst_off = p.lst_off;
+  a.n_tiles = p.n_tiles;
+  a.tiles_per_chunk = p.tiles_per_chunk;
+  a.P = P;
+  const int threads = (int)std::min<int64_t>(1024, ((S->d + 63) / 64) * 64);
+  auto kern = ss_narrow_kernel<Tin, MV>;
+  SK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes));
+  {
+    KernelTimer timer(S, st);
+    hipLaunchKernelGGL(kern, dim3((unsigned)p.n_chunks), dim3(threads), p.lds_bytes, st, a);
+  }
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+template <typename Tin>
+static int launch_narrow(const sk_sketch* S, const RowsPlan& p, int64_t m, const void* A, int64_t lda, void* P,
+                         const void* plan, hipStream_t st) {
+  if (m == 1) return launch_narrow_t<Tin, 1>(S, p, m, A, lda, P, plan, st);
+  if (m == 2) return launch_narrow_t<Tin, 2>(S, p, m, A, lda, P, plan, st);
+  return launch_narrow_t<Tin, 4>(S, p, m, A, lda, P, plan, st);
+}
+
 // Workspace: partials, then the plan records.
 int launch_rows_apply(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64_t m, const void* A, int64_t lda,
                       int dtype_out, void* SA, int64_t ldsa, void* ws, hipStream_t st) {
@@ -658,7 +816,14 @@ int launch_rows_apply(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64
   void* plan = (unsigned char*)ws + p.partial_bytes;
   int rc = launch_plan(S, p, plan, st);
   if (rc != SK_OK) return rc;
-  if (dtype_in == SK_F64)
+  if (p.narrow) {
+    if (dtype_in == SK_F64)
+      rc = launch_narrow<double>(S, p, m, A, lda, P, plan, st);
+    else if (dtype_in == SK_F32)
+      rc = launch_narrow<float>(S, p, m, A, lda, P, plan, st);
+    else
+      rc = launch_narrow<uint16_t>(S, p, m, A, lda, P, plan, st);
+  } else if (dtype_in == SK_F64)
     rc = launch_rows_jb<double>(S, p, m, A, lda, P, plan, st);
   else if (dtype_in == SK_F32)
     rc = launch_rows_jb<float>(S, p, m, A, lda, P, plan, st);

@@ -75,6 +75,11 @@ CASES = [
     (300, 1, 30, 3, 7),        # single column (the right-hand side)
     (9000, 200, 800, 8, 8),    # workload 2 column count, several row tiles
     (200000, 50, 200, 4, 9),   # many sub-tiles per row chunk (both LDS buffers in use)
+    (50000, 3, 400, 8, 10),    # narrow input: lanes over buckets, several tiles per chunk
+    (70001, 2, 2000, 8, 12),   # narrow input, two buckets per lane, ragged last tile
+    (9000, 4, 4096, 4, 13),    # narrow input at its largest d (four buckets per lane)
+    (1000003, 1, 800, 8, 15),  # narrow input, the right-hand side at scale (many tiles per chunk)
+    (4000, 5, 64, 4, 14),      # the narrowest input of the wide kernel
 ]
 
 
@@ -91,7 +96,8 @@ def test_apply_f64_parity(lib, n, m, d, zeta, seed):
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
 @pytest.mark.parametrize("n,m,d,zeta,seed", [(20000, 64, 200, 4, 1), (6007, 100, 2000, 8, 2),
                                              (3000, 16, 64, 8, 3), (1000, 500, 400, 8, 4),
-                                             (100000, 64, 400, 8, 5)])
+                                             (100000, 64, 400, 8, 5), (30000, 1, 200, 4, 6),
+                                             (20011, 3, 96, 8, 7)])
 def test_apply_lowprec_parity(lib, dtype, n, m, d, zeta, seed):
     rng = np.random.default_rng(seed)
     A = torch.from_numpy(rng.standard_normal((n, m))).cuda().to(torch.float32).to(dtype)
