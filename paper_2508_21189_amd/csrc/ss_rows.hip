@@ -77,12 +77,14 @@ struct PlanArgs {
   uint32_t k0, k1;
   unsigned char* out;  // [tiles][zeta] records of rec_bytes
   int rec_bytes, lst_off;
+  int rshift;          // list entries carry row << rshift
 };
 
 // Record of (tile, block t): u16 off[nb + 1] (bucket s holds list entries
-// [off[s], off[s+1])), then at lst_off u16 lst[R]: the tile's rows sorted by
-// bucket, stable, each entry row << 2 | first << 1 | negative, where `first`
-// marks the first row of its bucket.
+// [off[s], off[s+1])), then at lst_off u32 lst[R]: the tile's rows sorted by
+// bucket, stable, each entry (row << rshift) | negative << 31. The row kernel
+// uses rshift = log2(row bytes / 8), so (entry << 3) is the row's LDS byte
+// offset in the tile (the sign bit shifts out); the narrow kernel uses 0.
 __global__ void __launch_bounds__(1024) ss_plan_kernel(PlanArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -148,7 +150,7 @@ __global__ void __launch_bounds__(1024) ss_plan_kernel(PlanArgs a) {
     }
     unsigned char* rec = a.out + (tile * zeta + t) * (int64_t)a.rec_bytes;
     uint16_t* gof = (uint16_t*)rec;
-    uint16_t* glst = (uint16_t*)(rec + a.lst_off);
+    uint32_t* glst = (uint32_t*)(rec + a.lst_off);
     uint32_t run = inc - loc;
     for (int k = 0; k < per; ++k) {
       if (sb + k < nb) {
@@ -165,7 +167,7 @@ __global__ void __launch_bounds__(1024) ss_plan_kernel(PlanArgs a) {
       if (r < rv) {
         const uint32_t code = cd[r];
         const uint32_t rkr = rk[r];
-        glst[cnt[code >> 1] + rkr] = (uint16_t)(((uint32_t)r << 2) | ((rkr == 0u) << 1) | (code & 1u));
+        glst[cnt[code >> 1] + rkr] = ((uint32_t)r << a.rshift) | ((code & 1u) << 31);
       }
     }
   }
@@ -202,34 +204,32 @@ struct InType<uint16_t> {  // bf16
   using acc = float;
 };
 
-// acc += (+-1) * tile value. An entry carries the LDS address of a row
-// (bits 0..30; a multiple of the 64-column row size, so the lane's column
-// offset `base` can be OR-ed in) and the sign (bit 31). The address is one
-// v_and_or; the +-1.0 multiplier is another (masks live in VGPRs).
+// acc += (+-1) * tile value for a list entry e: the row's LDS address is
+// (e << 3) + base, base = buffer address + lane * element size (one
+// v_lshl_add); the sign is applied by flipping the value's sign bit (one
+// v_xor), and the add rounds once, exactly like acc + (+-v).
 typedef __attribute__((address_space(3))) const unsigned char* lds_cptr;
 
 template <typename Tin>
-__device__ inline void fma_entry(typename InType<Tin>::acc& acc, uint32_t base, uint32_t e, uint32_t vmask,
-                                 uint32_t vsgn, uint32_t vone);
+__device__ inline typename InType<Tin>::acc lds_val(uint32_t addr);
 template <>
-__device__ inline void fma_entry<double>(double& acc, uint32_t base, uint32_t e, uint32_t vmask, uint32_t vsgn,
-                                         uint32_t vone) {
-  const double v = *(const __attribute__((address_space(3))) double*)(lds_cptr)(uintptr_t)((e & vmask) | base);
-  const uint64_t sg = (uint64_t)((e & vsgn) | vone) << 32;
-  acc = __builtin_fma(__builtin_bit_cast(double, sg), v, acc);
+__device__ inline double lds_val<double>(uint32_t addr) {
+  return *(const __attribute__((address_space(3))) double*)(lds_cptr)(uintptr_t)addr;
 }
 template <>
-__device__ inline void fma_entry<float>(float& acc, uint32_t base, uint32_t e, uint32_t vmask, uint32_t vsgn,
-                                        uint32_t vone) {
-  const float v = *(const __attribute__((address_space(3))) float*)(lds_cptr)(uintptr_t)((e & vmask) | base);
-  acc = __builtin_fmaf(__builtin_bit_cast(float, (e & vsgn) | vone), v, acc);
+__device__ inline float lds_val<float>(uint32_t addr) {
+  return *(const __attribute__((address_space(3))) float*)(lds_cptr)(uintptr_t)addr;
 }
 template <>
-__device__ inline void fma_entry<uint16_t>(float& acc, uint32_t base, uint32_t e, uint32_t vmask, uint32_t vsgn,
-                                           uint32_t vone) {
-  const uint16_t h =
-      *(const __attribute__((address_space(3))) uint16_t*)(lds_cptr)(uintptr_t)((e & vmask) | base);
-  acc = __builtin_fmaf(__builtin_bit_cast(float, (e & vsgn) | vone), bf16_to_f32(h), acc);
+__device__ inline float lds_val<uint16_t>(uint32_t addr) {
+  return bf16_to_f32(*(const __attribute__((address_space(3))) uint16_t*)(lds_cptr)(uintptr_t)addr);
+}
+// (+-1) * v for a list entry e: flip the sign bit of v with bit 31 of e.
+__device__ inline double flip(double v, uint32_t e) {
+  return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) ^ ((uint64_t)(e & 0x80000000u) << 32));
+}
+__device__ inline float flip(float v, uint32_t e) {
+  return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) ^ (e & 0x80000000u));
 }
 
 template <typename Tin, int JB, int LB>
@@ -321,50 +321,59 @@ __global__ void __launch_bounds__(1024) ss_rows_kernel(RowsArgs a) {
       asm volatile("" : "+s"(sc));
       const unsigned char* pl = smem + buf * a.buf_stride + a.off_plan + tl * a.rec_bytes;
       const uint16_t* of = (const uint16_t*)pl;
-      const uint16_t* lst = (const uint16_t*)(pl + a.lst_off);
-      const uint32_t bufaddr = lds_addr_of(smem + buf * a.buf_stride);
-      const uint32_t zaddr = lds_addr_of(smem + buf * a.buf_stride + a.off_zero);
-      const uint32_t base = (uint32_t)(lane * ES);
-      uint32_t vmask = 0x7fffffffu, vsgn = 0x80000000u;
-      uint32_t vone = sizeof(Tacc) == 8 ? 0x3FF00000u : 0x3F800000u;
-      asm volatile("" : "+v"(vmask), "+v"(vsgn), "+v"(vone));
-      auto entry = [&](uint32_t v) { return (bufaddr + (v >> 2) * ROWB) | (v << 31); };
+      const uint32_t* lst = (const uint32_t*)(pl + a.lst_off);
+      uint32_t base = lds_addr_of(smem + buf * a.buf_stride) + (uint32_t)(lane * ES);
+      asm volatile("" : "+v"(base));  // one register: keeps the address to one v_lshl_add
+      const uint32_t zentry = (uint32_t)a.off_zero >> 3;
       uint32_t kbeg = 0, kcnt = 0;
       if (lane < sc) {
         kbeg = of[s_begin + lane];
         kcnt = (uint32_t)of[s_begin + lane + 1] - kbeg;
       }
-      const uint32_t e0 = kcnt >= 1 ? entry(lst[kbeg]) : zaddr;
+      const uint32_t e0 = kcnt >= 1 ? lst[kbeg] : zentry;
       // first rows of all buckets: unrolled and branch-free (lanes past the
-      // wave's range, like empty buckets, point at the zero row)
-      // (groups of four: the loads of a group overlap; the scheduling
-      // barrier keeps the compiler from hoisting every load and spilling)
+      // wave's range, like empty buckets, point at the zero row), GB loads
+      // in flight before their adds (GB bounded by the register budget)
+      constexpr int GB = 8;
 #pragma unroll
-      for (int j = 0; j < JB; ++j) {
-        fma_entry<Tin>(acc[j], base, (uint32_t)__builtin_amdgcn_readlane((int)e0, j), vmask, vsgn, vone);
-        asm volatile("" : "+v"(acc[j]));  // the add happens here, not sunk into the code below
-        if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      for (int g = 0; g < JB; g += GB) {
+        Tacc v[GB];
+        uint32_t ev[GB];
+#pragma unroll
+        for (int u = 0; u < GB; ++u) {
+          if (g + u < JB) {
+            ev[u] = (uint32_t)__builtin_amdgcn_readlane((int)e0, g + u);
+            v[u] = lds_val<Tin>((ev[u] << 3) + base);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < GB; ++u)
+          if (g + u < JB) acc[g + u] += flip(v[u], ev[u]);
+        // the adds happen here, not sunk into later code
+#pragma unroll
+        for (int u = 0; u < GB; ++u)
+          if (g + u < JB) asm volatile("" : "+v"(acc[g + u]));
+        __builtin_amdgcn_sched_barrier(0);
       }
-      __builtin_amdgcn_sched_barrier(0);
 
       // further rows: the remaining list entries of each bucket with two or
-      // more rows, two rows at a time (one uniform test per bucket)
+      // more rows, two at a time (an odd tail pairs with the zero row)
       const uint64_t m2 = __ballot(kcnt >= 2);
 #pragma unroll
       for (int j = 0; j < JB; ++j) {
         if ((m2 >> j) & 1ull) {
-          const int kb = __builtin_amdgcn_readlane((int)kbeg, j) + 1;
-          const int ke = kb - 1 + __builtin_amdgcn_readlane((int)kcnt, j);
-          int k = kb;
-          for (; k + 1 < ke; k += 2) {
-            const uint32_t va = (uint32_t)__builtin_amdgcn_readfirstlane((int)lst[k]);
-            const uint32_t vb = (uint32_t)__builtin_amdgcn_readfirstlane((int)lst[k + 1]);
-            fma_entry<Tin>(acc[j], base, entry(va), vmask, vsgn, vone);
-            fma_entry<Tin>(acc[j], base, entry(vb), vmask, vsgn, vone);
+          const uint32_t kb = (uint32_t)__builtin_amdgcn_readlane((int)kbeg, j);
+          const uint32_t ke = kb + (uint32_t)__builtin_amdgcn_readlane((int)kcnt, j);
+          for (uint32_t k = kb + 1; k < ke; k += 2) {
+            // lst[k + 1] always exists: records keep one spare slot
+            const uint32_t ea = lst[k];
+            const uint32_t eb_raw = lst[k + 1];
+            const uint32_t eb = k + 1 < ke ? eb_raw : zentry;
+            const Tacc va = lds_val<Tin>((ea << 3) + base);
+            const Tacc vb = lds_val<Tin>((eb << 3) + base);
+            acc[j] += flip(va, ea);
+            acc[j] += flip(vb, eb);
           }
-          if (k < ke)
-            fma_entry<Tin>(acc[j], base, entry((uint32_t)__builtin_amdgcn_readfirstlane((int)lst[k])), vmask, vsgn,
-                           vone);
         }
       }
     }
@@ -438,13 +447,13 @@ __global__ void __launch_bounds__(1024) ss_narrow_kernel(NarrowArgs a) {
         const int t = (int)(j / a.nb), s = (int)(j - (int64_t)t * a.nb);
         const unsigned char* rec = pl + t * a.rec_bytes;
         const uint16_t* of = (const uint16_t*)rec;
-        const uint16_t* lst = (const uint16_t*)(rec + a.lst_off);
+        const uint32_t* lst = (const uint32_t*)(rec + a.lst_off);
         const int kb = of[s], ke = of[s + 1];
         for (int k = kb; k < ke; ++k) {
           const uint32_t e = lst[k];
-          const Tacc* vr = vals + (e >> 2) * MV;
+          const Tacc* vr = vals + (e & 0x7fffffffu) * MV;
 #pragma unroll
-          for (int c = 0; c < MV; ++c) acc[q][c] += (e & 1u) ? -vr[c] : vr[c];
+          for (int c = 0; c < MV; ++c) acc[q][c] += (e >> 31) ? -vr[c] : vr[c];
         }
       }
     }
@@ -532,10 +541,11 @@ static int env_int(const char* name, int dflt) {
   return v ? std::atoi(v) : dflt;
 }
 
-// Plan record of one (tile, block): u16 offsets [nb + 1], then u16 list [R].
+// Plan record of one (tile, block): u16 offsets [nb + 1], then u32 list [R]
+// and one spare slot (the row kernel reads entries in pairs).
 static void plan_record(int R, int64_t nb, int* rec_bytes, int* lst_off) {
   *lst_off = (int)align16((size_t)(nb + 1) * 2);
-  *rec_bytes = (int)align16((size_t)*lst_off + (size_t)R * 2);
+  *rec_bytes = (int)align16((size_t)*lst_off + (size_t)(R + 1) * 4);
 }
 
 // LDS layout of the sketch kernel. Per buffer (x2): R tile rows, one zero
@@ -681,7 +691,7 @@ int plan_rows(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_
   return SK_OK;
 }
 
-static int launch_plan(const sk_sketch* S, const RowsPlan& p, void* plan, hipStream_t st) {
+static int launch_plan(const sk_sketch* S, const RowsPlan& p, void* plan, int rshift, hipStream_t st) {
   PlanArgs a;
   a.n = S->n;
   a.R = p.R;
@@ -695,6 +705,7 @@ static int launch_plan(const sk_sketch* S, const RowsPlan& p, void* plan, hipStr
   a.out = (unsigned char*)plan;
   a.rec_bytes = p.rec_bytes;
   a.lst_off = p.lst_off;
+  a.rshift = rshift;
   const int threads = 64 * std::min(16, S->zeta);
   const size_t lds = plan_lds(p.R, S->zeta, S->nb);
   SK_HIP(hipFuncSetAttribute((const void*)ss_plan_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -814,7 +825,10 @@ int launch_rows_apply(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64
                       int dtype_out, void* SA, int64_t ldsa, void* ws, hipStream_t st) {
   void* P = ws;
   void* plan = (unsigned char*)ws + p.partial_bytes;
-  int rc = launch_plan(S, p, plan, st);
+  // wide kernel: entry << 3 is the row's byte offset in the tile (rows of 64 elements)
+  int rshift = 0;
+  if (!p.narrow) rshift = dtype_in == SK_F64 ? 6 : (dtype_in == SK_F32 ? 5 : 4);
+  int rc = launch_plan(S, p, plan, rshift, st);
   if (rc != SK_OK) return rc;
   if (p.narrow) {
     if (dtype_in == SK_F64)
