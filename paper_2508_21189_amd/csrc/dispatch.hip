@@ -1,5 +1,6 @@
 // Sketch-kind dispatch for sketch_apply / sketch_apply_T, plus small helpers.
 #include "sk_drivers.hpp"
+#include "sk_gauss.hpp"
 
 #include <algorithm>
 
@@ -65,6 +66,8 @@ int apply_workspace(const sk_sketch* S, int op, int dtype_in, int64_t m, size_t*
       p.plan_bytes = (size_t)((S->n + 15) / 16 + 1) * S->zeta * (2 * (S->nb + 1) + 64);
     }
     *bytes = p.partial_bytes + p.plan_bytes;
+  } else if (op == 0 && S->kind == SK_GAUSSIAN) {
+    *bytes = gauss_workspace(S, (int)m);
   }
   return SK_OK;
 }
@@ -101,6 +104,24 @@ int apply_dispatch(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t
         if (rc != SK_OK) return rc;
       }
       return launch_rows_apply(S, p, dtype_in, m, A, lda, dtype_out, SA, ldsa, w, st);
+    }
+    case SK_GAUSSIAN: {
+      if (dtype_in != SK_F64 || dtype_out != SK_F64) {
+        set_error("sketch_apply: the Gaussian sketch takes and returns F64");
+        return SK_E_NOTSUP;
+      }
+      const size_t need = gauss_workspace(S, (int)m);
+      void* w = ws;
+      if (w) {
+        if (ws_bytes < need) {
+          set_error("sketch_apply: workspace too small (see sketch_workspace_size)");
+          return SK_E_INVAL;
+        }
+      } else {
+        int rc = handle_workspace(S, need, &w);
+        if (rc != SK_OK) return rc;
+      }
+      return launch_gauss_rows(S, m, (const double*)A, lda, nullptr, (double*)SA, ldsa, nullptr, w, need, st);
     }
     default:
       set_error("sketch_apply: this sketch kind is not available yet");

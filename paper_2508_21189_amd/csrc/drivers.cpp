@@ -10,6 +10,7 @@
 
 #include "sk_dense.hpp"
 #include "sk_drivers.hpp"
+#include "sk_gauss.hpp"
 #include "sk_lsqr.hpp"
 
 namespace sk {
@@ -90,8 +91,16 @@ struct SketchBufs {
 int sketch_bufs(Carver& cv, const sk_sketch* S, int k, int dts, const void* As, int64_t ldas, const double* b,
                 SketchBufs* B) {
   size_t wa = 0, wb = 0;
-  SK_TRY(apply_workspace_for(S, dts, k, As, ldas, &wa));
-  SK_TRY(apply_workspace_for(S, SK_F64, 1, b, 1, &wb));
+  if (S->kind == SK_GAUSSIAN) {
+    if (dts != SK_F64) {
+      set_error("the Gaussian sketch reads F64 only");
+      return SK_E_NOTSUP;
+    }
+    wa = gauss_workspace(S, k + 1);  // one pass over [A | b]
+  } else {
+    SK_TRY(apply_workspace_for(S, dts, k, As, ldas, &wa));
+    SK_TRY(apply_workspace_for(S, SK_F64, 1, b, 1, &wb));
+  }
   const int64_t d = S->d;
   B->SA = cv.take<double>((size_t)d * k);
   B->Sb = cv.take<double>((size_t)d);
@@ -110,8 +119,12 @@ int sketch_bufs(Carver& cv, const sk_sketch* S, int k, int dts, const void* As, 
 int sketch_and_factor(sk_sketch* S, int k, int dts, const void* As, int64_t ldas, const double* b, const SketchBufs& B,
                       Phases& ph, hipStream_t st) {
   const int64_t d = S->d;
-  SK_TRY(apply_dispatch(S, dts, k, As, ldas, SK_F64, B.SA, k, B.aws, B.aws_bytes, st));
-  SK_TRY(apply_dispatch(S, SK_F64, 1, b, 1, SK_F64, B.Sb, 1, B.aws, B.aws_bytes, st));
+  if (S->kind == SK_GAUSSIAN) {
+    SK_TRY(launch_gauss_rows(S, k, (const double*)As, ldas, b, B.SA, k, B.Sb, B.aws, B.aws_bytes, st));
+  } else {
+    SK_TRY(apply_dispatch(S, dts, k, As, ldas, SK_F64, B.SA, k, B.aws, B.aws_bytes, st));
+    SK_TRY(apply_dispatch(S, SK_F64, 1, b, 1, SK_F64, B.Sb, 1, B.aws, B.aws_bytes, st));
+  }
   SK_TRY(ph.mark());
   SK_TRY(launch_to_columns(B.SA, k, B.Sb, d, k, B.W, d, st));
   SK_TRY(qr_columns(B.W, d, d, k, 1, B.tau, B.Tbuf, st));
