@@ -1,6 +1,7 @@
 // Sketch-kind dispatch for sketch_apply / sketch_apply_T, plus small helpers.
 #include "sk_drivers.hpp"
 #include "sk_gauss.hpp"
+#include "sk_srtt.hpp"
 
 #include <algorithm>
 
@@ -68,6 +69,8 @@ int apply_workspace(const sk_sketch* S, int op, int dtype_in, int64_t m, size_t*
     *bytes = p.partial_bytes + p.plan_bytes;
   } else if (op == 0 && S->kind == SK_GAUSSIAN) {
     *bytes = gauss_workspace(S, (int)m);
+  } else if (op == 0 && S->kind == SK_SRTT) {
+    *bytes = srtt_workspace(S, (int)m);
   }
   return SK_OK;
 }
@@ -122,6 +125,24 @@ int apply_dispatch(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t
         if (rc != SK_OK) return rc;
       }
       return launch_gauss_rows(S, m, (const double*)A, lda, nullptr, (double*)SA, ldsa, nullptr, w, need, st);
+    }
+    case SK_SRTT: {
+      if (dtype_in != SK_F64 || dtype_out != SK_F64) {
+        set_error("sketch_apply: the SRTT sketch takes and returns F64");
+        return SK_E_NOTSUP;
+      }
+      const size_t need = srtt_workspace(S, (int)m);
+      void* w = ws;
+      if (w) {
+        if (ws_bytes < need) {
+          set_error("sketch_apply: workspace too small (see sketch_workspace_size)");
+          return SK_E_INVAL;
+        }
+      } else {
+        int rc = handle_workspace(S, need, &w);
+        if (rc != SK_OK) return rc;
+      }
+      return launch_srtt_rows(S, m, (const double*)A, lda, nullptr, (double*)SA, ldsa, nullptr, w, need, st);
     }
     default:
       set_error("sketch_apply: this sketch kind is not available yet");

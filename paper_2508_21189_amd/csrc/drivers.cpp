@@ -12,6 +12,7 @@
 #include "sk_drivers.hpp"
 #include "sk_gauss.hpp"
 #include "sk_lsqr.hpp"
+#include "sk_srtt.hpp"
 
 namespace sk {
 
@@ -91,12 +92,13 @@ struct SketchBufs {
 int sketch_bufs(Carver& cv, const sk_sketch* S, int k, int dts, const void* As, int64_t ldas, const double* b,
                 SketchBufs* B) {
   size_t wa = 0, wb = 0;
-  if (S->kind == SK_GAUSSIAN) {
+  if (S->kind == SK_GAUSSIAN || S->kind == SK_SRTT) {
     if (dts != SK_F64) {
-      set_error("the Gaussian sketch reads F64 only");
+      set_error("the Gaussian and SRTT sketches read F64 only");
       return SK_E_NOTSUP;
     }
-    wa = gauss_workspace(S, k + 1);  // one pass over [A | b]
+    // one pass over [A | b]
+    wa = S->kind == SK_GAUSSIAN ? gauss_workspace(S, k + 1) : srtt_workspace(S, k + 1);
   } else {
     SK_TRY(apply_workspace_for(S, dts, k, As, ldas, &wa));
     SK_TRY(apply_workspace_for(S, SK_F64, 1, b, 1, &wb));
@@ -121,6 +123,8 @@ int sketch_and_factor(sk_sketch* S, int k, int dts, const void* As, int64_t ldas
   const int64_t d = S->d;
   if (S->kind == SK_GAUSSIAN) {
     SK_TRY(launch_gauss_rows(S, k, (const double*)As, ldas, b, B.SA, k, B.Sb, B.aws, B.aws_bytes, st));
+  } else if (S->kind == SK_SRTT) {
+    SK_TRY(launch_srtt_rows(S, k, (const double*)As, ldas, b, B.SA, k, B.Sb, B.aws, B.aws_bytes, st));
   } else {
     SK_TRY(apply_dispatch(S, dts, k, As, ldas, SK_F64, B.SA, k, B.aws, B.aws_bytes, st));
     SK_TRY(apply_dispatch(S, SK_F64, 1, b, 1, SK_F64, B.Sb, 1, B.aws, B.aws_bytes, st));
