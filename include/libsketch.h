@@ -198,6 +198,39 @@ int lstsq_sketch_precond(sketch_t S, int64_t m, const double* A, int64_t lda, in
 int lstsq_residual(sketch_t S, int64_t m, const double* A, int64_t lda, const double* b, const double* x,
                    double* resnorm, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Randomized SVD (Alg. 1).
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+  double t_sketch_ms;  /* Y = A S^T */
+  double t_orth_ms;    /* Q = orth(Y) */
+  double t_project_ms; /* B = Q^T A */
+  double t_svd_ms;     /* SVD of B and U = Q Uh */
+  double t_total_ms;   /* device time of the whole call */
+  int jacobi_sweeps;   /* sweeps of the Jacobi SVD of the k x k factor */
+} sk_rsvd_info;
+
+/*
+ * Rank-k approximation A ~ U diag(sigma) Vt from the sketch Y = A S^T, with
+ * k = d rows of S and A rows x n (n = the sketch's n), row-major, dtype
+ * SK_F32 or SK_F64 (lda >= n). Steps, following Alg. 1 with no
+ * oversampling and no power iteration:
+ *   Y = A S^T (the handle's kind; accumulated in F32 for F32 input, stored F64);
+ *   Q = orth(Y): shifted Cholesky QR, three passes, F64 (a reading: the paper
+ *   leaves orth() open);
+ *   B = Q^T A: one GEMM, F32 for F32 input (Q rounded to F32), else F64;
+ *   B = Uh diag(sigma) V^T via Cholesky QR of B^T and a one-sided Jacobi SVD
+ *   of the k x k triangular factor, F64; U = Q Uh.
+ * Outputs (device, F64): U rows x k row-major (ldu >= k; may be NULL), sigma
+ * (k, descending), Vt k x n row-major (ldvt >= n; may be NULL).
+ * Needs k <= min(rows, n) and k <= 4096. Synchronizes `stream`. Returns
+ * SK_W_RANKDEF if a Cholesky pivot was not positive (Y or B numerically rank
+ * deficient; outputs are then unreliable). info may be NULL.
+ */
+int rsvd(sketch_t S, int dtype, int64_t rows, const void* A, int64_t lda, double* U, int64_t ldu, double* sigma,
+         double* Vt, int64_t ldvt, sk_rsvd_info* info, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

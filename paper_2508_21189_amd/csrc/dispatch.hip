@@ -71,6 +71,8 @@ int apply_workspace(const sk_sketch* S, int op, int dtype_in, int64_t m, size_t*
     *bytes = gauss_workspace(S, (int)m);
   } else if (op == 0 && S->kind == SK_SRTT) {
     *bytes = srtt_workspace(S, (int)m);
+  } else if (op == 1 && S->kind == SK_SPARSESTACK) {
+    return cols_workspace(S, dtype_in, bytes);
   }
   return SK_OK;
 }
@@ -152,9 +154,23 @@ int apply_dispatch(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t
 
 int apply_T_dispatch(sk_sketch* S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out, void* Y,
                      int64_t ldy, void* ws, size_t ws_bytes, hipStream_t st) {
-  (void)ws;
-  (void)ws_bytes;
   if (S->kind == SK_IDENTITY_TEST) return launch_convert(dtype_in, A, lda, dtype_out, Y, ldy, rows, S->n, st);
+  if (S->kind == SK_SPARSESTACK) {
+    size_t need = 0;
+    int rc = cols_workspace(S, dtype_in, &need);
+    if (rc != SK_OK) return rc;
+    void* w = ws;
+    if (w) {
+      if (ws_bytes < need) {
+        set_error("sketch_apply_T: workspace too small (see sketch_workspace_size)");
+        return SK_E_INVAL;
+      }
+    } else {
+      rc = handle_workspace(S, need, &w);
+      if (rc != SK_OK) return rc;
+    }
+    return launch_cols_apply(S, dtype_in, rows, A, lda, dtype_out, Y, ldy, w, need, st);
+  }
   set_error("sketch_apply_T: this sketch kind is not available yet");
   return SK_E_NOTSUP;
 }

@@ -11,6 +11,7 @@
 #include "sk_dense.hpp"
 #include "sk_drivers.hpp"
 #include "sk_gauss.hpp"
+#include "sk_lowrank.hpp"
 #include "sk_lsqr.hpp"
 #include "sk_srtt.hpp"
 
@@ -141,6 +142,7 @@ bool dtype_ok(int dt) { return dt == SK_F64 || dt == SK_F32 || dt == SK_BF16; }
 }  // namespace
 
 void drivers_release(sk_sketch* S) {
+  blas_release(S);
   if (S->dws) (void)hipFree(S->dws);
   if (S->h_pinned) (void)hipHostFree(S->h_pinned);
   S->dws = nullptr;

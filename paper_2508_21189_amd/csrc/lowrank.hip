@@ -1,0 +1,343 @@
+// Dense FP64 kernels of the randomized SVD (Alg. 1):
+//   * blocked right-looking Cholesky G = R^T R (upper R, row-major, in
+//     place) for the Cholesky-QR orthonormalization of the tall sketch:
+//     per 32-column panel one workgroup factors the diagonal block in LDS and
+//     inverts it, a column-parallel kernel forms the panel's block row, and a
+//     tiled kernel applies the rank-32 update to the trailing upper triangle;
+//   * one-sided (Hestenes) Jacobi SVD of a k x k matrix with one workgroup
+//     per column pair: each launch is one round of the round-robin ordering
+//     (k/2 disjoint pairs), so a sweep is k - 1 launches and every pair of a
+//     round runs on its own CU;
+//   * small helpers (trace-based shift, transposes, zeroing).
+#include "sk_lowrank.hpp"
+
+#include <algorithm>
+
+namespace sk {
+
+constexpr int kCb = 32;  // Cholesky panel width
+
+__device__ inline double wg_reduce_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0;
+  for (int w = 0; w < nw; ++w) s += red[w];
+  return s;
+}
+
+// G[i][i] += shift, shift = c * trace(G) (the shifted first pass of
+// Cholesky QR); one workgroup.
+__global__ void __launch_bounds__(1024) add_trace_shift_kernel(double* __restrict__ G, int k, double c) {
+  __shared__ double red[16];
+  double t = 0;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) t += G[(int64_t)i * k + i];
+  const double shift = c * wg_reduce_sum(t, red);
+  for (int i = threadIdx.x; i < k; i += blockDim.x) G[(int64_t)i * k + i] += shift;
+}
+
+// Factor the diagonal block [j0, j0 + b) in LDS; write R_dd (upper) back into
+// G and its inverse into Dinv (b x b, stride kCb). *fail = 1 on a
+// non-positive pivot.
+__global__ void __launch_bounds__(256) chol_diag_kernel(double* __restrict__ G, int k, int j0, int b,
+                                                        double* __restrict__ Dinv, int* __restrict__ fail) {
+  __shared__ double L[kCb][kCb + 1];
+  __shared__ double X[kCb][kCb + 1];
+  __shared__ double piv;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < b * b; idx += blockDim.x) {
+    const int r = idx / b, c = idx - r * b;
+    L[r][c] = G[(int64_t)(j0 + r) * k + j0 + c];
+  }
+  __syncthreads();
+  for (int jj = 0; jj < b; ++jj) {
+    if (tid == 0) {
+      const double p = L[jj][jj];
+      if (!(p > 0.0)) *fail = 1;
+      piv = p > 0.0 ? sqrt(p) : 1.0;
+    }
+    __syncthreads();
+    const double d = piv;
+    if (tid >= jj && tid < b) L[jj][tid] = (tid == jj) ? d : L[jj][tid] / d;
+    __syncthreads();
+    // trailing update of the block: L[i][c] -= L[jj][i] * L[jj][c], jj < i <= c
+    for (int idx = tid; idx < b * b; idx += blockDim.x) {
+      const int i = idx / b, c = idx - i * b;
+      if (i > jj && c >= i) L[i][c] -= L[jj][i] * L[jj][c];
+    }
+    __syncthreads();
+  }
+  // inverse of the upper-triangular R_dd, column by column (thread = column)
+  if (tid < b) {
+    const int j = tid;
+    for (int i = 0; i < b; ++i) X[i][j] = 0.0;
+    X[j][j] = 1.0 / L[j][j];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0;
+      for (int l = i + 1; l <= j; ++l) s += L[i][l] * X[l][j];
+      X[i][j] = -s / L[i][i];
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < b * b; idx += blockDim.x) {
+    const int r = idx / b, c = idx - r * b;
+    G[(int64_t)(j0 + r) * k + j0 + c] = c >= r ? L[r][c] : 0.0;
+    Dinv[r * kCb + c] = X[r][c];
+  }
+}
+
+// Block row of the panel: R[j0 + l][c] = sum_{l' <= l} Dinv[l'][l] G[j0 + l'][c]
+// for c >= j0 + b (R_dd^T x = g). One thread per column c.
+__global__ void __launch_bounds__(256) chol_panel_kernel(double* __restrict__ G, int k, int j0, int b,
+                                                         const double* __restrict__ Dinv) {
+  __shared__ double D[kCb][kCb];
+  for (int idx = threadIdx.x; idx < b * kCb; idx += blockDim.x) D[idx / kCb][idx % kCb] = Dinv[idx];
+  __syncthreads();
+  const int c = j0 + b + blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k) return;
+  double g[kCb];
+#pragma unroll
+  for (int l = 0; l < kCb; ++l) g[l] = l < b ? G[(int64_t)(j0 + l) * k + c] : 0.0;
+#pragma unroll
+  for (int l = 0; l < kCb; ++l) {
+    if (l < b) {
+      double s = 0;
+#pragma unroll
+      for (int lp = 0; lp <= l; ++lp) s += D[lp][l] * g[lp];
+      G[(int64_t)(j0 + l) * k + c] = s;
+    }
+  }
+}
+
+// Trailing update G[i][c] -= sum_l R[j0+l][i] R[j0+l][c] for t0 <= i <= c < k,
+// t0 = j0 + b, in 32 x 32 tiles (only tiles on or above the diagonal).
+__global__ void __launch_bounds__(256) chol_trail_kernel(double* __restrict__ G, int k, int j0, int b) {
+  __shared__ double Ri[kCb][33], Rc[kCb][33];
+  const int t0 = j0 + b;
+  const int nt = (k - t0 + 31) / 32;
+  // blockIdx.x enumerates (ti, tc) with ti <= tc
+  int idx = blockIdx.x, ti = 0;
+  while (idx >= nt - ti) {
+    idx -= nt - ti;
+    ++ti;
+  }
+  const int tc = ti + idx;
+  const int i0 = t0 + 32 * ti, c0 = t0 + 32 * tc;
+  for (int e = threadIdx.x; e < b * 32; e += blockDim.x) {
+    const int l = e / 32, x = e - l * 32;
+    Ri[l][x] = i0 + x < k ? G[(int64_t)(j0 + l) * k + i0 + x] : 0.0;
+    Rc[l][x] = c0 + x < k ? G[(int64_t)(j0 + l) * k + c0 + x] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
+    const int x = e / 32, y = e - x * 32;
+    const int i = i0 + x, c = c0 + y;
+    if (i < k && c < k && c >= i) {
+      double s = 0;
+      for (int l = 0; l < b; ++l) s += Ri[l][x] * Rc[l][y];
+      G[(int64_t)i * k + c] -= s;
+    }
+  }
+}
+
+// Zero the strictly lower triangle (k x k row-major).
+__global__ void zero_lower_kernel(double* __restrict__ R, int k) {
+  const int64_t total = (int64_t)k * k;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / k, c = idx - i * k;
+    if (c < i) R[idx] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi SVD, one workgroup per column pair
+// ---------------------------------------------------------------------------
+// Uc, Vc: column-major working copies (column j at j * k).
+__global__ void jacobi_init_kernel(const double* __restrict__ M, int k, int input_colmajor, double* __restrict__ Uc,
+                                   double* __restrict__ Vc) {
+  const int64_t total = (int64_t)k * k;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t col = idx / k, row = idx - col * k;
+    Uc[idx] = input_colmajor ? M[idx] : M[row * k + col];
+    Vc[idx] = row == col ? 1.0 : 0.0;
+  }
+}
+
+__device__ inline void rr_pair_g(int kp, int r, int i, int* p, int* q) {
+  if (i == 0) {
+    *p = r;
+    *q = kp - 1;
+  } else {
+    const int m = kp - 1;
+    *p = (r + i) % m;
+    *q = ((r - i) % m + m) % m;
+  }
+}
+
+__global__ void __launch_bounds__(256) jacobi_round_kernel(double* __restrict__ Uc, double* __restrict__ Vc, int k,
+                                                           int r, double tol, int* __restrict__ rotated) {
+  __shared__ double red[3][4];
+  const int kp = k + (k & 1);
+  int p, q;
+  rr_pair_g(kp, r, blockIdx.x, &p, &q);
+  if (p >= k || q >= k) return;
+  double* up = Uc + (int64_t)p * k;
+  double* uq = Uc + (int64_t)q * k;
+  double a = 0, b = 0, g = 0;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    const double x = up[i], y = uq[i];
+    a += x * x;
+    b += y * y;
+    g += x * y;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+    g += __shfl_xor(g, o, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wave] = a;
+    red[1][wave] = b;
+    red[2][wave] = g;
+  }
+  __syncthreads();
+  a = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+  b = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+  g = ((red[2][0] + red[2][1]) + red[2][2]) + red[2][3];
+  if (!(fabs(g) > tol * sqrt(a * b)) || g == 0.0) return;
+  const double zeta = (b - a) / (2.0 * g);
+  const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+  double* vp = Vc + (int64_t)p * k;
+  double* vq = Vc + (int64_t)q * k;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    const double x = up[i], y = uq[i];
+    up[i] = c * x - sn * y;
+    uq[i] = sn * x + c * y;
+    const double xv = vp[i], yv = vq[i];
+    vp[i] = c * xv - sn * yv;
+    vq[i] = sn * xv + c * yv;
+  }
+  if (threadIdx.x == 0) *rotated = 1;
+}
+
+// s_j = ||u_j||, U = normalized columns; columns ranked by descending s
+// (ties by index); U, V written row-major k x k.
+__global__ void __launch_bounds__(1024) jacobi_finish_kernel(const double* __restrict__ Uc,
+                                                             const double* __restrict__ Vc, int k,
+                                                             double* __restrict__ U, double* __restrict__ s,
+                                                             double* __restrict__ V, double* __restrict__ sig) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  for (int j = wave; j < k; j += nw) {
+    const double* uj = Uc + (int64_t)j * k;
+    double a = 0;
+    for (int i = lane; i < k; i += 64) a += uj[i] * uj[i];
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if (lane == 0) sig[j] = sqrt(a);
+  }
+  __syncthreads();
+  for (int j = tid; j < k; j += blockDim.x) {
+    const double sj = sig[j];
+    int rank = 0;
+    for (int i = 0; i < k; ++i) rank += (sig[i] > sj) || (sig[i] == sj && i < j);
+    s[rank] = sj;
+    const double inv = sj > 0 ? 1.0 / sj : 0.0;
+    for (int row = 0; row < k; ++row) {
+      U[(int64_t)row * k + rank] = Uc[(int64_t)j * k + row] * inv;
+      V[(int64_t)row * k + rank] = Vc[(int64_t)j * k + row];
+    }
+  }
+}
+
+__global__ void set_int_kernel(int* __restrict__ p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+// Y[j][i] = X[i][j] for X r x c row-major.
+__global__ void transpose_kernel(const double* __restrict__ X, int64_t r, int64_t c, double* __restrict__ Y) {
+  const int64_t total = r * c;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / c, j = idx - i * c;
+    Y[j * r + i] = X[idx];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+static unsigned grid_for(int64_t total) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 8192));
+}
+
+int launch_cholesky_upper(double* G, int k, double shift_coef, double* Dinv, int* fail, hipStream_t st) {
+  if (shift_coef > 0) {
+    hipLaunchKernelGGL(add_trace_shift_kernel, dim3(1), dim3(1024), 0, st, G, k, shift_coef);
+    SK_HIP(hipGetLastError());
+  }
+  for (int j0 = 0; j0 < k; j0 += kCb) {
+    const int b = std::min(kCb, k - j0);
+    hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, st, G, k, j0, b, Dinv, fail);
+    const int rest = k - j0 - b;
+    if (rest > 0) {
+      hipLaunchKernelGGL(chol_panel_kernel, dim3((rest + 255) / 256), dim3(256), 0, st, G, k, j0, b,
+                         (const double*)Dinv);
+      const int nt = (rest + 31) / 32;
+      hipLaunchKernelGGL(chol_trail_kernel, dim3(nt * (nt + 1) / 2), dim3(256), 0, st, G, k, j0, b);
+    }
+    SK_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(zero_lower_kernel, dim3(grid_for((int64_t)k * k)), dim3(256), 0, st, G, k);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+int launch_set_int(int* p, int v, hipStream_t st) {
+  hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, st, p, v);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+int launch_transpose(const double* X, int64_t r, int64_t c, double* Y, hipStream_t st) {
+  hipLaunchKernelGGL(transpose_kernel, dim3(grid_for(r * c)), dim3(256), 0, st, X, r, c, Y);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+size_t jacobi_work_doubles(int k) { return (size_t)3 * k * k + k; }
+
+int jacobi_svd_rounds(const double* M, int k, int input_colmajor, double* U, double* s, double* V, double* work,
+                      int* flag, int* h_flag, int max_sweeps, int* sweeps, hipStream_t st) {
+  double* Uc = work;
+  double* Vc = work + (size_t)k * k;
+  double* sig = work + (size_t)2 * k * k;
+  hipLaunchKernelGGL(jacobi_init_kernel, dim3(grid_for((int64_t)k * k)), dim3(256), 0, st, M, k, input_colmajor, Uc,
+                     Vc);
+  SK_HIP(hipGetLastError());
+  const int kp = k + (k & 1);
+  int sw = 0;
+  for (; sw < max_sweeps; ++sw) {
+    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, st, flag, 0);
+    for (int r = 0; r < kp - 1; ++r)
+      hipLaunchKernelGGL(jacobi_round_kernel, dim3(kp / 2), dim3(256), 0, st, Uc, Vc, k, r, 1e-15, flag);
+    SK_HIP(hipGetLastError());
+    SK_HIP(hipMemcpyAsync(h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    SK_HIP(hipStreamSynchronize(st));
+    if (*h_flag == 0) {
+      ++sw;
+      break;
+    }
+  }
+  if (sweeps) *sweeps = sw;
+  hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(1024), 0, st, (const double*)Uc, (const double*)Vc, k, U, s,
+                     V, sig);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+}  // namespace sk

@@ -106,6 +106,7 @@ struct sk_sketch {
   void* dws = nullptr;
   size_t dws_bytes = 0;
   void* h_pinned = nullptr;
+  void* blas = nullptr;  // rocBLAS handle of the low-rank driver (created on first use)
   // optional timing of the dominant kernel of each call (sketch_timing)
   mutable bool timing = false;
   mutable std::vector<std::pair<hipEvent_t, hipEvent_t>> events;

@@ -34,6 +34,11 @@ int plan_rows(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_
 int launch_rows_apply(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64_t m, const void* A,
                       int64_t lda, int dtype_out, void* SA, int64_t ldsa, void* ws, hipStream_t st);
 
+// Column mode (Y = A S^T, A rows x n row-major): workspace bytes and launch.
+int cols_workspace(const sk_sketch* S, int dtype_in, size_t* bytes);
+int launch_cols_apply(const sk_sketch* S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out,
+                      void* Y, int64_t ldy, void* ws, size_t ws_bytes, hipStream_t st);
+
 int launch_pattern(const sk_sketch* S, int32_t* bucket, int8_t* sign, hipStream_t st);
 int launch_adjoint(const sk_sketch* S, int64_t m, const double* Y, int64_t ldy, double* Z, int64_t ldz,
                    hipStream_t st);

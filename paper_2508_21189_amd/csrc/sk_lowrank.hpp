@@ -1,0 +1,29 @@
+// Dense FP64 building blocks of the randomized SVD (lowrank.hip, blas.cpp).
+#pragma once
+#include "sk_common.hpp"
+
+namespace sk {
+
+// G (k x k row-major, symmetric; the upper triangle is read) := R, upper,
+// with G + shift I = R^T R and shift = shift_coef * trace(G) (no shift when
+// shift_coef <= 0). Dinv: 32 x 32 doubles of scratch. *fail (device) is set
+// to 1 on a non-positive pivot.
+int launch_cholesky_upper(double* G, int k, double shift_coef, double* Dinv, int* fail, hipStream_t st);
+int launch_set_int(int* p, int v, hipStream_t st);
+// Y (c x r) = X^T for X r x c row-major.
+int launch_transpose(const double* X, int64_t r, int64_t c, double* Y, hipStream_t st);
+// One-sided Jacobi SVD M = U diag(s) V^T (k x k; M row-major, or column-major
+// when input_colmajor), one launch per round of pairs; U, V row-major, s
+// descending. work: jacobi_work_doubles(k); flag: one device int; h_flag:
+// pinned host int. Synchronizes the stream once per sweep.
+size_t jacobi_work_doubles(int k);
+int jacobi_svd_rounds(const double* M, int k, int input_colmajor, double* U, double* s, double* V, double* work,
+                      int* flag, int* h_flag, int max_sweeps, int* sweeps, hipStream_t st);
+
+// Row-major GEMM on the handle's rocBLAS handle and stream:
+// C (M x N) = alpha op(A) op(B) + beta C; dtype SK_F64 or SK_F32.
+int gemm_rm(sk_sketch* S, int dtype, bool transA, bool transB, int64_t M, int64_t N, int64_t K, double alpha,
+            const void* A, int64_t lda, const void* B, int64_t ldb, double beta, void* C, int64_t ldc, hipStream_t st);
+void blas_release(sk_sketch* S);
+
+}  // namespace sk

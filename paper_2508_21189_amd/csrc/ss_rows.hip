@@ -691,10 +691,13 @@ int plan_rows(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_
   return SK_OK;
 }
 
-static int launch_plan(const sk_sketch* S, const RowsPlan& p, void* plan, int rshift, hipStream_t st) {
+// Bucket plans of every tile of R consecutive indices (rows of A in row mode,
+// columns of A in column mode).
+int launch_plan_generic(const sk_sketch* S, int R, int rec_bytes, int lst_off, int64_t n_tiles, void* plan,
+                        int rshift, hipStream_t st) {
   PlanArgs a;
   a.n = S->n;
-  a.R = p.R;
+  a.R = R;
   a.zeta = S->zeta;
   a.nb = (int)S->nb;
   int nbits = 0;
@@ -703,15 +706,19 @@ static int launch_plan(const sk_sketch* S, const RowsPlan& p, void* plan, int rs
   a.k0 = S->k0;
   a.k1 = S->k1;
   a.out = (unsigned char*)plan;
-  a.rec_bytes = p.rec_bytes;
-  a.lst_off = p.lst_off;
+  a.rec_bytes = rec_bytes;
+  a.lst_off = lst_off;
   a.rshift = rshift;
   const int threads = 64 * std::min(16, S->zeta);
-  const size_t lds = plan_lds(p.R, S->zeta, S->nb);
+  const size_t lds = plan_lds(R, S->zeta, S->nb);
   SK_HIP(hipFuncSetAttribute((const void*)ss_plan_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(ss_plan_kernel, dim3((unsigned)p.n_tiles), dim3(threads), lds, st, a);
+  hipLaunchKernelGGL(ss_plan_kernel, dim3((unsigned)n_tiles), dim3(threads), lds, st, a);
   SK_HIP(hipGetLastError());
   return SK_OK;
+}
+
+static int launch_plan(const sk_sketch* S, const RowsPlan& p, void* plan, int rshift, hipStream_t st) {
+  return launch_plan_generic(S, p.R, p.rec_bytes, p.lst_off, p.n_tiles, plan, rshift, st);
 }
 
 template <typename Tin, int JB, int LB>

@@ -84,6 +84,12 @@ class LsqrInfo(ctypes.Structure):
                 ("t_qr_ms", ctypes.c_double), ("t_lsqr_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
 
 
+class RsvdInfo(ctypes.Structure):
+    """sk_rsvd_info."""
+    _fields_ = [("t_sketch_ms", ctypes.c_double), ("t_orth_ms", ctypes.c_double), ("t_project_ms", ctypes.c_double),
+                ("t_svd_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double), ("jacobi_sweeps", ctypes.c_int)]
+
+
 def _as_dict(st):
     return {name: getattr(st, name) for name, _ in st._fields_}
 
@@ -93,6 +99,7 @@ _DRIVER_SIGS = {
     "lstsq_sketch_precond": [_vp, _i64, _vp, _i64, ctypes.c_int, _vp, _i64, _vp, _vp, ctypes.c_double, ctypes.c_int,
                              ctypes.c_int, ctypes.POINTER(LsqrInfo), _vp],
     "lstsq_residual": [_vp, _i64, _vp, _i64, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp],
+    "rsvd": [_vp, ctypes.c_int, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, ctypes.POINTER(RsvdInfo), _vp],
 }
 
 
@@ -235,3 +242,20 @@ class Sketch:
         check(load().lstsq_residual(self.h, A.shape[1], _ptr(A), A.stride(0), _ptr(b), _ptr(x), ctypes.byref(out),
                                     _stream(stream)))
         return out.value
+
+    # -- randomized SVD ----------------------------------------------------------
+    def rsvd(self, A, want_u=True, want_vt=True, stream=None):
+        """Alg. 1 with this sketch (k = d): returns (U, sigma, Vt, status, info dict)."""
+        assert A.is_cuda and A.dim() == 2 and A.shape[1] == self.n and A.stride(1) == 1
+        assert A.dtype in (torch.float32, torch.float64)
+        rows, k = A.shape[0], self.d
+        dev = A.device
+        U = torch.empty((rows, k), dtype=torch.float64, device=dev) if want_u else None
+        Vt = torch.empty((k, self.n), dtype=torch.float64, device=dev) if want_vt else None
+        sig = torch.empty(k, dtype=torch.float64, device=dev)
+        info = RsvdInfo()
+        rc = check(load().rsvd(self.h, _DT[A.dtype], rows, _ptr(A), A.stride(0),
+                               _ptr(U) if U is not None else None, k,
+                               _ptr(sig), _ptr(Vt) if Vt is not None else None, self.n,
+                               ctypes.byref(info), _stream(stream)))
+        return U, sig, Vt, rc, _as_dict(info)

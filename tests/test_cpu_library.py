@@ -61,7 +61,8 @@ def _header_struct_fields(name):
     return [(t.strip(), f.strip()) for t, f in re.findall(r"(int|double)\s+(\w+)\s*;", body)]
 
 
-@pytest.mark.parametrize("cname,pyname", [("sk_solve_info", "SolveInfo"), ("sk_lsqr_info", "LsqrInfo")])
+@pytest.mark.parametrize("cname,pyname", [("sk_solve_info", "SolveInfo"), ("sk_lsqr_info", "LsqrInfo"),
+                                           ("sk_rsvd_info", "RsvdInfo")])
 def test_info_structs_match_header(cname, pyname):
     import ctypes as ct
     from paper_2508_21189_amd import libsketch
@@ -80,3 +81,5 @@ def test_driver_null_handle_fails_cleanly():
     out = ctypes.c_double(0)
     assert lib.lstsq_residual(None, 4, None, 4, None, None, ctypes.byref(out), None) == libsketch.SK_E_INVAL
     assert "invalid" in libsketch.last_error()
+    sig = ctypes.c_void_p(0)
+    assert lib.rsvd(None, 1, 4, None, 4, None, 4, None, None, 4, None, None) == libsketch.SK_E_INVAL
