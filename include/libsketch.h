@@ -103,11 +103,18 @@ int sketch_apply(sketch_t S, int dtype_in, int layout, int64_t m, const void* A,
 /*
  * Y = A S^T (the paper's A Omega): A is rows x n row-major (lda >= n) of
  * dtype_in, Y is rows x d row-major (ldy >= d) of dtype_out.
+ *   SparseStack: any input type, F32 accumulation for F32/BF16, F64 for F64.
+ *   Gaussian: F64 or F32 input; G (d x n) is generated into the workspace and
+ *     Y = A G^T is one GEMM on the matrix cores (F32 GEMM for F32 input).
+ *   SRTT: one Walsh-Hadamard transform per row in LDS; needs
+ *     npad * element size <= 160 KB (npad <= 2^15 for F32/BF16, 2^14 for F64).
+ * Deterministic for SparseStack and SRTT; the Gaussian GEMM follows rocBLAS.
  */
 int sketch_apply_T(sketch_t S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out,
                    void* Y, int64_t ldy, void* ws, size_t ws_bytes, void* stream);
 
-/* Workspace bytes needed by sketch_apply (op 0) or sketch_apply_T (op 1). */
+/* Workspace bytes needed by sketch_apply (op 0, m = columns of A) or
+ * sketch_apply_T (op 1, m = rows of A). */
 int sketch_workspace_size(sketch_t S, int op, int dtype_in, int64_t m, size_t* bytes);
 
 /*

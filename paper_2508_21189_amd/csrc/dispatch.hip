@@ -73,6 +73,9 @@ int apply_workspace(const sk_sketch* S, int op, int dtype_in, int64_t m, size_t*
     *bytes = srtt_workspace(S, (int)m);
   } else if (op == 1 && S->kind == SK_SPARSESTACK) {
     return cols_workspace(S, dtype_in, bytes);
+  } else if (op == 1 && (S->kind == SK_GAUSSIAN || S->kind == SK_SRTT)) {
+    // m is the number of rows of A in this orientation; F64 output is the worst case
+    return cols_dense_workspace(S, dtype_in, SK_F64, m, bytes);
   }
   return SK_OK;
 }
@@ -170,6 +173,24 @@ int apply_T_dispatch(sk_sketch* S, int dtype_in, int64_t rows, const void* A, in
       if (rc != SK_OK) return rc;
     }
     return launch_cols_apply(S, dtype_in, rows, A, lda, dtype_out, Y, ldy, w, need, st);
+  }
+  if (S->kind == SK_GAUSSIAN || S->kind == SK_SRTT) {
+    size_t need = 0;
+    int rc = cols_dense_workspace(S, dtype_in, dtype_out, rows, &need);
+    if (rc != SK_OK) return rc;
+    void* w = ws;
+    if (need > 0) {
+      if (w) {
+        if (ws_bytes < need) {
+          set_error("sketch_apply_T: workspace too small (see sketch_workspace_size)");
+          return SK_E_INVAL;
+        }
+      } else {
+        rc = handle_workspace(S, need, &w);
+        if (rc != SK_OK) return rc;
+      }
+    }
+    return launch_cols_dense(S, dtype_in, rows, A, lda, dtype_out, Y, ldy, w, need, st);
   }
   set_error("sketch_apply_T: this sketch kind is not available yet");
   return SK_E_NOTSUP;

@@ -21,6 +21,11 @@ int apply_T_dispatch(sk_sketch* S, int dtype_in, int64_t rows, const void* A, in
 int launch_convert(int dtype_in, const void* in, int64_t ldi, int dtype_out, void* out, int64_t ldo, int64_t rows,
                    int64_t cols, hipStream_t st);
 
+// Column mode of the Gaussian and SRTT sketches (cols_dense.hip).
+int cols_dense_workspace(const sk_sketch* S, int dtype_in, int dtype_out, int64_t rows, size_t* bytes);
+int launch_cols_dense(sk_sketch* S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out, void* Y,
+                      int64_t ldy, void* ws, size_t ws_bytes, hipStream_t st);
+
 // Frees driver-owned device memory attached to a handle.
 void drivers_release(sk_sketch* S);
 

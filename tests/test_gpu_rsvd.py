@@ -102,3 +102,50 @@ def test_rsvd_f32(lib):
     err_gpu = np.linalg.norm(A64 - (U.cpu().numpy() * s) @ Vt.cpu().numpy(), 2)
     err_ref = lr.spectral_residual(A64, Q, iters=200)
     assert abs(err_gpu - err_ref) <= 1e-2 * err_ref
+
+
+@pytest.mark.parametrize("rows,n,d,seed", [(130, 777, 40, 1), (64, 4096, 512, 2)])
+def test_apply_T_gaussian(lib, rows, n, d, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((rows, n))
+    S = lib.Sketch("gaussian", d, n, 1, seed)
+    G = sk.gaussian_dense(n, d, seed)
+    ref = A @ G.T
+    got = S.apply_T(torch.from_numpy(A).cuda()).cpu().numpy()
+    absr = np.abs(A) @ np.abs(G).T
+    assert np.all(np.abs(got - ref) <= (n * 2.0 ** -53 + 1e-13) * absr)
+    A32 = torch.from_numpy(A).to(torch.float32)
+    got32 = S.apply_T(A32.cuda(), out_dtype=torch.float64).cpu().numpy()
+    ref32 = A32.double().numpy() @ G.astype(np.float32).astype(np.float64).T
+    assert np.all(np.abs(got32 - ref32) <= (n * 2.0 ** -24) * absr)
+
+
+@pytest.mark.parametrize("rows,n,d,seed", [(130, 777, 40, 1), (50, 16384, 512, 2), (33, 4096, 64, 3)])
+def test_apply_T_srtt(lib, rows, n, d, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((rows, n))
+    S = lib.Sketch("srtt", d, n, 1, seed)
+    ref = sk.srtt_apply(A.T, d, seed).T
+    p = int(np.ceil(np.log2(n)))
+    l1 = np.abs(A).sum(axis=1)[:, None] / np.sqrt(d)
+    got = S.apply_T(torch.from_numpy(A).cuda()).cpu().numpy()
+    assert np.all(np.abs(got - ref) <= (p + 2) * 2.0 ** -53 * l1)
+    A32 = torch.from_numpy(A).to(torch.float32)
+    ref32 = sk.srtt_apply(A32.double().numpy().T, d, seed).T
+    got32 = S.apply_T(A32.cuda(), out_dtype=torch.float64).cpu().numpy()
+    assert np.all(np.abs(got32 - ref32) <= (p + 2) * 2.0 ** -24 * l1)
+
+
+@pytest.mark.parametrize("kind", ["gaussian", "srtt"])
+def test_rsvd_comparison_sketches(lib, kind):
+    rows, cols, k = 1500, 1024, 64
+    A, _ = _decay(rows, cols, seed=3)
+    S = lib.Sketch(kind, k, cols, 1, 77)
+    U, s, Vt, rc, info = S.rsvd(torch.from_numpy(A).cuda())
+    assert rc == 0
+    Om = sk.dense(sk.KIND_GAUSSIAN if kind == "gaussian" else sk.KIND_SRTT, cols, k, 1, 77)
+    _, sr, _, Q = lr.rsvd_from_sketch(A, A @ Om.T)
+    s = s.cpu().numpy()
+    assert np.max(np.abs(s - sr) / sr) <= 1e-9
+    err_gpu = np.linalg.norm(A - (U.cpu().numpy() * s) @ Vt.cpu().numpy(), 2)
+    assert abs(err_gpu - lr.spectral_residual(A, Q, iters=200)) <= 1e-2 * err_gpu
