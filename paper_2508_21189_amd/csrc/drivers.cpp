@@ -332,7 +332,10 @@ int lstsq_residual(sketch_t S, int64_t m, const double* A, int64_t lda, const do
   carve(cv2);
   SK_HIP(hipMemcpyAsync(u, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
   SK_TRY(launch_fill(coef, 1, -1.0, st));
-  SK_TRY(launch_lsqr_pass(A, lda, n, k, x, coef, nullptr, u, part, st));
+  {
+    KernelTimer timer(S, st);
+    SK_TRY(launch_lsqr_pass(A, lda, n, k, x, coef, nullptr, u, part, st));
+  }
   double* hp = static_cast<double*>(S->h_pinned);
   SK_HIP(hipMemcpyAsync(hp, part + (size_t)groups * (k + 1) + k, sizeof(double), hipMemcpyDeviceToHost, st));
   SK_HIP(hipStreamSynchronize(st));

@@ -13,6 +13,7 @@
 #include "sk_lsqr.hpp"
 
 #include <algorithm>
+#include <cstdlib>
 
 namespace sk {
 
@@ -39,35 +40,55 @@ __global__ void __launch_bounds__(256) lsqr_pass_kernel(const double* __restrict
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
   const int64_t r1 = min(n, r0 + rows_per_wg);
   int64_t i = r0 + wave;
-  for (; i + 4 * (U - 1) < r1; i += 4 * U) {
-    double x[U][MPL], dt[U], uo[U];
+  // U rows per step (rows i, i+4, ...); the next step's rows are loaded
+  // before this step's reductions so that two steps of A are in flight.
+  auto load_rows = [&](int64_t i0, double (&xx)[U][MPL], double (&uu)[U]) {
 #pragma unroll
     for (int r = 0; r < U; ++r) {
-      const double* a = A + (i + 4 * r) * lda;
+      const double* a = A + (i0 + 4 * r) * lda;
 #pragma unroll
       for (int k = 0; k < MPL; ++k) {
         const int c = lane + 64 * k;
-        x[r][k] = c < m ? a[c] : 0.0;
+        xx[r][k] = c < m ? __builtin_nontemporal_load(a + c) : 0.0;
       }
-      uo[r] = u[i + 4 * r];
+      uu[r] = u[i0 + 4 * r];
     }
+  };
+  if (i + 4 * (U - 1) < r1) {
+    double x[U][MPL], uo[U];
+    load_rows(i, x, uo);
+    for (;;) {
+      const int64_t inext = i + 4 * U;
+      const bool more = inext + 4 * (U - 1) < r1;
+      double xn[U][MPL], un[U];
+      if (more) load_rows(inext, xn, un);
+      double dt[U];
 #pragma unroll
-    for (int r = 0; r < U; ++r) {
-      dt[r] = 0.0;
+      for (int r = 0; r < U; ++r) {
+        dt[r] = 0.0;
 #pragma unroll
-      for (int k = 0; k < MPL; ++k) dt[r] += x[r][k] * wl[k];
-    }
-    for (int o = 32; o > 0; o >>= 1) {
+        for (int k = 0; k < MPL; ++k) dt[r] += x[r][k] * wl[k];
+      }
+      for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
-      for (int r = 0; r < U; ++r) dt[r] += __shfl_xor(dt[r], o, 64);
-    }
+        for (int r = 0; r < U; ++r) dt[r] += __shfl_xor(dt[r], o, 64);
+      }
 #pragma unroll
-    for (int r = 0; r < U; ++r) {
-      const double p = dt[r] + coef * uo[r];
-      if (lane == 0) u[i + 4 * r] = p;
+      for (int r = 0; r < U; ++r) {
+        const double p = dt[r] + coef * uo[r];
+        if (lane == 0) u[i + 4 * r] = p;
 #pragma unroll
-      for (int k = 0; k < MPL; ++k) q[k] += x[r][k] * p;
-      pp += p * p;
+        for (int k = 0; k < MPL; ++k) q[k] += x[r][k] * p;
+        pp += p * p;
+      }
+      i = inext;
+      if (!more) break;
+#pragma unroll
+      for (int r = 0; r < U; ++r) {
+        uo[r] = un[r];
+#pragma unroll
+        for (int k = 0; k < MPL; ++k) x[r][k] = xn[r][k];
+      }
     }
   }
   for (; i < r1; i += 4) {
@@ -311,24 +332,38 @@ __global__ void rinv_vec_kernel(const double* __restrict__ Rinv, int k, const do
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-int lsqr_pass_groups(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 63) / 64)); }
+static int env_or(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return v ? std::atoi(v) : dflt;
+}
+
+int lsqr_pass_groups(int64_t n) {
+  static const int cap = env_or("SKETCH_LSQR_GROUPS", 1024);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(cap, (n + 63) / 64));
+}
 
 int launch_lsqr_pass(const double* A, int64_t lda, int64_t n, int m, const double* w, const double* coefp,
                      const int* donep, double* u, double* part, hipStream_t st) {
   const int groups = lsqr_pass_groups(n);
   const int64_t rows = (n + groups - 1) / groups;
   const int mpl = (m + 63) / 64;
-#define SK_PASS(MP)                                                                                              \
-  hipLaunchKernelGGL((lsqr_pass_kernel<MP, (MP <= 4 ? 4 : 2)>), dim3(groups), dim3(256), 0, st, A, lda, n, m, w,  \
-                     coefp, donep, u, part, rows)
+  static const int urows = env_or("SKETCH_LSQR_ROWS", 2);
+#define SK_PASS(MP, U)                                                                                             \
+  hipLaunchKernelGGL((lsqr_pass_kernel<MP, U>), dim3(groups), dim3(256), 0, st, A, lda, n, m, w, coefp, donep, u,  \
+                     part, rows)
   if (mpl <= 1)
-    SK_PASS(1);
+    SK_PASS(1, 4);
   else if (mpl <= 2)
-    SK_PASS(2);
-  else if (mpl <= 4)
-    SK_PASS(4);
-  else if (mpl <= 8)
-    SK_PASS(8);
+    SK_PASS(2, 4);
+  else if (mpl <= 4) {
+    if (urows >= 8)
+      SK_PASS(4, 8);
+    else if (urows <= 2)
+      SK_PASS(4, 2);
+    else
+      SK_PASS(4, 4);
+  } else if (mpl <= 8)
+    SK_PASS(8, 2);
   else {
     set_error("LSQR: at most 512 columns");
     return SK_E_NOTSUP;

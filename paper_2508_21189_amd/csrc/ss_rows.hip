@@ -356,23 +356,31 @@ __global__ void __launch_bounds__(1024) ss_rows_kernel(RowsArgs a) {
         __builtin_amdgcn_sched_barrier(0);
       }
 
-      // further rows: the remaining list entries of each bucket with two or
-      // more rows, two at a time (an odd tail pairs with the zero row)
-      const uint64_t m2 = __ballot(kcnt >= 2);
+      // further rows. The second and third entries of every bucket are
+      // preloaded one per lane (like the first), so the common cases (two or
+      // three rows) take one readlane each; buckets with four or more rows
+      // walk the rest of their list. Bucket tests are bit tests of ballots
+      // kept in scalar registers.
+      const uint32_t e1 = kcnt >= 2 ? lst[kbeg + 1] : zentry;
+      const uint32_t e2 = kcnt >= 3 ? lst[kbeg + 2] : zentry;
+      uint64_t m2 = __ballot(kcnt >= 2), m3 = __ballot(kcnt >= 3), m4 = __ballot(kcnt >= 4);
+      asm volatile("" : "+s"(m2), "+s"(m3), "+s"(m4));
 #pragma unroll
       for (int j = 0; j < JB; ++j) {
-        if ((m2 >> j) & 1ull) {
-          const uint32_t kb = (uint32_t)__builtin_amdgcn_readlane((int)kbeg, j);
-          const uint32_t ke = kb + (uint32_t)__builtin_amdgcn_readlane((int)kcnt, j);
-          for (uint32_t k = kb + 1; k < ke; k += 2) {
-            // lst[k + 1] always exists: records keep one spare slot
-            const uint32_t ea = lst[k];
-            const uint32_t eb_raw = lst[k + 1];
-            const uint32_t eb = k + 1 < ke ? eb_raw : zentry;
-            const Tacc va = lds_val<Tin>((ea << 3) + base);
-            const Tacc vb = lds_val<Tin>((eb << 3) + base);
-            acc[j] += flip(va, ea);
-            acc[j] += flip(vb, eb);
+        if (m2 & (1ull << j)) {
+          const uint32_t ea = (uint32_t)__builtin_amdgcn_readlane((int)e1, j);
+          acc[j] += flip(lds_val<Tin>((ea << 3) + base), ea);
+          if (m3 & (1ull << j)) {
+            const uint32_t eb = (uint32_t)__builtin_amdgcn_readlane((int)e2, j);
+            acc[j] += flip(lds_val<Tin>((eb << 3) + base), eb);
+            if (m4 & (1ull << j)) {
+              const uint32_t kb = (uint32_t)__builtin_amdgcn_readlane((int)kbeg, j);
+              const uint32_t ke = kb + (uint32_t)__builtin_amdgcn_readlane((int)kcnt, j);
+              for (uint32_t k = kb + 3; k < ke; ++k) {
+                const uint32_t ec = lst[k];
+                acc[j] += flip(lds_val<Tin>((ec << 3) + base), ec);
+              }
+            }
           }
         }
       }
