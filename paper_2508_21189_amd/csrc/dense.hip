@@ -139,6 +139,144 @@ __global__ void __launch_bounds__(1024) hh_panel_kernel(double* __restrict__ W, 
   }
 }
 
+// Register-resident variant of the panel factorization for panels whose
+// rows fit in the workgroup: thread t holds rows k + t + NT*i (i < RPT) of
+// the NB panel columns in registers, so each column step touches no memory:
+// one block reduction for ||x||^2 (and the pivot), one for all the panel
+// products (v^T y for the later columns, v_q^T v for the Gram entries of T),
+// then the update in registers. The panel is written back at the end.
+template <int NB, int RPT, int NTH>
+__global__ void __launch_bounds__(NTH) hh_panel_reg_kernel(double* __restrict__ W, int64_t ldw, int64_t d, int k,
+                                                           int nbp, double* __restrict__ tau,
+                                                           double* __restrict__ T) {
+  __shared__ double red[NTH / 64][NB + 2];
+  __shared__ double vals[NB + 2];
+  __shared__ double G[kPanel][kPanel + 1];
+  __shared__ double Ts[kPanel][kPanel + 1];
+  __shared__ double taus[kPanel];
+  constexpr int NT = NTH;
+  constexpr int NW = NTH / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // x[i * NB + q]: row k + tid + NT * i, panel column q (all indices static)
+  double x[RPT * NB];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int64_t r = k + tid + (int64_t)NT * i;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) x[i * NB + q] = (r < d && q < nbp) ? W[(int64_t)(k + q) * ldw + r] : 0.0;
+  }
+  for (int jj = 0; jj < nbp; ++jj) {
+    // pivot column jj of this thread's rows (selected with static indices)
+    double pc[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      double v = 0;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) v = (q == jj) ? x[i * NB + q] : v;
+      pc[i] = v;
+    }
+    double part = 0, alpha_part = 0;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int lr = tid + NT * i;
+      if (lr > jj) part += pc[i] * pc[i];
+      if (lr == jj) alpha_part = pc[i];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      part += __shfl_xor(part, o, 64);
+      alpha_part += __shfl_xor(alpha_part, o, 64);
+    }
+    if (lane == 0) {
+      red[wave][0] = part;
+      red[wave][1] = alpha_part;
+    }
+    __syncthreads();
+    double sig2 = 0, alpha = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      sig2 += red[w][0];
+      alpha += red[w][1];
+    }
+    double t = 0, beta = alpha, scale = 0;
+    if (sig2 > 0) {
+      beta = -copysign(sqrt(alpha * alpha + sig2), alpha);
+      t = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    // v: scaled below the pivot, the implicit 1 at the pivot
+    double vv[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int lr = tid + NT * i;
+      if (lr > jj && t != 0) pc[i] *= scale;
+      vv[i] = lr > jj ? pc[i] : (lr == jj ? 1.0 : 0.0);
+    }
+    double acc[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      double sacc = 0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) sacc += vv[i] * x[i * NB + q];
+      acc[q] = sacc;
+    }
+    __syncthreads();  // red is reused
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      double v = acc[q];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (lane == 0) red[wave][q] = v;
+    }
+    __syncthreads();
+    if (tid < nbp && tid != jj) {
+      double sacc = 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) sacc += red[w][tid];
+      vals[tid] = sacc;
+      if (tid < jj) G[tid][jj] = sacc;
+    }
+    if (tid == 0) {
+      tau[k + jj] = t;
+      taus[jj] = t;
+    }
+    __syncthreads();
+    // H = I - t v v^T on the later panel columns; the pivot column holds v
+    // below the pivot and beta at it
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const double f = (t != 0 && q > jj && q < nbp) ? t * vals[q] : 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int lr = tid + NT * i;
+        double xv = x[i * NB + q] - f * vv[i];
+        if (q == jj) xv = lr > jj ? pc[i] : (lr == jj ? beta : x[i * NB + q]);
+        x[i * NB + q] = xv;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int64_t r = k + tid + (int64_t)NT * i;
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+      if (r < d && q < nbp) W[(int64_t)(k + q) * ldw + r] = x[i * NB + q];
+  }
+  // T: T[i][i] = tau_i; T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
+  for (int i = 0; i < nbp; ++i) {
+    if (tid < i) {
+      double s2 = 0;
+      for (int l = tid; l < i; ++l) s2 += Ts[tid][l] * G[l][i];
+      Ts[tid][i] = -taus[i] * s2;
+    }
+    if (tid == i) Ts[i][i] = taus[i];
+    if (tid > i && tid < nbp) Ts[tid][i] = 0.0;
+    __syncthreads();
+  }
+  for (int idx = tid; idx < nbp * nbp; idx += NT) {
+    const int r = idx / nbp, cc = idx - r * nbp;
+    T[r * kPanel + cc] = Ts[r][cc];
+  }
+}
+
 // Trailing update of one column y (index k + nbp + blockIdx.x) of W:
 // y <- y - V T^T V^T y, with V the panel's reflectors (rows >= k).
 __global__ void __launch_bounds__(256) hh_trail_kernel(double* __restrict__ W, int64_t ldw, int64_t d, int k, int nbp,
@@ -240,10 +378,20 @@ __global__ void fill_kernel(double* __restrict__ x, int64_t n, double value) {
 // Host side
 // ---------------------------------------------------------------------------
 int qr_columns(double* W, int64_t ldw, int64_t d, int k, int extra_cols, double* tau, double* Tbuf, hipStream_t st) {
-  for (int c = 0; c < k; c += kPanel) {
-    const int nbp = std::min(kPanel, k - c);
-    double* T = Tbuf + (size_t)(c / kPanel) * kPanel * kPanel;
-    hipLaunchKernelGGL(hh_panel_kernel, dim3(1), dim3(1024), 0, st, W, ldw, d, c, nbp, tau, T);
+  // panel width: 32 when the panel's rows fit one row per thread, else 16
+  // (two rows per thread) while they fit in registers, else the
+  // memory-resident panel kernel
+  const int nb = d <= 1024 ? 32 : 16;
+  for (int c = 0; c < k; c += nb) {
+    const int nbp = std::min(nb, k - c);
+    double* T = Tbuf + (size_t)(c / nb) * kPanel * kPanel;
+    const int64_t rows = d - c;
+    if (rows <= 1024 && nb == 32)
+      hipLaunchKernelGGL((hh_panel_reg_kernel<32, 2, 512>), dim3(1), dim3(512), 0, st, W, ldw, d, c, nbp, tau, T);
+    else if (rows <= 2048)
+      hipLaunchKernelGGL((hh_panel_reg_kernel<16, 4, 512>), dim3(1), dim3(512), 0, st, W, ldw, d, c, nbp, tau, T);
+    else
+      hipLaunchKernelGGL(hh_panel_kernel, dim3(1), dim3(1024), 0, st, W, ldw, d, c, nbp, tau, T);
     SK_HIP(hipGetLastError());
     const int first = c + nbp;
     const int ntrail = k + extra_cols - first;
@@ -254,6 +402,8 @@ int qr_columns(double* W, int64_t ldw, int64_t d, int k, int extra_cols, double*
   }
   return SK_OK;
 }
+
+size_t qr_tbuf_doubles(int k) { return (size_t)((k + 15) / 16) * kPanel * kPanel; }
 
 int launch_to_columns(const double* M, int64_t ldm, const double* r, int64_t d, int k0, double* W, int64_t ldw,
                       hipStream_t st) {

@@ -111,7 +111,7 @@ int sketch_bufs(Carver& cv, const sk_sketch* S, int k, int dts, const void* As, 
   B->aws = cv.take<char>(B->aws_bytes);
   B->W = cv.take<double>((size_t)d * (k + 1));
   B->tau = cv.take<double>((size_t)k);
-  B->Tbuf = cv.take<double>((size_t)((k + 31) / 32) * 32 * 32);
+  B->Tbuf = cv.take<double>(qr_tbuf_doubles(k));
   B->R = cv.take<double>((size_t)k * k);
   B->c = cv.take<double>((size_t)k);
   return SK_OK;

@@ -9,8 +9,9 @@ int launch_to_columns(const double* M, int64_t ldm, const double* r, int64_t d, 
                       hipStream_t st);
 // Blocked Householder QR of the first k columns of W (d x (k + extra_cols),
 // column-major), applying Q^T to the extra columns as well. tau: k entries;
-// Tbuf: ceil(k/32) * 32 * 32 doubles.
+// Tbuf: qr_tbuf_doubles(k) doubles.
 int qr_columns(double* W, int64_t ldw, int64_t d, int k, int extra_cols, double* tau, double* Tbuf, hipStream_t st);
+size_t qr_tbuf_doubles(int k);
 // R (k x k row-major, upper) and c = first k entries of the (transformed) column k.
 int launch_extract_r(const double* W, int64_t ldw, int k, int has_rhs, double* R, double* c, hipStream_t st);
 // X = R^{-1} (k x k row-major, upper) and XT = X^T. k <= 8192.
