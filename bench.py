@@ -12,10 +12,15 @@ The JSON line also carries
   roofline      the sketch kernel's own average duration (HIP events on its
                 stream), as a fraction of the 8 TB/s HBM peak;
   lsqr          sketch-and-precondition solves of the same system to
-                tol = 1e-10 (LSQR's least-squares test), with the sketch read
-                from the float64 A, a float32 copy and a bfloat16 copy: wall
-                time per solve (median), iterations, the sketch / QR / LSQR
-                split, and the LSQR iteration's HBM roofline;
+                tol = 1e-10 (LSQR's least-squares test): SparseStack with the
+                sketch read from the float64 A, a float32 copy and a bfloat16
+                copy, and the Gaussian and SRTT sketches: wall time per solve
+                (median), iterations, the sketch / QR / LSQR split, and the
+                LSQR iteration's HBM roofline;
+  lsqr_mixed    the same on the 8388608 x 500, kappa = 1e10 system, where the
+                float32 / bfloat16 sketch copies pay off;
+  rsvd          Alg. 1 on a 65536 x 16384 float32 matrix with known spectrum
+                (k = 512) for the three sketch kinds, with the spectral error;
   cpu_baseline  the plain CPU oracle timed on a bounded row sample of the
                 same matrix on this host.
 """
@@ -74,44 +79,122 @@ def cpu_baseline(A_dev, rows):
                       "median of 3 runs, %.2f s each" % (rows, N, t)}
 
 
-def lsqr_variants(libsketch, torch, A, b, reps, tol=1e-10):
-    """Median wall time of lstsq_sketch_precond per sketch input precision."""
+def _solve_stats(libsketch, torch, S, A, b, reps, tol, As=None):
+    """Median wall time (and its split) of reps sketch-and-precondition solves."""
     import statistics
-    S = libsketch.Sketch("sparsestack", D, N, ZETA, SKETCH_SEED)
+    S.lstsq_precond(A, b, tol=tol, maxit=300, A_sketch=As)  # warm-up (workspace, code objects)
+    walls, infos = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, rc, info = S.lstsq_precond(A, b, tol=tol, maxit=300, A_sketch=As)
+        torch.cuda.synchronize()
+        walls.append((time.perf_counter() - t0) * 1e3)
+        infos.append(info)
+    res = S.residual(A, b, x)
+    it = infos[-1]
+    med = lambda key: round(statistics.median(i[key] for i in infos), 3)
+    return {"solve_ms": round(statistics.median(walls), 3), "status": rc, "iters": it["iters"],
+            "converged": it["converged"], "t_sketch_ms": med("t_sketch_ms"), "t_qr_ms": med("t_qr_ms"),
+            "t_lsqr_ms": med("t_lsqr_ms"),
+            "lsqr_ms_per_iter": round(statistics.median(i["t_lsqr_ms"] / max(1, i["iters"]) for i in infos), 4),
+            "resnorm": res, "rnorm_est": it["rnorm_est"]}
+
+
+def lsqr_variants(libsketch, torch, A, b, reps, tol=1e-10):
+    """Sketch-and-precondition solves of the coherent system: SparseStack with
+    the sketch reading float64 / float32 / bfloat16 copies of A, and the
+    Gaussian (matrix-core GEMM) and SRTT (Walsh-Hadamard) sketches."""
     out = {}
-    for name, dt in (("f64", None), ("f32", torch.float32), ("bf16", torch.bfloat16)):
+    variants = (("sparsestack_f64", "sparsestack", ZETA, None), ("sparsestack_f32", "sparsestack", ZETA, torch.float32),
+                ("sparsestack_bf16", "sparsestack", ZETA, torch.bfloat16), ("gaussian_f64", "gaussian", 1, None),
+                ("srtt_f64", "srtt", 1, None))
+    for name, kind, zeta, dt in variants:
+        S = libsketch.Sketch(kind, D, N, zeta, SKETCH_SEED)
         As = A.to(dt) if dt is not None else None
-        S.lstsq_precond(A, b, tol=tol, maxit=300, A_sketch=As)  # warm-up (workspace, code objects)
-        walls, infos = [], []
-        for _ in range(reps):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            x, rc, info = S.lstsq_precond(A, b, tol=tol, maxit=300, A_sketch=As)
-            torch.cuda.synchronize()
-            walls.append((time.perf_counter() - t0) * 1e3)
-            infos.append(info)
-        res = S.residual(A, b, x)
-        med = statistics.median(walls)
-        it = infos[-1]
-        per_iter = statistics.median(i["t_lsqr_ms"] / max(1, i["iters"]) for i in infos)
-        out[name] = {"solve_ms": round(med, 3), "status": rc, "iters": it["iters"], "converged": it["converged"],
-                     "t_sketch_ms": round(statistics.median(i["t_sketch_ms"] for i in infos), 3),
-                     "t_qr_ms": round(statistics.median(i["t_qr_ms"] for i in infos), 3),
-                     "t_lsqr_ms": round(statistics.median(i["t_lsqr_ms"] for i in infos), 3),
-                     "lsqr_ms_per_iter": round(per_iter, 4),
-                     "resnorm": res, "rnorm_est": it["rnorm_est"]}
-        print("bench: lsqr %s %.2f ms, %d iterations" % (name, med, it["iters"]), file=sys.stderr, flush=True)
-        del As
-    f64 = out["f64"]
+        out[name] = _solve_stats(libsketch, torch, S, A, b, reps, tol, As)
+        print("bench: lsqr %s %.2f ms, %d iterations" % (name, out[name]["solve_ms"], out[name]["iters"]),
+              file=sys.stderr, flush=True)
+        del As, S
+        torch.cuda.empty_cache()
+    f64 = out["sparsestack_f64"]
     per_iter = f64["lsqr_ms_per_iter"]
     it_bytes = N * M * 8
     out["tol"] = tol
-    out["speedup_vs_f64"] = {k: round(f64["solve_ms"] / out[k]["solve_ms"], 3) for k in ("f32", "bf16")}
+    out["speedup_vs_sparsestack_f64"] = {k: round(f64["solve_ms"] / out[k]["solve_ms"], 3) for k in out
+                                         if isinstance(out[k], dict) and k != "sparsestack_f64"}
     out["roofline_iteration"] = {"bound": "hbm", "achieved": round(it_bytes / (per_iter * 1e-3) / 1e9, 2),
                                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                  "frac": round(it_bytes / (per_iter * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                  "alg_bytes_per_iteration": it_bytes,
                                  "note": "one fused pass over A per iteration plus the small step kernels"}
+    return out
+
+
+def lsqr_mixed(libsketch, inputs, torch, reps, tol=1e-10):
+    """The mixed-precision system: A 8388608 x 500 iid N(0,1) with column
+    scaling kappa(D) = 1e10, SparseStack d = 2000, zeta = 8, the sketch reading
+    A itself (float64) or its float32 / bfloat16 copy; QR and LSQR in float64."""
+    n3, m3, d3 = 1 << 23, 500, 2000
+    print("bench: generating %d x %d float64 input" % (n3, m3), file=sys.stderr, flush=True)
+    A, b, _ = inputs.scaled_gaussian(n3, m3, exponent=10.0, seed=DATA_SEED + 1)
+    out = {"workload": "A %dx%d f64 iid N(0,1), kappa(D)=1e10; SparseStack d=%d zeta=8" % (n3, m3, d3)}
+    S = libsketch.Sketch("sparsestack", d3, n3, 8, SKETCH_SEED + 1)
+    for name, dt in (("f64", None), ("f32", torch.float32), ("bf16", torch.bfloat16)):
+        As = A.to(dt) if dt is not None else None
+        out[name] = _solve_stats(libsketch, torch, S, A, b, reps, tol, As)
+        print("bench: mixed %s %.2f ms, %d iterations" % (name, out[name]["solve_ms"], out[name]["iters"]),
+              file=sys.stderr, flush=True)
+        del As
+        torch.cuda.empty_cache()
+    out["speedup_vs_f64"] = {k: round(out["f64"]["solve_ms"] / out[k]["solve_ms"], 3) for k in ("f32", "bf16")}
+    del A, b, S
+    torch.cuda.empty_cache()
+    return out
+
+
+def rsvd_variants(libsketch, inputs, torch, reps):
+    """Alg. 1 on A = U diag(i^-2) V^T (65536 x 16384, float32), k = 512, with
+    SparseStack (zeta = 8), SRTT and Gaussian sketches; the spectral error
+    ||A - U S V^T||_2 is estimated on the device by 30 power iterations."""
+    import statistics
+    rows, cols, k = 65536, 16384, 512
+    print("bench: generating the %d x %d low-rank matrix" % (rows, cols), file=sys.stderr, flush=True)
+    A, sig = inputs.lowrank_decay(rows, cols, seed=DATA_SEED + 2, dtype=torch.float32)
+    A64 = A.double()
+    out = {"workload": "A %dx%d f32 = U diag(i^-2) V^T, k=%d" % (rows, cols, k), "floor_sigma_k+1": float(sig[k])}
+    for kind, zeta in (("sparsestack", 8), ("srtt", 1), ("gaussian", 1)):
+        S = libsketch.Sketch(kind, k, cols, zeta, SKETCH_SEED + 2)
+        S.rsvd(A)
+        walls, infos = [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            U, s, Vt, rc, info = S.rsvd(A)
+            torch.cuda.synchronize()
+            walls.append((time.perf_counter() - t0) * 1e3)
+            infos.append(info)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(1)
+        x = torch.randn(cols, dtype=torch.float64, device="cuda", generator=g)
+        x /= x.norm()
+        est = 0.0
+        for _ in range(30):
+            y = A64 @ x - U @ (s * (Vt @ x))
+            z = A64.T @ y - Vt.T @ (s * (U.T @ y))
+            nz = z.norm()
+            est = float(nz.sqrt())
+            x = z / nz
+        it = infos[-1]
+        out[kind] = {"total_ms": round(statistics.median(walls), 3), "status": rc,
+                     "t_sketch_ms": round(it["t_sketch_ms"], 3), "t_orth_ms": round(it["t_orth_ms"], 3),
+                     "t_project_ms": round(it["t_project_ms"], 3), "t_svd_ms": round(it["t_svd_ms"], 3),
+                     "jacobi_sweeps": it["jacobi_sweeps"], "spectral_error": est}
+        print("bench: rsvd %s %.2f ms, error %.3e" % (kind, out[kind]["total_ms"], est), file=sys.stderr, flush=True)
+        del U, Vt, S
+        torch.cuda.empty_cache()
+    del A, A64
+    torch.cuda.empty_cache()
     return out
 
 
@@ -124,7 +207,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain device copy of A (a kernel of known traffic, for counter calibration)")
-    ap.add_argument("--lsqr-reps", type=int, default=3, help="timed solves per sketch precision (0 = skip)")
+    ap.add_argument("--lsqr-reps", type=int, default=3, help="timed solves per sketch variant (0 = skip)")
+    ap.add_argument("--mixed-reps", type=int, default=2,
+                    help="timed solves per precision of the 8388608 x 500 mixed-precision system (0 = skip)")
+    ap.add_argument("--rsvd-reps", type=int, default=1, help="timed randomized SVDs per sketch kind (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -172,7 +258,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "coherent least squares: A 4194304x200 f64 (Pareto 1.5 rows, 1%% spikes x1e3, "
+        "config": {"workload": "coherent least squares: A 4194304x200 f64 (Pareto 1.5 rows, 1% spikes x1e3, "
                                "kappa(D)=1e8), SparseStack d=800 zeta=8",
                    "n": N, "m": M, "d": D, "zeta": ZETA, "spiked_rows": nspk},
         "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
@@ -187,9 +273,16 @@ def main():
         del Acopy
     if args.lsqr_reps > 0:
         rec["lsqr"] = lsqr_variants(libsketch, torch, A, b, args.lsqr_reps)
+    cpu_sample = A[:args.cpu_rows].cpu() if not args.no_cpu else None
+    del A, b, out, ws, S
+    torch.cuda.empty_cache()
+    if args.mixed_reps > 0:
+        rec["lsqr_mixed"] = lsqr_mixed(libsketch, inputs, torch, args.mixed_reps)
+    if args.rsvd_reps > 0:
+        rec["rsvd"] = rsvd_variants(libsketch, inputs, torch, args.rsvd_reps)
     if not args.no_cpu:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
-        rec["cpu_baseline"] = cpu_baseline(A, args.cpu_rows)
+        rec["cpu_baseline"] = cpu_baseline(cpu_sample, args.cpu_rows)
     print(json.dumps(rec), flush=True)
 
 
