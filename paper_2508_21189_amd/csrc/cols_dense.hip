@@ -14,8 +14,6 @@
 
 namespace sk {
 
-constexpr double kTwoPiC = 6.283185307179586;
-
 template <typename T>
 __global__ void gauss_fill_kernel(T* __restrict__ G, int64_t d, int64_t n, uint32_t k0, uint32_t k1, double scale) {
   const int64_t pairs = ((d + 1) / 2) * n;
@@ -28,7 +26,7 @@ __global__ void gauss_fill_kernel(T* __restrict__ G, int64_t d, int64_t n, uint3
     const double u2 = ((double)x2 + 0.5) * 0x1p-52;
     const double r = sqrt(-2.0 * log(u1));
     double s, c;
-    sincos(kTwoPiC * u2, &s, &c);
+    sincospi(2.0 * u2, &s, &c);
     G[(2 * q) * n + i] = (T)(r * c * scale);
     if (2 * q + 1 < d) G[(2 * q + 1) * n + i] = (T)(r * s * scale);
   }

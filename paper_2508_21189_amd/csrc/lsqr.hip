@@ -120,6 +120,125 @@ __global__ void __launch_bounds__(256) lsqr_pass_kernel(const double* __restrict
   }
 }
 
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+// x of the lane n places down this lane's 16-lane DPP row (row_ror:n).
+template <int N>
+__device__ inline double row_ror(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, 0x120 + N, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), 0x120 + N, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+// Sum of x over the 16 lanes of this lane's DPP row: every lane ends with
+// the same total.
+__device__ inline double row16_sum(double x) {
+  x += row_ror<8>(x);
+  x += row_ror<4>(x);
+  x += row_ror<2>(x);
+  x += row_ror<1>(x);
+  return x;
+}
+
+// The same pass for an even number of columns m and 16-byte aligned rows
+// (lda even): 16 lanes per row, each loading column pairs 2 (l%16) + 32 k,
+// k < MP2, so a wave covers 4 rows per load instruction and a row's dot
+// product needs 4 DPP steps inside its 16-lane row. A workgroup takes 16
+// consecutive rows per step (row 4 wave + l/16 of the step); the next step's
+// rows are loaded before this step's arithmetic. Columns past m load column
+// 0 of the same row (w is zero there, and their column sums are dropped);
+// rows past the workgroup's range repeat its last row with p = 0.
+template <int MP2>
+__global__ void __launch_bounds__(256) lsqr_pass16_kernel(const double* __restrict__ A, int64_t lda, int64_t n, int m,
+                                                          const double* __restrict__ w,
+                                                          const double* __restrict__ coefp,
+                                                          const int* __restrict__ donep, double* __restrict__ u,
+                                                          double* __restrict__ part, int64_t rows_per_wg) {
+  if (donep && *donep) return;
+  __shared__ double red[4][MP2 * 32 + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, cl = lane & 15;
+  const double coef = *coefp;
+  v2d wl[MP2], q[MP2];
+#pragma unroll
+  for (int k = 0; k < MP2; ++k) {
+    const int c = 2 * cl + 32 * k;
+    const v2d wv = c < m ? v2d{w[c], w[c + 1]} : v2d{0.0, 0.0};
+    wl[k] = wv;
+    q[k] = v2d{0.0, 0.0};
+  }
+  double pp = 0.0;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
+  const int64_t r1 = min(n, r0 + rows_per_wg);
+  const int64_t nsteps = r1 > r0 ? (r1 - r0 + 15) / 16 : 0;
+  auto load = [&](int64_t rb, v2d (&x)[MP2], double& uu) {
+    const int64_t i = min(rb + 4 * wave + g, r1 - 1);
+    const double* a = A + i * lda;
+#pragma unroll
+    for (int k = 0; k < MP2; ++k) {
+      const int c = 2 * cl + 32 * k;  // past m: column 0 of the same row
+      x[k] = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(a + (c < m ? c : 0)));
+    }
+    uu = u[i];
+  };
+  v2d x[MP2];
+  double uo = 0.0;
+  if (nsteps > 0) load(r0, x, uo);
+  for (int64_t st = 0; st < nsteps; ++st) {
+    const int64_t rb = r0 + 16 * st;
+    v2d xn[MP2];
+    double un = 0.0;
+    const bool more = st + 1 < nsteps;
+    if (more) load(rb + 16, xn, un);
+    double dt = 0.0;
+#pragma unroll
+    for (int k = 0; k < MP2; ++k) {
+      dt = fma(x[k].x, wl[k].x, dt);
+      dt = fma(x[k].y, wl[k].y, dt);
+    }
+    dt = row16_sum(dt);
+    const int64_t i = rb + 4 * wave + g;
+    const bool ok = i < r1;
+    const double p = ok ? fma(coef, uo, dt) : 0.0;
+    if (ok && cl == 0) u[i] = p;
+#pragma unroll
+    for (int k = 0; k < MP2; ++k) {
+      q[k].x = fma(x[k].x, p, q[k].x);
+      q[k].y = fma(x[k].y, p, q[k].y);
+    }
+    pp = fma(p, p, pp);
+    if (more) {
+#pragma unroll
+      for (int k = 0; k < MP2; ++k) x[k] = xn[k];
+      uo = un;
+    }
+  }
+  // the wave's column sums: add the 4 rows groups (lanes l, l^16, l^32, l^48)
+#pragma unroll
+  for (int k = 0; k < MP2; ++k) {
+    q[k].x += __shfl_xor(q[k].x, 16, 64);
+    q[k].y += __shfl_xor(q[k].y, 16, 64);
+    q[k].x += __shfl_xor(q[k].x, 32, 64);
+    q[k].y += __shfl_xor(q[k].y, 32, 64);
+  }
+  pp += __shfl_xor(pp, 16, 64);
+  pp += __shfl_xor(pp, 32, 64);
+  if (g == 0) {
+#pragma unroll
+    for (int k = 0; k < MP2; ++k) {
+      red[wave][2 * cl + 32 * k] = q[k].x;
+      red[wave][2 * cl + 32 * k + 1] = q[k].y;
+    }
+    if (cl == 0) red[wave][MP2 * 32] = pp;
+  }
+  __syncthreads();
+  double* out = part + (int64_t)blockIdx.x * (m + 1);
+  for (int j = tid; j <= m; j += blockDim.x) {
+    const int jj = j < m ? j : MP2 * 32;
+    out[j] = ((red[0][jj] + red[1][jj]) + red[2][jj]) + red[3][jj];
+  }
+}
+
 // out[j] = sum_g part[g][j]: one workgroup per column j; thread t sums
 // g = t, t + 256, ... in order, then a fixed-order tree (deterministic).
 __global__ void __launch_bounds__(256) reduce_cols_kernel(const double* __restrict__ part, int ngroups, int width,
@@ -338,37 +457,60 @@ static int env_or(const char* name, int dflt) {
 }
 
 int lsqr_pass_groups(int64_t n) {
-  static const int cap = env_or("SKETCH_LSQR_GROUPS", 1024);
+  static const int cap = env_or("SKETCH_LSQR_GROUPS", 1536);
   return (int)std::max<int64_t>(1, std::min<int64_t>(cap, (n + 63) / 64));
 }
 
 int launch_lsqr_pass(const double* A, int64_t lda, int64_t n, int m, const double* w, const double* coefp,
                      const int* donep, double* u, double* part, hipStream_t st) {
   const int groups = lsqr_pass_groups(n);
-  const int64_t rows = (n + groups - 1) / groups;
-  const int mpl = (m + 63) / 64;
-  static const int urows = env_or("SKETCH_LSQR_ROWS", 2);
+  int64_t rows = (n + groups - 1) / groups;
+  // 16 lanes a row for up to 256 columns; wider rows keep 64 lanes a row,
+  // whose per-row overhead is already small next to 8 loads a lane
+  const bool vec16 = m % 2 == 0 && lda % 2 == 0 && (uintptr_t)A % 16 == 0 && m <= 256;
+  static const int use16 = env_or("SKETCH_LSQR_VEC16", 1);
+  if (vec16 && use16) {
+    rows = ((rows + 15) / 16) * 16;
+    const int mp2 = (m + 31) / 32;
+#define SK_PASS16(MP)                                                                                           \
+  hipLaunchKernelGGL((lsqr_pass16_kernel<MP>), dim3(groups), dim3(256), 0, st, A, lda, n, m, w, coefp, donep, u, \
+                     part, rows)
+    if (mp2 <= 1)
+      SK_PASS16(1);
+    else if (mp2 <= 2)
+      SK_PASS16(2);
+    else if (mp2 <= 4)
+      SK_PASS16(4);
+    else if (mp2 <= 7)
+      SK_PASS16(7);
+    else
+      SK_PASS16(8);
+#undef SK_PASS16
+  } else {
+    const int mpl = (m + 63) / 64;
+    static const int urows = env_or("SKETCH_LSQR_ROWS", 2);
 #define SK_PASS(MP, U)                                                                                             \
   hipLaunchKernelGGL((lsqr_pass_kernel<MP, U>), dim3(groups), dim3(256), 0, st, A, lda, n, m, w, coefp, donep, u,  \
                      part, rows)
-  if (mpl <= 1)
-    SK_PASS(1, 4);
-  else if (mpl <= 2)
-    SK_PASS(2, 4);
-  else if (mpl <= 4) {
-    if (urows >= 8)
-      SK_PASS(4, 8);
-    else if (urows <= 2)
-      SK_PASS(4, 2);
-    else
-      SK_PASS(4, 4);
-  } else if (mpl <= 8)
-    SK_PASS(8, 2);
-  else {
-    set_error("LSQR: at most 512 columns");
-    return SK_E_NOTSUP;
-  }
+    if (mpl <= 1)
+      SK_PASS(1, 4);
+    else if (mpl <= 2)
+      SK_PASS(2, 4);
+    else if (mpl <= 4) {
+      if (urows >= 8)
+        SK_PASS(4, 8);
+      else if (urows <= 2)
+        SK_PASS(4, 2);
+      else
+        SK_PASS(4, 4);
+    } else if (mpl <= 8)
+      SK_PASS(8, 2);
+    else {
+      set_error("LSQR: at most 512 columns");
+      return SK_E_NOTSUP;
+    }
 #undef SK_PASS
+  }
   SK_HIP(hipGetLastError());
   hipLaunchKernelGGL(reduce_cols_kernel, dim3(m + 1), dim3(256), 0, st, part, groups, m + 1, donep,
                      part + (int64_t)groups * (m + 1));
