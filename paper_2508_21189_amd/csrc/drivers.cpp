@@ -72,6 +72,19 @@ struct Phases {
   }
 };
 
+// Two events without timing, for the queued stopping tests of LSQR.
+struct EventPair {
+  hipEvent_t e[2] = {};
+  int create() {
+    for (auto& x : e) SK_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+    return SK_OK;
+  }
+  ~EventPair() {
+    for (auto& x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+};
+
 #define SK_TRY(expr)            \
   do {                          \
     int _rc = (expr);           \
@@ -274,21 +287,52 @@ int lstsq_sketch_precond(sketch_t S, int64_t m, const double* A, int64_t lda, in
   SK_TRY(launch_lsqr_setup(sd, tol, maxit, st));
   SK_TRY(launch_lsqr_pass(A, lda, n, k, x0, &sd->coef, nullptr, u, part, st));
   SK_TRY(launch_lsqr_init(sd, qv, Rinv, RinvT, k, v, wd, y, wv, st));
+  // Iterations go out in batches, each followed by a snapshot of the device
+  // state into one of two pinned slots. The host keeps two batches queued:
+  // while it waits for one snapshot the GPU already runs the next batch, so
+  // the stopping test costs no idle time. Launches after the device has set
+  // done (converged or maxit reached) return at once.
+  static_assert(2 * sizeof(LsqrDev) <= 4096, "two state slots in the pinned page");
   LsqrDev* hs = static_cast<LsqrDev*>(S->h_pinned);
+  EventPair ev;
+  SK_TRY(ev.create());
+  auto snapshot = [&](int slot) -> int {
+    SK_HIP(hipMemcpyAsync(&hs[slot], sd, sizeof(LsqrDev), hipMemcpyDeviceToHost, st));
+    SK_HIP(hipEventRecord(ev.e[slot], st));
+    return SK_OK;
+  };
   const int batch = 4;
-  for (int it = 0;;) {
-    SK_HIP(hipMemcpyAsync(hs, sd, sizeof(LsqrDev), hipMemcpyDeviceToHost, st));
-    SK_HIP(hipStreamSynchronize(st));
-    if (hs->done || it >= maxit) break;
-    const int nb = std::min(batch, maxit - it);
+  int issued = 0;
+  auto issue = [&](int slot) -> int {
+    const int nb = std::min(batch, maxit - issued);
     for (int j = 0; j < nb; ++j) {
       SK_TRY(launch_lsqr_pass(A, lda, n, k, wv, &sd->coef, &sd->done, u, part, st));
       SK_TRY(launch_lsqr_step(sd, qv, Rinv, RinvT, k, v, wd, y, wv, st));
     }
-    it += nb;
+    issued += nb;
+    return snapshot(slot);
+  };
+  SK_TRY(snapshot(0));  // state after the initialization
+  int inflight = 1, pending = 0;
+  if (issued < maxit) {
+    SK_TRY(issue(1));
+    ++inflight;
+  }
+  for (;;) {
+    SK_HIP(hipEventSynchronize(ev.e[pending]));
+    --inflight;
+    if (hs[pending].done) break;
+    if (issued < maxit) {
+      SK_TRY(issue(pending));
+      ++inflight;
+    } else if (inflight == 0) {
+      break;
+    }
+    pending ^= 1;
   }
   SK_TRY(launch_lsqr_finish(Rinv, k, x0, y, x, st));
   SK_TRY(ph.mark());                                                // 3: solution written
+  SK_HIP(hipMemcpyAsync(&hs[0], sd, sizeof(LsqrDev), hipMemcpyDeviceToHost, st));
   SK_HIP(hipStreamSynchronize(st));
   if (info) {
     info->iters = hs->iters;

@@ -7,6 +7,7 @@ namespace sk {
 // Plan of the row-mode SparseStack apply (SA = S A, A row-major n x m).
 struct RowsPlan {
   int C = 64;            // columns per slab (lanes per wave that hold data)
+  int rowb = 512;        // LDS bytes of a tile row (C columns, rounded up to 16)
   int n_slabs = 1;
   int R = 128;           // rows per LDS sub-tile
   int W = 16;            // waves per workgroup

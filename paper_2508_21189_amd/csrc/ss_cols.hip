@@ -206,7 +206,7 @@ int cols_workspace(const sk_sketch* S, int dtype_in, size_t* bytes) {
 }
 
 int launch_plan_generic(const sk_sketch* S, int R, int rec_bytes, int lst_off, int64_t n_tiles, void* plan,
-                        int rshift, hipStream_t st);
+                        int runit, hipStream_t st);
 
 template <typename Tin, int JB>
 static int launch_cols_t(const sk_sketch* S, const ColsPlan& p, int64_t rows, const void* A, int64_t lda, void* Y,
@@ -262,7 +262,7 @@ int launch_cols_apply(const sk_sketch* S, int dtype_in, int64_t rows, const void
     set_error("sketch_apply_T: workspace too small (see sketch_workspace_size)");
     return SK_E_INVAL;
   }
-  rc = launch_plan_generic(S, p.TC, p.rec_bytes, p.lst_off, p.n_tiles, ws, 0, st);
+  rc = launch_plan_generic(S, p.TC, p.rec_bytes, p.lst_off, p.n_tiles, ws, 1, st);
   if (rc != SK_OK) return rc;
   const int of64 = dtype_out == SK_F64;
   if (dtype_in == SK_F64) return launch_cols_jb<double>(S, p, rows, A, lda, Y, ldy, of64, ws, st);

@@ -77,14 +77,15 @@ struct PlanArgs {
   uint32_t k0, k1;
   unsigned char* out;  // [tiles][zeta] records of rec_bytes
   int rec_bytes, lst_off;
-  int rshift;          // list entries carry row << rshift
+  int runit;           // list entries carry row * runit
 };
 
 // Record of (tile, block t): u16 off[nb + 1] (bucket s holds list entries
 // [off[s], off[s+1])), then at lst_off u32 lst[R]: the tile's rows sorted by
-// bucket, stable, each entry (row << rshift) | negative << 31. The row kernel
-// uses rshift = log2(row bytes / 8), so (entry << 3) is the row's LDS byte
-// offset in the tile (the sign bit shifts out); the narrow kernel uses 0.
+// bucket, stable, each entry (row * runit) | negative << 31. The row kernel
+// uses runit = (LDS bytes of a tile row) / 8, so (entry << 3) is the row's LDS
+// byte offset in the tile (the sign bit shifts out); the narrow kernel and
+// the column mode use 1.
 __global__ void __launch_bounds__(1024) ss_plan_kernel(PlanArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -167,7 +168,7 @@ __global__ void __launch_bounds__(1024) ss_plan_kernel(PlanArgs a) {
       if (r < rv) {
         const uint32_t code = cd[r];
         const uint32_t rkr = rk[r];
-        glst[cnt[code >> 1] + rkr] = ((uint32_t)r << a.rshift) | ((code & 1u) << 31);
+        glst[cnt[code >> 1] + rkr] = ((uint32_t)r * (uint32_t)a.runit) | ((code & 1u) << 31);
       }
     }
   }
@@ -187,6 +188,7 @@ struct RowsArgs {
   int rec_bytes, lst_off;
   void* P;
   int buf_stride, off_zero, off_plan, plan_dma_bytes, off_xtra;
+  int rowb;  // LDS bytes of a tile row: the slab's columns, rounded up to 16
 };
 
 template <typename Tin>
@@ -236,10 +238,13 @@ template <typename Tin, int JB, int LB>
 __global__ void __launch_bounds__(1024) ss_rows_kernel(RowsArgs a) {
   using Tacc = typename InType<Tin>::acc;
   constexpr int ES = sizeof(Tin);
-  constexpr int ROWB = 64 * ES;  // LDS bytes per tile row (64 columns)
+  constexpr int ZROWB = 64 * ES;  // LDS bytes of the zero row (one value per lane)
   static_assert(JB <= 64, "one bucket per lane");
   // The kernel declares no static LDS, so this dynamic segment starts at LDS
-  // address 0 and every tile row starts at a multiple of ROWB.
+  // address 0. Tile rows are packed at a stride of a.rowb bytes (the slab's
+  // columns only), so a tile holds as many rows as its bytes allow; lanes
+  // past the slab read the next row or the zero row, and their sums are
+  // never written.
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
   const int tid = threadIdx.x, lane = tid & 63;
@@ -276,27 +281,32 @@ __global__ void __launch_bounds__(1024) ss_rows_kernel(RowsArgs a) {
   for (int j = 0; j < JB; ++j) acc[j] = 0;
 
   // zero rows (empty buckets read them), one after each tile buffer
-  for (int i = tid; i < 2 * (ROWB / 4); i += nthreads) {
-    const int b = i / (ROWB / 4);
-    ((uint32_t*)(smem + b * a.buf_stride + a.off_zero))[i - b * (ROWB / 4)] = 0u;
+  for (int i = tid; i < 2 * (ZROWB / 4); i += nthreads) {
+    const int b = i / (ZROWB / 4);
+    ((uint32_t*)(smem + b * a.buf_stride + a.off_zero))[i - b * (ZROWB / 4)] = 0u;
   }
 
   auto issue_loads = [&](int st, int buf) {
     const int64_t r0 = r_begin + (int64_t)st * R;
     const int rv = (int)min((int64_t)R, r_end - r0);
     unsigned char* dst = smem + buf * a.buf_stride;
-    const int n_instr = R * ROWB / (64 * LB);
+    const int rowb = a.rowb;
+    const int tile_bytes = R * rowb;
+    const int n_instr = (tile_bytes + 64 * LB - 1) / (64 * LB);
     for (int k = wave; k < n_instr; k += nwaves) {
       const int byte = (k * 64 + lane) * LB;
-      const int row = byte / ROWB;
-      const int cb = byte - row * ROWB;
+      const int row = byte / rowb;
+      const int cb = byte - row * rowb;
       const unsigned char* src = a.A;  // in-bounds stand-in for padding lanes
       if (row < rv && cb < slab_bytes) src = a.A + (r0 + row) * a.lda_bytes + col0 * ES + cb;
       const uint32_t la = (uint32_t)__builtin_amdgcn_readfirstlane((int)lds_addr_of(dst + k * 64 * LB));
-      if constexpr (LB == 16)
-        dma_to_lds16(src, la);
-      else
-        dma_to_lds4(src, la);
+      // lanes past the tile stay inactive: their slots hold the zero row
+      if (byte < tile_bytes) {
+        if constexpr (LB == 16)
+          dma_to_lds16(src, la);
+        else
+          dma_to_lds4(src, la);
+      }
     }
     // the tile's plan records for this group's blocks (contiguous)
     const unsigned char* psrc = a.plan + ((r0 / R) * a.zeta + t0) * (int64_t)a.rec_bytes;
@@ -562,9 +572,9 @@ static void plan_record(int R, int64_t nb, int* rec_bytes, int* lst_off) {
 struct RowsLds {
   size_t tile, zero, plan, plan_dma, buf_stride, xtra, total;
 };
-static RowsLds rows_lds(int es, int R, int bpg, int rec_bytes, int W) {
+static RowsLds rows_lds(int es, int R, int rowb, int bpg, int rec_bytes, int W) {
   RowsLds l;
-  l.tile = (size_t)R * 64 * es;
+  l.tile = (size_t)R * rowb;
   l.zero = l.tile;
   l.plan = align16(l.zero + (size_t)64 * es);
   l.plan_dma = align1k((size_t)bpg * rec_bytes);
@@ -667,17 +677,18 @@ int plan_rows(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_
   if (C > 64) C = 64;
   p->C = C;
   p->n_slabs = (int)((m + C - 1) / C);
+  p->rowb = (int)align16((size_t)C * es);
 
-  // tile rows: 64 KB per buffer, shrunk until the LDS plan fits
-  int R = env_int("SKETCH_TILE_ROWS", 65536 / (64 * es));
+  // tile rows: about 64 KB per buffer, shrunk until the LDS plan fits
+  int R = env_int("SKETCH_TILE_ROWS", 65536 / p->rowb);
   const size_t lds_cap = 160 * 1024;
   for (;;) {
     plan_record(R, nb, &p->rec_bytes, &p->lst_off);
-    if (rows_lds(es, R, p->bpg, p->rec_bytes, p->W).total <= lds_cap || R <= 16) break;
-    R /= 2;
+    if (rows_lds(es, R, p->rowb, p->bpg, p->rec_bytes, p->W).total <= lds_cap || R <= 16) break;
+    R = R * 7 / 8;
   }
   p->R = R;
-  p->lds_bytes = rows_lds(es, R, p->bpg, p->rec_bytes, p->W).total;
+  p->lds_bytes = rows_lds(es, R, p->rowb, p->bpg, p->rec_bytes, p->W).total;
   if (p->lds_bytes > lds_cap) {
     set_error("sketch_apply: LDS plan does not fit");
     return SK_E_NOTSUP;
@@ -702,7 +713,7 @@ int plan_rows(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_
 // Bucket plans of every tile of R consecutive indices (rows of A in row mode,
 // columns of A in column mode).
 int launch_plan_generic(const sk_sketch* S, int R, int rec_bytes, int lst_off, int64_t n_tiles, void* plan,
-                        int rshift, hipStream_t st) {
+                        int runit, hipStream_t st) {
   PlanArgs a;
   a.n = S->n;
   a.R = R;
@@ -716,7 +727,7 @@ int launch_plan_generic(const sk_sketch* S, int R, int rec_bytes, int lst_off, i
   a.out = (unsigned char*)plan;
   a.rec_bytes = rec_bytes;
   a.lst_off = lst_off;
-  a.rshift = rshift;
+  a.runit = runit;
   const int threads = 64 * std::min(16, S->zeta);
   const size_t lds = plan_lds(R, S->zeta, S->nb);
   SK_HIP(hipFuncSetAttribute((const void*)ss_plan_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -725,8 +736,8 @@ int launch_plan_generic(const sk_sketch* S, int R, int rec_bytes, int lst_off, i
   return SK_OK;
 }
 
-static int launch_plan(const sk_sketch* S, const RowsPlan& p, void* plan, int rshift, hipStream_t st) {
-  return launch_plan_generic(S, p.R, p.rec_bytes, p.lst_off, p.n_tiles, plan, rshift, st);
+static int launch_plan(const sk_sketch* S, const RowsPlan& p, void* plan, int runit, hipStream_t st) {
+  return launch_plan_generic(S, p.R, p.rec_bytes, p.lst_off, p.n_tiles, plan, runit, st);
 }
 
 template <typename Tin, int JB, int LB>
@@ -754,7 +765,8 @@ static int launch_rows_t(const sk_sketch* S, const RowsPlan& p, int64_t m, const
   a.rec_bytes = p.rec_bytes;
   a.lst_off = p.lst_off;
   a.P = P;
-  const RowsLds l = rows_lds(es, p.R, p.bpg, p.rec_bytes, p.W);
+  const RowsLds l = rows_lds(es, p.R, p.rowb, p.bpg, p.rec_bytes, p.W);
+  a.rowb = p.rowb;
   a.buf_stride = (int)l.buf_stride;
   a.off_zero = (int)l.zero;
   a.off_plan = (int)l.plan;
@@ -841,9 +853,8 @@ int launch_rows_apply(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64
   void* P = ws;
   void* plan = (unsigned char*)ws + p.partial_bytes;
   // wide kernel: entry << 3 is the row's byte offset in the tile (rows of 64 elements)
-  int rshift = 0;
-  if (!p.narrow) rshift = dtype_in == SK_F64 ? 6 : (dtype_in == SK_F32 ? 5 : 4);
-  int rc = launch_plan(S, p, plan, rshift, st);
+  const int runit = p.narrow ? 1 : p.rowb / 8;
+  int rc = launch_plan(S, p, plan, runit, st);
   if (rc != SK_OK) return rc;
   if (p.narrow) {
     if (dtype_in == SK_F64)
