@@ -178,52 +178,159 @@ __device__ inline void rr_pair_g(int kp, int r, int i, int* p, int* q) {
   }
 }
 
-__global__ void __launch_bounds__(256) jacobi_round_kernel(double* __restrict__ Uc, double* __restrict__ Vc, int k,
-                                                           int r, double tol, int* __restrict__ rotated) {
-  __shared__ double red[3][4];
-  const int kp = k + (k & 1);
-  int p, q;
-  rr_pair_g(kp, r, blockIdx.x, &p, &q);
-  if (p >= k || q >= k) return;
-  double* up = Uc + (int64_t)p * k;
-  double* uq = Uc + (int64_t)q * k;
-  double a = 0, b = 0, g = 0;
-  for (int i = threadIdx.x; i < k; i += blockDim.x) {
-    const double x = up[i], y = uq[i];
-    a += x * x;
-    b += y * y;
-    g += x * y;
+// 64-bit DPP move of v (dpp_ctrl C, row mask RM); disabled rows give 0.
+template <int C, int RM>
+__device__ inline double dpp64(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, C, RM, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), C, RM, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+// Sum of v over the wave, returned uniformly (the value that ends in lane 63):
+// row_ror 8, 4, 2, 1 inside each 16-lane row, then row_bcast 15 and 31 carry
+// the row sums up to the last row.
+__device__ inline double wave_sum_dpp(double v) {
+  v += dpp64<0x128, 0xF>(v);
+  v += dpp64<0x124, 0xF>(v);
+  v += dpp64<0x122, 0xF>(v);
+  v += dpp64<0x121, 0xF>(v);
+  v += dpp64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Block one-sided Jacobi. The columns of Uc are cut into blocks of BS; a
+// workgroup takes either one block (diagonal visit: every pair inside it, in
+// BS - 1 round-robin rounds) or a pair of blocks of the round (cross visit:
+// the BS x BS pairs between them, in BS rounds of BS disjoint pairs). It
+// holds the visit's columns in LDS, gives each pair of a round to one wave,
+// rotates the columns there, and accumulates the same rotations in W
+// (2BS x 2BS), so the columns of Vc are updated once at the end, V_J <- V_J W,
+// one row of V_J per thread. Rotation and skip test are those of the pairwise
+// method: a pair is rotated when |x_p . x_q| > tol sqrt(|x_p|^2 |x_q|^2).
+// Columns past k (and blocks past the last) are absent: zero, never rotated,
+// never written.
+template <int BS>
+__global__ void __launch_bounds__(1024) jacobi_block_kernel(double* __restrict__ Uc, double* __restrict__ Vc, int k,
+                                                            int nbp, int round, int diag, double tol,
+                                                            int* __restrict__ rotated) {
+  constexpr int NC = 2 * BS;
+  extern __shared__ double lds[];
+  double* X = lds;                   // [NC][k]: local column c at X + c k
+  double* W = lds + (size_t)NC * k;  // [NC][NC]: local column c at W + c NC
+  __shared__ int any;
+  const int tid = threadIdx.x, lane = tid & 63, nt = blockDim.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  int P, Q = -1;
+  if (diag)
+    P = blockIdx.x;
+  else
+    rr_pair_g(nbp, round, blockIdx.x, &P, &Q);
+  auto gcol = [&](int c) -> int {
+    const int b = c < BS ? P : Q;
+    const int j = b * BS + (c < BS ? c : c - BS);
+    return (b >= 0 && j < k) ? j : -1;
+  };
+  const int ncols = diag ? BS : NC;
+  for (int idx = tid; idx < ncols * k; idx += nt) {
+    const int c = idx / k, i = idx - c * k;
+    const int j = gcol(c);
+    X[idx] = j >= 0 ? Uc[(int64_t)j * k + i] : 0.0;
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    a += __shfl_xor(a, o, 64);
-    b += __shfl_xor(b, o, 64);
-    g += __shfl_xor(g, o, 64);
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) {
-    red[0][wave] = a;
-    red[1][wave] = b;
-    red[2][wave] = g;
-  }
+  for (int idx = tid; idx < NC * NC; idx += nt) W[idx] = (idx / NC == idx % NC) ? 1.0 : 0.0;
+  if (tid == 0) any = 0;
   __syncthreads();
-  a = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
-  b = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
-  g = ((red[2][0] + red[2][1]) + red[2][2]) + red[2][3];
-  if (!(fabs(g) > tol * sqrt(a * b)) || g == 0.0) return;
-  const double zeta = (b - a) / (2.0 * g);
-  const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-  double* vp = Vc + (int64_t)p * k;
-  double* vq = Vc + (int64_t)q * k;
-  for (int i = threadIdx.x; i < k; i += blockDim.x) {
-    const double x = up[i], y = uq[i];
-    up[i] = c * x - sn * y;
-    uq[i] = sn * x + c * y;
-    const double xv = vp[i], yv = vq[i];
-    vp[i] = c * xv - sn * yv;
-    vq[i] = sn * xv + c * yv;
+
+  const int rounds = diag ? BS - 1 : BS;
+  const int npairs = diag ? BS / 2 : BS;
+  for (int r = 0; r < rounds; ++r) {
+    if (wave < npairs) {
+      int p, q;
+      if (diag) {
+        rr_pair_g(BS, r, wave, &p, &q);
+      } else {
+        p = wave;
+        q = BS + (wave + r) % BS;
+      }
+      double* xp = X + (size_t)p * k;
+      double* xq = X + (size_t)q * k;
+      // the first 8 rows of each lane stay in registers from the dot products
+      // to the rotation; rows past 512 are read again
+      double xr[8], yr[8];
+      double a = 0, b = 0, g = 0;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int i = lane + 64 * t;
+        xr[t] = i < k ? xp[i] : 0.0;
+        yr[t] = i < k ? xq[i] : 0.0;
+        a += xr[t] * xr[t];
+        b += yr[t] * yr[t];
+        g += xr[t] * yr[t];
+      }
+      for (int i = lane + 512; i < k; i += 64) {
+        const double x = xp[i], y = xq[i];
+        a += x * x;
+        b += y * y;
+        g += x * y;
+      }
+      a = wave_sum_dpp(a);
+      b = wave_sum_dpp(b);
+      g = wave_sum_dpp(g);
+      if (fabs(g) > tol * sqrt(a * b) && g != 0.0) {
+        const double zeta = (b - a) / (2.0 * g);
+        const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = lane + 64 * u;
+          if (i < k) {
+            xp[i] = c * xr[u] - sn * yr[u];
+            xq[i] = sn * xr[u] + c * yr[u];
+          }
+        }
+        for (int i = lane + 512; i < k; i += 64) {
+          const double x = xp[i], y = xq[i];
+          xp[i] = c * x - sn * y;
+          xq[i] = sn * x + c * y;
+        }
+        if (lane < NC) {
+          const double x = W[p * NC + lane], y = W[q * NC + lane];
+          W[p * NC + lane] = c * x - sn * y;
+          W[q * NC + lane] = sn * x + c * y;
+        }
+        if (lane == 0) any = 1;
+      }
+    }
+    __syncthreads();
   }
-  if (threadIdx.x == 0) *rotated = 1;
+  if (!any) return;  // nothing rotated: Uc and Vc are unchanged
+  for (int idx = tid; idx < ncols * k; idx += nt) {
+    const int c = idx / k, i = idx - c * k;
+    const int j = gcol(c);
+    if (j >= 0) Uc[(int64_t)j * k + i] = X[idx];
+  }
+  // V_J <- V_J W: thread i keeps row i of the old V_J in registers
+  for (int i = tid; i < k; i += nt) {
+    double v[NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) {
+      const int j = r < ncols ? gcol(r) : -1;
+      v[r] = j >= 0 ? Vc[(int64_t)j * k + i] : 0.0;
+    }
+#pragma unroll 1
+    for (int c = 0; c < ncols; ++c) {
+      const int j = gcol(c);
+      if (j < 0) continue;
+      double acc = 0.0;
+#pragma unroll
+      for (int r = 0; r < NC; ++r) acc += v[r] * W[c * NC + r];
+      Vc[(int64_t)j * k + i] = acc;
+    }
+  }
+  if (tid == 0) *rotated = 1;
 }
 
 // s_j = ||u_j||, U = normalized columns; columns ranked by descending s
@@ -319,13 +426,48 @@ int jacobi_svd_rounds(const double* M, int k, int input_colmajor, double* U, dou
   hipLaunchKernelGGL(jacobi_init_kernel, dim3(grid_for((int64_t)k * k)), dim3(256), 0, st, M, k, input_colmajor, Uc,
                      Vc);
   SK_HIP(hipGetLastError());
-  const int kp = k + (k & 1);
+  // block size: about k / 64 (enough block pairs per round to spread over
+  // the CUs), 2 to 16, and small enough for a visit (2 BS columns of k
+  // doubles + W) to fit in LDS
+  const size_t cap = 160 * 1024;
+  int bs = 16;
+  while (bs > 2 && (bs * 64 > k || ((size_t)2 * bs * k + (size_t)4 * bs * bs) * sizeof(double) > cap)) bs /= 2;
+  const size_t lds = ((size_t)2 * bs * k + (size_t)4 * bs * bs) * sizeof(double);
+  if (lds > cap) {
+    set_error("Jacobi SVD: k too large for the block visits");
+    return SK_E_NOTSUP;
+  }
+  const int nblk = (k + bs - 1) / bs;
+  const int nbp = nblk + (nblk & 1);
+  auto visit = [&](int grid, int round, int diag) -> int {
+    switch (bs) {
+#define SK_JB(B)                                                                                                  \
+  case B:                                                                                                       \
+    SK_HIP(hipFuncSetAttribute((const void*)jacobi_block_kernel<B>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                               (int)lds));                                                                      \
+    hipLaunchKernelGGL(jacobi_block_kernel<B>, dim3(grid), dim3(64 * B), lds, st, Uc, Vc, k, nbp, round, diag,  \
+                       1e-15, flag);                                                                            \
+    break;
+      SK_JB(16)
+      SK_JB(8)
+      SK_JB(4)
+      SK_JB(2)
+#undef SK_JB
+      default:
+        return SK_E_NOTSUP;
+    }
+    SK_HIP(hipGetLastError());
+    return SK_OK;
+  };
   int sw = 0;
   for (; sw < max_sweeps; ++sw) {
     hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, st, flag, 0);
-    for (int r = 0; r < kp - 1; ++r)
-      hipLaunchKernelGGL(jacobi_round_kernel, dim3(kp / 2), dim3(256), 0, st, Uc, Vc, k, r, 1e-15, flag);
-    SK_HIP(hipGetLastError());
+    int rc = visit(nblk, 0, 1);
+    if (rc != SK_OK) return rc;
+    for (int r = 0; r < nbp - 1; ++r) {
+      rc = visit(nbp / 2, r, 0);
+      if (rc != SK_OK) return rc;
+    }
     SK_HIP(hipMemcpyAsync(h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
     SK_HIP(hipStreamSynchronize(st));
     if (*h_flag == 0) {

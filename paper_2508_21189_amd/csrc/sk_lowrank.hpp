@@ -13,7 +13,8 @@ int launch_set_int(int* p, int v, hipStream_t st);
 // Y (c x r) = X^T for X r x c row-major.
 int launch_transpose(const double* X, int64_t r, int64_t c, double* Y, hipStream_t st);
 // One-sided Jacobi SVD M = U diag(s) V^T (k x k; M row-major, or column-major
-// when input_colmajor), one launch per round of pairs; U, V row-major, s
+// when input_colmajor), by block visits (one launch for the diagonal blocks
+// and one per round of block pairs in every sweep); U, V row-major, s
 // descending. work: jacobi_work_doubles(k); flag: one device int; h_flag:
 // pinned host int. Synchronizes the stream once per sweep.
 size_t jacobi_work_doubles(int k);
