@@ -1,8 +1,12 @@
 // Plain library GEMMs (rocBLAS) used by the randomized SVD for its dense
-// products: Y^T Y, Y R^-1, Q^T A, Q U, W^T Q_b^T. Row-major operands are
+// products: Y^T Y, Y R^-1, Q^T A, Q U, W^T Q_b^T. The Gram matrices of the
+// tall factors are split over row chunks (one strided-batched GEMM; the
+// partial Grams are then added in chunk order), since a k x k result alone
+// gives the GPU only (k/128)^2 output tiles to work on. Row-major operands are
 // passed as their column-major transposes (C^T = op(B)^T op(A)^T).
 #include <rocblas/rocblas.h>
 
+#include <algorithm>
 #include <climits>
 
 #include "sk_lowrank.hpp"
@@ -56,6 +60,40 @@ int gemm_rm(sk_sketch* S, int dtype, bool transA, bool transB, int64_t M, int64_
     return SK_E_HIP;
   }
   return SK_OK;
+}
+
+int gram_rm(sk_sketch* S, const double* X, int64_t ldx, int64_t r, int k, double* G, double* part, int max_chunks,
+            hipStream_t st) {
+  int chunks = (int)std::min<int64_t>(max_chunks, std::max<int64_t>(1, r / 512));
+  if (chunks <= 1) return gemm_rm(S, SK_F64, true, false, k, k, r, 1.0, X, ldx, X, ldx, 0.0, G, k, st);
+  const int64_t rc = (r + chunks - 1) / chunks;
+  const int64_t full = r / rc, rem = r - full * rc;
+  if (rc > INT_MAX || ldx > INT_MAX) {
+    set_error("gram: dimension beyond 32-bit range");
+    return SK_E_NOTSUP;
+  }
+  rocblas_handle h;
+  int rc2 = blas_handle(S, &h);
+  if (rc2 != SK_OK) return rc2;
+  if (rocblas_set_stream(h, st) != rocblas_status_success) {
+    set_error("rocblas_set_stream failed");
+    return SK_E_HIP;
+  }
+  const double one = 1.0, zero = 0.0;
+  const rocblas_stride sx = (rocblas_stride)(rc * ldx), sp = (rocblas_stride)k * k;
+  // column-major view: part_c (k x k) = X_c^T X_c with X_c^T = (k x rc, ld ldx)
+  rocblas_status s = rocblas_dgemm_strided_batched(
+      h, rocblas_operation_none, rocblas_operation_transpose, k, k, (rocblas_int)rc, &one, X, (rocblas_int)ldx, sx, X,
+      (rocblas_int)ldx, sx, &zero, part, k, sp, (rocblas_int)full);
+  if (s == rocblas_status_success && rem > 0)
+    s = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, k, k, (rocblas_int)rem, &one,
+                      X + full * rc * ldx, (rocblas_int)ldx, X + full * rc * ldx, (rocblas_int)ldx, &zero,
+                      part + full * sp, k);
+  if (s != rocblas_status_success) {
+    set_error("rocBLAS gemm failed");
+    return SK_E_HIP;
+  }
+  return launch_sum_partials(part, (int)(full + (rem > 0 ? 1 : 0)), (int64_t)k * k, G, st);
 }
 
 }  // namespace sk

@@ -56,8 +56,11 @@ int lowrank_workspace(sk_sketch* S, size_t bytes, char** out) {
   return SK_OK;
 }
 
+constexpr int kGramChunks = 16;
+
 struct OrthBufs {
   double *G, *Rinv, *RinvT, *Rtmp, *Dinv;
+  double* Gpart;  // kGramChunks partial Gram matrices
   int* fail;
 };
 
@@ -70,7 +73,7 @@ int orth_cholqr3(sk_sketch* S, double* X, double* alt, int64_t r, int k, const O
   double* cur = X;
   double* nxt = alt;
   for (int pass = 0; pass < 3; ++pass) {
-    SK_TRY2(gemm_rm(S, SK_F64, true, false, k, k, r, 1.0, cur, k, cur, k, 0.0, b.G, k, st));
+    SK_TRY2(gram_rm(S, cur, k, r, k, b.G, b.Gpart, kGramChunks, st));
     const double coef = pass == 0 ? 11.0 * ((double)r * k + (double)k * (k + 1)) * u : 0.0;
     SK_TRY2(launch_cholesky_upper(b.G, k, coef, b.Dinv, b.fail, st));
     SK_TRY2(launch_trinv(b.G, k, b.Rinv, b.RinvT, st));
@@ -155,6 +158,7 @@ extern "C" int rsvd(sketch_t S, int dtype, int64_t rows, const void* A, int64_t 
     ob.RinvT = c.take<double>((size_t)k * k);
     ob.Rtmp = c.take<double>((size_t)k * k);
     ob.Dinv = c.take<double>(32 * 32);
+    ob.Gpart = c.take<double>((size_t)kGramChunks * k * k);
     ob.fail = c.take<int>(1);
     jflag = c.take<int>(1);
     Racc = c.take<double>((size_t)k * k);

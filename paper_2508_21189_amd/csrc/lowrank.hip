@@ -416,6 +416,20 @@ int launch_transpose(const double* X, int64_t r, int64_t c, double* Y, hipStream
   return SK_OK;
 }
 
+__global__ void sum_partials_kernel(const double* __restrict__ P, int np, int64_t count, double* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int c = 0; c < np; ++c) acc += P[(int64_t)c * count + e];
+    out[e] = acc;
+  }
+}
+
+int launch_sum_partials(const double* P, int np, int64_t count, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(grid_for(count)), dim3(256), 0, st, P, np, count, out);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
 size_t jacobi_work_doubles(int k) { return (size_t)3 * k * k + k; }
 
 int jacobi_svd_rounds(const double* M, int k, int input_colmajor, double* U, double* s, double* V, double* work,

@@ -26,5 +26,11 @@ int jacobi_svd_rounds(const double* M, int k, int input_colmajor, double* U, dou
 int gemm_rm(sk_sketch* S, int dtype, bool transA, bool transB, int64_t M, int64_t N, int64_t K, double alpha,
             const void* A, int64_t lda, const void* B, int64_t ldb, double beta, void* C, int64_t ldc, hipStream_t st);
 void blas_release(sk_sketch* S);
+// G (k x k row-major) = X^T X for X r x k row-major (ld ldx), over at most
+// max_chunks row chunks; part: max_chunks * k * k doubles of scratch.
+int gram_rm(sk_sketch* S, const double* X, int64_t ldx, int64_t r, int k, double* G, double* part, int max_chunks,
+            hipStream_t st);
+// out[e] = sum_c P[c * count + e], c = 0 .. np-1 in order.
+int launch_sum_partials(const double* P, int np, int64_t count, double* out, hipStream_t st);
 
 }  // namespace sk
