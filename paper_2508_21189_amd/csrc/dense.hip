@@ -369,6 +369,84 @@ __global__ void __launch_bounds__(64) trinv_upper_kernel(const double* __restric
   }
 }
 
+// Blocked inverse of an upper-triangular R (k x k row-major, k <= 512), in
+// 32 x 32 blocks. First one wave per diagonal block inverts it (lane c holds
+// column c; the rows of R come by readlane): X_JJ = R_JJ^{-1}. Then one
+// workgroup per column block J forms, for I = J-1 down to 0,
+//   X_IJ = -X_II (sum_{L=I+1..J} R_IL X_LJ),
+// with the column block of X held in LDS. Writes X (upper, zero below) and
+// XT = X^T.
+constexpr int kTb = 32;
+
+__device__ inline double rl64d(double v, int lane) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__global__ void __launch_bounds__(64) trinv_diag_kernel(const double* __restrict__ R, int k, double* __restrict__ X) {
+  const int c = threadIdx.x;
+  const int j0 = blockIdx.x * kTb;
+  const int b = min(kTb, k - j0);
+  double col[kTb];  // col[r] = R[j0 + r][j0 + c]
+#pragma unroll
+  for (int r = 0; r < kTb; ++r) col[r] = (c < b && r < b) ? R[(int64_t)(j0 + r) * k + j0 + c] : 0.0;
+  double x[kTb];
+#pragma unroll
+  for (int i = kTb - 1; i >= 0; --i) {
+    x[i] = 0.0;
+    if (i < b) {
+      double sacc = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int l = i + 1; l < kTb; ++l)
+        if (l < b) sacc -= rl64d(col[i], l) * x[l];
+      x[i] = sacc / rl64d(col[i], i);
+    }
+  }
+  if (c < b) {
+#pragma unroll
+    for (int r = 0; r < kTb; ++r)
+      if (r < b) X[(int64_t)(j0 + r) * k + j0 + c] = x[r];
+  }
+}
+
+__global__ void __launch_bounds__(1024) trinv_cols_kernel(const double* __restrict__ R, int k, double* __restrict__ X,
+                                                          double* __restrict__ XT) {
+  constexpr int XS = kTb + 1;  // LDS row stride of the column block
+  extern __shared__ double Xs[];  // [k][XS]
+  __shared__ double T[kTb][kTb + 1];
+  const int J = blockIdx.x, j0 = J * kTb, bj = min(kTb, k - j0);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int idx = tid; idx < k * kTb; idx += nt) {
+    const int r = idx / kTb, c = idx - r * kTb;
+    Xs[r * XS + c] = (r >= j0 && r < j0 + bj && c < bj) ? X[(int64_t)r * k + j0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int r = tid / kTb, c = tid - (tid / kTb) * kTb;  // 1024 threads: one entry of a 32 x 32 block each
+  for (int I = J - 1; I >= 0; --I) {
+    const int i0 = I * kTb;
+    double sacc = 0.0;
+    const double* Rrow = R + (int64_t)(i0 + r) * k;
+    for (int l = i0 + kTb; l < j0 + bj; ++l) sacc += Rrow[l] * Xs[l * XS + c];
+    T[r][c] = sacc;
+    __syncthreads();
+    double v = 0.0;
+    const double* Xii = X + (int64_t)(i0 + r) * k + i0;
+    for (int m = r; m < kTb; ++m) v += Xii[m] * T[m][c];
+    Xs[(i0 + r) * XS + c] = c < bj ? -v : 0.0;
+    __syncthreads();
+  }
+  for (int idx = tid; idx < k * kTb; idx += nt) {
+    const int rr = idx / kTb, cc = idx - rr * kTb;
+    if (cc < bj) X[(int64_t)rr * k + j0 + cc] = Xs[rr * XS + cc];
+  }
+  for (int idx = tid; idx < k * kTb; idx += nt) {
+    const int cc = idx / k, rr = idx - cc * k;
+    if (cc < bj) XT[(int64_t)(j0 + cc) * k + rr] = Xs[rr * XS + cc];
+  }
+}
+
 __global__ void fill_kernel(double* __restrict__ x, int64_t n, double value) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     x[i] = value;
@@ -431,7 +509,16 @@ int launch_fill(double* x, int64_t n, double value, hipStream_t st) {
 }
 
 int launch_trinv(const double* R, int k, double* X, double* XT, hipStream_t st) {
-  hipLaunchKernelGGL(trinv_upper_kernel, dim3(k), dim3(64), (size_t)k * sizeof(double), st, R, k, X, XT);
+  if (k <= 512) {
+    const int nblk = (k + kTb - 1) / kTb;
+    hipLaunchKernelGGL(trinv_diag_kernel, dim3(nblk), dim3(64), 0, st, R, k, X);
+    SK_HIP(hipGetLastError());
+    const size_t lds = (size_t)k * (kTb + 1) * sizeof(double);
+    SK_HIP(hipFuncSetAttribute((const void*)trinv_cols_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(trinv_cols_kernel, dim3(nblk), dim3(1024), lds, st, R, k, X, XT);
+  } else {
+    hipLaunchKernelGGL(trinv_upper_kernel, dim3(k), dim3(64), (size_t)k * sizeof(double), st, R, k, X, XT);
+  }
   SK_HIP(hipGetLastError());
   return SK_OK;
 }

@@ -12,6 +12,7 @@
 #include "sk_lowrank.hpp"
 
 #include <algorithm>
+#include <cstdlib>
 
 namespace sk {
 
@@ -38,53 +39,68 @@ __global__ void __launch_bounds__(1024) add_trace_shift_kernel(double* __restric
   for (int i = threadIdx.x; i < k; i += blockDim.x) G[(int64_t)i * k + i] += shift;
 }
 
-// Factor the diagonal block [j0, j0 + b) in LDS; write R_dd (upper) back into
-// G and its inverse into Dinv (b x b, stride kCb). *fail = 1 on a
+__device__ inline double rl64(double v, int lane) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Factor the diagonal block [j0, j0 + b) (b <= 32) in one wave; write R_dd
+// (upper) back into G and its inverse into Dinv (b x b, stride kCb). Lane c
+// holds column c of the block in registers; row jj and the pivots are
+// broadcast with readlane, so no step waits on a barrier. *fail = 1 on a
 // non-positive pivot.
-__global__ void __launch_bounds__(256) chol_diag_kernel(double* __restrict__ G, int k, int j0, int b,
-                                                        double* __restrict__ Dinv, int* __restrict__ fail) {
-  __shared__ double L[kCb][kCb + 1];
-  __shared__ double X[kCb][kCb + 1];
-  __shared__ double piv;
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < b * b; idx += blockDim.x) {
-    const int r = idx / b, c = idx - r * b;
-    L[r][c] = G[(int64_t)(j0 + r) * k + j0 + c];
-  }
-  __syncthreads();
-  for (int jj = 0; jj < b; ++jj) {
-    if (tid == 0) {
-      const double p = L[jj][jj];
-      if (!(p > 0.0)) *fail = 1;
-      piv = p > 0.0 ? sqrt(p) : 1.0;
-    }
-    __syncthreads();
-    const double d = piv;
-    if (tid >= jj && tid < b) L[jj][tid] = (tid == jj) ? d : L[jj][tid] / d;
-    __syncthreads();
-    // trailing update of the block: L[i][c] -= L[jj][i] * L[jj][c], jj < i <= c
-    for (int idx = tid; idx < b * b; idx += blockDim.x) {
-      const int i = idx / b, c = idx - i * b;
-      if (i > jj && c >= i) L[i][c] -= L[jj][i] * L[jj][c];
-    }
-    __syncthreads();
-  }
-  // inverse of the upper-triangular R_dd, column by column (thread = column)
-  if (tid < b) {
-    const int j = tid;
-    for (int i = 0; i < b; ++i) X[i][j] = 0.0;
-    X[j][j] = 1.0 / L[j][j];
-    for (int i = j - 1; i >= 0; --i) {
-      double s = 0;
-      for (int l = i + 1; l <= j; ++l) s += L[i][l] * X[l][j];
-      X[i][j] = -s / L[i][i];
+__global__ void __launch_bounds__(64) chol_diag_kernel(double* __restrict__ G, int k, int j0, int b,
+                                                       double* __restrict__ Dinv, int* __restrict__ fail) {
+  const int c = threadIdx.x;
+  double col[kCb];  // col[r] = entry (r, c) of the block
+#pragma unroll
+  for (int r = 0; r < kCb; ++r) col[r] = (c < b && r < b) ? G[(int64_t)(j0 + r) * k + j0 + c] : 0.0;
+  bool bad = false;
+#pragma unroll
+  for (int jj = 0; jj < kCb; ++jj) {
+    if (jj < b) {
+      const double p = rl64(col[jj], jj);
+      bad |= !(p > 0.0);
+      const double d = p > 0.0 ? sqrt(p) : 1.0;
+      if (c == jj)
+        col[jj] = d;
+      else if (c > jj)
+        col[jj] = col[jj] / d;
+      // trailing update: entry (i, c) -= R[jj][i] R[jj][c], jj < i <= c
+#pragma unroll
+      for (int i = jj + 1; i < kCb; ++i) {
+        if (i < b) {
+          const double rji = rl64(col[jj], i);
+          if (c >= i) col[i] -= rji * col[jj];
+        }
+      }
     }
   }
-  __syncthreads();
-  for (int idx = tid; idx < b * b; idx += blockDim.x) {
-    const int r = idx / b, c = idx - r * b;
-    G[(int64_t)(j0 + r) * k + j0 + c] = c >= r ? L[r][c] : 0.0;
-    Dinv[r * kCb + c] = X[r][c];
+  if (bad && c == 0) *fail = 1;
+  // X = R_dd^{-1} (upper), column c per lane, by rows from the bottom:
+  // X[i][c] = (delta_ic - sum_{l > i} R[i][l] X[l][c]) / R[i][i]
+  double x[kCb];
+#pragma unroll
+  for (int i = kCb - 1; i >= 0; --i) {
+    x[i] = 0.0;
+    if (i < b) {
+      double sacc = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int l = i + 1; l < kCb; ++l)
+        if (l < b) sacc -= rl64(col[i], l) * x[l];
+      x[i] = sacc / rl64(col[i], i);
+    }
+  }
+  if (c < b) {
+#pragma unroll
+    for (int r = 0; r < kCb; ++r) {
+      if (r < b) {
+        G[(int64_t)(j0 + r) * k + j0 + c] = c >= r ? col[r] : 0.0;
+        Dinv[r * kCb + c] = x[r];
+      }
+    }
   }
 }
 
@@ -389,7 +405,7 @@ int launch_cholesky_upper(double* G, int k, double shift_coef, double* Dinv, int
   }
   for (int j0 = 0; j0 < k; j0 += kCb) {
     const int b = std::min(kCb, k - j0);
-    hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, st, G, k, j0, b, Dinv, fail);
+    hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(64), 0, st, G, k, j0, b, Dinv, fail);
     const int rest = k - j0 - b;
     if (rest > 0) {
       hipLaunchKernelGGL(chol_panel_kernel, dim3((rest + 255) / 256), dim3(256), 0, st, G, k, j0, b,
@@ -444,8 +460,13 @@ int jacobi_svd_rounds(const double* M, int k, int input_colmajor, double* U, dou
   // the CUs), 2 to 16, and small enough for a visit (2 BS columns of k
   // doubles + W) to fit in LDS
   const size_t cap = 160 * 1024;
-  int bs = 16;
-  while (bs > 2 && (bs * 64 > k || ((size_t)2 * bs * k + (size_t)4 * bs * bs) * sizeof(double) > cap)) bs /= 2;
+  static const int bs_env = [] {
+    const char* v = std::getenv("SKETCH_JACOBI_BS");
+    return v ? std::atoi(v) : 0;
+  }();
+  int bs = (bs_env == 2 || bs_env == 4 || bs_env == 8 || bs_env == 16) ? bs_env : 16;
+  while (bs > 2 && ((bs_env == 0 && bs * 64 > k) || ((size_t)2 * bs * k + (size_t)4 * bs * bs) * sizeof(double) > cap))
+    bs /= 2;
   const size_t lds = ((size_t)2 * bs * k + (size_t)4 * bs * bs) * sizeof(double);
   if (lds > cap) {
     set_error("Jacobi SVD: k too large for the block visits");
