@@ -238,6 +238,54 @@ typedef struct {
 int rsvd(sketch_t S, int dtype, int64_t rows, const void* A, int64_t lda, double* U, int64_t ldu, double* sigma,
          double* Vt, int64_t ldvt, sk_rsvd_info* info, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Generalized Nystrom approximation (Section "Generalized Nystrom
+ * approximation": Alg. 4, outer-product form, and Alg. 5, SVD form).
+ *
+ * A is rows x cols, row-major, dtype SK_F32 or SK_F64, lda >= cols. The two
+ * test matrices are sketch handles: Omega = So^T with So k x cols (k = So's
+ * d, So's n = cols) and Psi = Sp^T with Sp p x rows (p = Sp's d, Sp's n =
+ * rows), k <= p <= min(rows, cols), p <= 4096; the paper recommends
+ * p = ceil(1.5 k).
+ * Y = A Omega is So's column-mode apply, X^T = Psi^T A is Sp's row-mode apply
+ * (both read A once, accumulate in F32 for F32 input and are stored F64),
+ * and Psi^T Y (or Psi^T Q) is Sp's row-mode apply to the rows x k factor.
+ * Small factorizations run in F64 on the device: SVDs by the one-sided
+ * Jacobi method on the tall p x k factors, orthonormal bases (Alg. 5) by
+ * shifted Cholesky QR (a reading: the paper leaves qr_econ open). The
+ * numerical rank is r = #{i : sigma_i > 5 eps sigma_1}, eps = 2^-52. The
+ * workspace belongs to So's handle (it grows on demand). Both calls are
+ * synchronous on `stream` at their end. info may be NULL.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int rank;             /* numerical rank r of Psi^T Y (Alg. 4) or Psi^T Q (Alg. 5) */
+  int jacobi_sweeps;    /* Jacobi sweeps of the small SVDs (summed) */
+  double t_sketch_ms;   /* Y = A Omega and X^T = Psi^T A */
+  double t_core_ms;     /* the small factorizations */
+  double t_factors_ms;  /* F, G (Alg. 4) or U, V (Alg. 5) */
+  double t_total_ms;    /* device time of the whole call */
+} sk_gn_info;
+
+/*
+ * Alg. 4: A ~ F G^T with F = Y V_r Sigma_r^-1 (rows x k, ldf >= k) and
+ * G = X U_r (cols x k, ldg >= k), [U, Sigma, V] = svd_econ(X^T Omega);
+ * columns r.. of F and G are zero. Returns SK_OK, or a negative status with
+ * no output written (invalid shapes, unsupported dtype or kind).
+ */
+int gen_nystrom(sketch_t So, sketch_t Sp, int dtype, int64_t rows, const void* A, int64_t lda, double* F,
+                int64_t ldf, double* G, int64_t ldg, sk_gn_info* info, void* stream);
+
+/*
+ * Alg. 5: A ~ U diag(sigma) V^T with U rows x k (ldu >= k), sigma (k,
+ * descending) and V cols x k (ldv >= k): [Q, ~] = qr_econ(Y), [P, T] =
+ * qr_econ(X), [U1, S1, V1] = svd_econ(Psi^T Q), C = V1_r S1_r^-1 U1_r^T T^T,
+ * [Uh, sigma, Vh] = svd_econ(C), U = Q Uh, V = P Vh. Returns SK_W_RANKDEF
+ * when the Cholesky QR of Y or X met a non-positive pivot (then U, V are
+ * unreliable).
+ */
+int gen_nystrom_svd(sketch_t So, sketch_t Sp, int dtype, int64_t rows, const void* A, int64_t lda, double* U,
+                    int64_t ldu, double* sigma, double* V, int64_t ldv, sk_gn_info* info, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,8 +1,10 @@
-"""Randomized SVD (Alg. 1) and its error measures (oracle; test infrastructure only).
+"""Randomized SVD (Alg. 1), generalized Nystrom (Alg. 4 and 5) and their error
+measures (oracle; test infrastructure only).
 
-Readings where the paper is silent: orth() is Householder QR (numpy/LAPACK);
-svd_econ(B) is LAPACK's SVD; there is no oversampling and no power iteration
-(Alg. 1 has none).
+Readings where the paper is silent: orth() and qr_econ() are Householder QR
+(numpy/LAPACK); svd_econ() is LAPACK's SVD; there is no oversampling and no
+power iteration (Alg. 1 has none); eps_mach in the rank rule of Alg. 4 and 5
+is the FP64 unit roundoff 2^-52.
 """
 import numpy as np
 
@@ -41,3 +43,46 @@ def frobenius_residual(A, Q):
     """||A - Q Q^T A||_F."""
     A = np.asarray(A, dtype=np.float64)
     return np.linalg.norm(A - Q @ (Q.T @ A))
+
+
+EPS_MACH = 2.0 ** -52
+
+
+def _numerical_rank(s, eps):
+    """r = #{i : s_i > 5 eps s_1} (the rank rule of Alg. 4 and 5; s descending)."""
+    return int(np.count_nonzero(s > 5.0 * eps * s[0])) if s.size and s[0] > 0 else 0
+
+
+def gen_nystrom_outer(A, Omega, Psi, eps=EPS_MACH):
+    """Alg. 4 (outer-product form): A ~ F G^T.
+
+    Y = A Omega, X = A^T Psi; [U, S, V] = svd_econ(X^T Omega); r from S;
+    F = Y V(:, :r) S(:r)^-1, G = X U(:, :r). Returns (F, G, r).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    Y = A @ Omega
+    X = A.T @ Psi
+    U, s, Vt = np.linalg.svd(X.T @ Omega, full_matrices=False)
+    r = _numerical_rank(s, eps)
+    F = Y @ (Vt[:r].T / s[:r])
+    G = X @ U[:, :r]
+    return F, G, r
+
+
+def gen_nystrom_svd(A, Omega, Psi, eps=EPS_MACH):
+    """Alg. 5 (SVD form): A ~ U diag(sigma) V^T.
+
+    Y = A Omega, X = A^T Psi; [Q, ~] = qr_econ(Y), [P, T] = qr_econ(X);
+    [U1, S1, V1] = svd_econ(Psi^T Q); r from S1; C = V1_r S1_r^-1 U1_r^T T^T;
+    [Uh, sigma, Vh] = svd_econ(C); U = Q Uh, V = P Vh. Returns (U, sigma, V, r).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    Y = A @ Omega
+    X = A.T @ Psi
+    Q, _ = np.linalg.qr(Y, mode="reduced")
+    P, T = np.linalg.qr(X, mode="reduced")
+    U1, s1, V1t = np.linalg.svd(Psi.T @ Q, full_matrices=False)
+    r = _numerical_rank(s1, eps)
+    C = V1t[:r].T @ ((U1[:, :r].T @ T.T) / s1[:r, None])
+    Uh, sig, Vht = np.linalg.svd(C, full_matrices=False)
+    return Q @ Uh, sig, P @ Vht.T, r

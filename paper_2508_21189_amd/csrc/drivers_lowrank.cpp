@@ -12,6 +12,7 @@
 // Jacobi SVD of R_b^T = Uh diag(s) W^T, so V = Q_b W.
 #include <algorithm>
 #include <cmath>
+#include <string>
 
 #include "sk_dense.hpp"
 #include "sk_drivers.hpp"
@@ -114,6 +115,12 @@ struct Marks {
   }
 };
 
+// Applies a sketch (row mode) into a caller-carved workspace.
+int apply_into(sk_sketch* S, int dtype, int64_t m, const void* A, int64_t lda, double* out, int64_t ldo, void* ws,
+               size_t ws_bytes, hipStream_t st) {
+  return apply_dispatch(S, dtype, m, A, lda, SK_F64, out, ldo, ws, ws_bytes, st);
+}
+
 }  // namespace
 
 }  // namespace sk
@@ -165,7 +172,7 @@ extern "C" int rsvd(sketch_t S, int dtype, int64_t rows, const void* A, int64_t 
     Ut = c.take<double>((size_t)k * k);
     Wt = c.take<double>((size_t)k * k);
     sv = c.take<double>((size_t)k);
-    jw = c.take<double>(jacobi_work_doubles(k));
+    jw = c.take<double>(jacobi_work_doubles(k, k));
   };
   Carve c0;
   carve(c0);
@@ -196,7 +203,7 @@ extern "C" int rsvd(sketch_t S, int dtype, int64_t rows, const void* A, int64_t 
   SK_TRY2(orth_cholqr3(S, Qb, Qb2, cols, k, ob, Racc, &Qbf, st));
   int sweeps = 0;
   // R_b^T = Uh diag(s) W^T: the column-major view of R_b's memory is R_b^T
-  SK_TRY2(jacobi_svd_rounds(Racc, k, 1, Ut, sv, Wt, jw, jflag, h + 1, 40, &sweeps, st));
+  SK_TRY2(jacobi_svd_rounds(Racc, k, k, 1, Ut, sv, Wt, jw, jflag, h + 1, 40, &sweeps, st));
   SK_HIP(hipMemcpyAsync(sigma, sv, sizeof(double) * k, hipMemcpyDeviceToDevice, st));
   if (U) SK_TRY2(gemm_rm(S, SK_F64, false, false, rows, k, k, 1.0, Q, k, Ut, k, 0.0, U, ldu, st));
   if (Vt) SK_TRY2(gemm_rm(S, SK_F64, true, true, k, cols, k, 1.0, Wt, k, Qbf, k, 0.0, Vt, ldvt, st));
@@ -213,6 +220,218 @@ extern "C" int rsvd(sketch_t S, int dtype, int64_t rows, const void* A, int64_t 
   }
   if (*h) {
     set_error("rsvd: Cholesky QR met a non-positive pivot (the sketch is numerically rank deficient)");
+    return SK_W_RANKDEF;
+  }
+  return SK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Generalized Nystrom (Alg. 4 and Alg. 5). Omega = So^T (cols x k), Psi =
+// Sp^T (rows x p): Y = A Omega is the column-mode apply of So, X^T = Psi^T A
+// the row-mode apply of Sp, and Psi^T Y (or Psi^T Q) the row-mode apply of Sp
+// to the n x k factor.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct GnCheck {
+  int64_t cols;
+  int k, p;
+};
+
+int gn_check(const char* who, sketch_t So, sketch_t Sp, int dtype, int64_t rows, const void* A, int64_t lda,
+             GnCheck* c) {
+  if (!So || !Sp || !A || rows < 1 || (dtype != SK_F64 && dtype != SK_F32)) {
+    set_error(std::string(who) + ": invalid argument");
+    return SK_E_INVAL;
+  }
+  c->cols = So->n;
+  c->k = (int)So->d;
+  c->p = (int)Sp->d;
+  if (Sp->n != rows || lda < c->cols || c->k > c->p || (int64_t)c->p > rows || (int64_t)c->p > c->cols ||
+      c->k > 4096 || c->p > 4096) {
+    set_error(std::string(who) +
+              ": need Omega^T = So (k x cols), Psi^T = Sp (p x rows), k <= p <= min(rows, cols), p <= 4096, "
+              "lda >= cols");
+    return SK_E_INVAL;
+  }
+  return SK_OK;
+}
+
+}  // namespace
+
+extern "C" int gen_nystrom(sketch_t So, sketch_t Sp, int dtype, int64_t rows, const void* A, int64_t lda, double* F,
+                           int64_t ldf, double* G, int64_t ldg, sk_gn_info* info, void* stream) {
+  GnCheck c;
+  SK_TRY2(gn_check("gen_nystrom", So, Sp, dtype, rows, A, lda, &c));
+  if (!F || !G || ldf < c.k || ldg < c.k) {
+    set_error("gen_nystrom: F (rows x k, ldf >= k) and G (cols x k, ldg >= k) are required");
+    return SK_E_INVAL;
+  }
+  const int k = c.k, p = c.p;
+  const int64_t cols = c.cols;
+  hipStream_t st = (hipStream_t)stream;
+  size_t wT = 0, wA = 0, wY = 0;
+  SK_TRY2(apply_workspace(So, 1, dtype, rows, &wT));
+  SK_TRY2(apply_workspace(Sp, 0, dtype, cols, &wA));
+  SK_TRY2(apply_workspace(Sp, 0, SK_F64, k, &wY));
+  void *awT, *awA, *awY;
+  double *Y, *Xt, *M, *Um, *sv, *Vm, *jw, *Vs, *Ur;
+  int *jflag, *rk;
+  auto carve = [&](Carve& cv) {
+    awT = cv.take<char>(wT);
+    awA = cv.take<char>(wA);
+    awY = cv.take<char>(wY);
+    Y = cv.take<double>((size_t)rows * k);
+    Xt = cv.take<double>((size_t)p * cols);
+    M = cv.take<double>((size_t)p * k);
+    Um = cv.take<double>((size_t)p * k);
+    sv = cv.take<double>(k);
+    Vm = cv.take<double>((size_t)k * k);
+    jw = cv.take<double>(jacobi_work_doubles(p, k));
+    Vs = cv.take<double>((size_t)k * k);
+    Ur = cv.take<double>((size_t)p * k);
+    jflag = cv.take<int>(1);
+    rk = cv.take<int>(1);
+  };
+  Carve c0;
+  carve(c0);
+  char* base = nullptr;
+  SK_TRY2(lowrank_workspace(So, c0.off, &base));
+  Carve c1{base, 0};
+  carve(c1);
+  int* h = static_cast<int*>(So->h_pinned);
+
+  Marks mk(st);
+  SK_TRY2(mk.mark());  // 0
+  SK_TRY2(apply_T_dispatch(So, dtype, rows, A, lda, SK_F64, Y, k, awT, wT, st));
+  SK_TRY2(apply_into(Sp, dtype, cols, A, lda, Xt, cols, awA, wA, st));
+  SK_TRY2(mk.mark());  // 1: both sketches of A
+  SK_TRY2(apply_into(Sp, SK_F64, k, Y, k, M, k, awY, wY, st));  // Psi^T Y = X^T Omega
+  int sweeps = 0;
+  SK_TRY2(jacobi_svd_rounds(M, p, k, 0, Um, sv, Vm, jw, jflag, h + 1, 60, &sweeps, st));
+  SK_TRY2(launch_gn_truncate(sv, k, Vm, Vs, Um, p, Ur, rk, st));
+  SK_TRY2(mk.mark());  // 2: core
+  SK_TRY2(gemm_rm(So, SK_F64, false, false, rows, k, k, 1.0, Y, k, Vs, k, 0.0, F, ldf, st));     // F = Y V_r S_r^-1
+  SK_TRY2(gemm_rm(So, SK_F64, true, false, cols, k, p, 1.0, Xt, cols, Ur, k, 0.0, G, ldg, st));  // G = X U_r
+  SK_TRY2(mk.mark());  // 3: factors
+  SK_HIP(hipMemcpyAsync(h, rk, sizeof(int), hipMemcpyDeviceToHost, st));
+  SK_HIP(hipStreamSynchronize(st));
+  if (info) {
+    info->rank = *h;
+    info->t_sketch_ms = mk.ms(0, 1);
+    info->t_core_ms = mk.ms(1, 2);
+    info->t_factors_ms = mk.ms(2, 3);
+    info->t_total_ms = mk.ms(0, 3);
+    info->jacobi_sweeps = sweeps;
+  }
+  return SK_OK;
+}
+
+extern "C" int gen_nystrom_svd(sketch_t So, sketch_t Sp, int dtype, int64_t rows, const void* A, int64_t lda,
+                               double* U, int64_t ldu, double* sigma, double* V, int64_t ldv, sk_gn_info* info,
+                               void* stream) {
+  GnCheck c;
+  SK_TRY2(gn_check("gen_nystrom_svd", So, Sp, dtype, rows, A, lda, &c));
+  if (!U || !sigma || !V || ldu < c.k || ldv < c.k) {
+    set_error("gen_nystrom_svd: U (rows x k, ldu >= k), sigma (k) and V (cols x k, ldv >= k) are required");
+    return SK_E_INVAL;
+  }
+  const int k = c.k, p = c.p;
+  const int64_t cols = c.cols;
+  hipStream_t st = (hipStream_t)stream;
+  size_t wT = 0, wA = 0, wY = 0;
+  SK_TRY2(apply_workspace(So, 1, dtype, rows, &wT));
+  SK_TRY2(apply_workspace(Sp, 0, dtype, cols, &wA));
+  SK_TRY2(apply_workspace(Sp, 0, SK_F64, k, &wY));
+  void *awT, *awA, *awY;
+  double *Y, *Y2, *Xt, *Xb, *Xb2, *T, *M1, *U1, *s1, *V1, *jw, *Vs, *U1r, *W1, *C, *Uc, *sc, *Vc;
+  OrthBufs ok_, op_;
+  int *jflag, *rk;
+  auto orth_bufs = [&](Carve& cv, OrthBufs& o, int n) {
+    o.G = cv.take<double>((size_t)n * n);
+    o.Rinv = cv.take<double>((size_t)n * n);
+    o.RinvT = cv.take<double>((size_t)n * n);
+    o.Rtmp = cv.take<double>((size_t)n * n);
+    o.Dinv = cv.take<double>(32 * 32);
+    o.Gpart = cv.take<double>((size_t)kGramChunks * n * n);
+    o.fail = cv.take<int>(1);
+  };
+  auto carve = [&](Carve& cv) {
+    awT = cv.take<char>(wT);
+    awA = cv.take<char>(wA);
+    awY = cv.take<char>(wY);
+    Y = cv.take<double>((size_t)rows * k);
+    Y2 = cv.take<double>((size_t)rows * k);
+    Xt = cv.take<double>((size_t)p * cols);
+    Xb = cv.take<double>((size_t)cols * p);
+    Xb2 = cv.take<double>((size_t)cols * p);
+    T = cv.take<double>((size_t)p * p);
+    M1 = cv.take<double>((size_t)p * k);
+    U1 = cv.take<double>((size_t)p * k);
+    s1 = cv.take<double>(k);
+    V1 = cv.take<double>((size_t)k * k);
+    jw = cv.take<double>(jacobi_work_doubles(p, k));
+    Vs = cv.take<double>((size_t)k * k);
+    U1r = cv.take<double>((size_t)p * k);
+    W1 = cv.take<double>((size_t)k * p);
+    C = cv.take<double>((size_t)k * p);
+    Uc = cv.take<double>((size_t)p * k);
+    sc = cv.take<double>(k);
+    Vc = cv.take<double>((size_t)k * k);
+    orth_bufs(cv, ok_, k);
+    orth_bufs(cv, op_, p);
+    jflag = cv.take<int>(1);
+    rk = cv.take<int>(1);
+  };
+  Carve c0;
+  carve(c0);
+  char* base = nullptr;
+  SK_TRY2(lowrank_workspace(So, c0.off, &base));
+  Carve c1{base, 0};
+  carve(c1);
+  int* h = static_cast<int*>(So->h_pinned);
+
+  Marks mk(st);
+  SK_TRY2(mk.mark());  // 0
+  SK_TRY2(launch_set_int(ok_.fail, 0, st));
+  SK_TRY2(launch_set_int(op_.fail, 0, st));
+  SK_TRY2(apply_T_dispatch(So, dtype, rows, A, lda, SK_F64, Y, k, awT, wT, st));
+  SK_TRY2(apply_into(Sp, dtype, cols, A, lda, Xt, cols, awA, wA, st));
+  SK_TRY2(mk.mark());  // 1: both sketches of A
+  double* Q = nullptr;
+  SK_TRY2(orth_cholqr3(So, Y, Y2, rows, k, ok_, nullptr, &Q, st));  // [Q, ~] = qr_econ(Y)
+  SK_TRY2(launch_transpose(Xt, p, cols, Xb, st));                   // X = A^T Psi (cols x p)
+  double* P = nullptr;
+  SK_TRY2(orth_cholqr3(So, Xb, Xb2, cols, p, op_, T, &P, st));     // [P, T] = qr_econ(X)
+  SK_TRY2(apply_into(Sp, SK_F64, k, Q, k, M1, k, awY, wY, st));    // Psi^T Q
+  int sw1 = 0, sw2 = 0;
+  SK_TRY2(jacobi_svd_rounds(M1, p, k, 0, U1, s1, V1, jw, jflag, h + 1, 60, &sw1, st));
+  SK_TRY2(launch_gn_truncate(s1, k, V1, Vs, U1, p, U1r, rk, st));
+  // C = V1_r S1_r^-1 U1_r^T T^T = Vs (T U1r)^T
+  SK_TRY2(gemm_rm(So, SK_F64, true, true, k, p, p, 1.0, U1r, k, T, p, 0.0, W1, p, st));
+  SK_TRY2(gemm_rm(So, SK_F64, false, false, k, p, k, 1.0, Vs, k, W1, p, 0.0, C, p, st));
+  // svd_econ(C), C k x p: the Jacobi SVD of C^T (the column-major view of C)
+  // gives C^T = Uc diag(sc) Vc^T, i.e. C = Vc diag(sc) Uc^T
+  SK_TRY2(jacobi_svd_rounds(C, p, k, 1, Uc, sc, Vc, jw, jflag, h + 1, 60, &sw2, st));
+  SK_TRY2(mk.mark());  // 2: core
+  SK_HIP(hipMemcpyAsync(sigma, sc, sizeof(double) * k, hipMemcpyDeviceToDevice, st));
+  SK_TRY2(gemm_rm(So, SK_F64, false, false, rows, k, k, 1.0, Q, k, Vc, k, 0.0, U, ldu, st));  // U = Q Uhat
+  SK_TRY2(gemm_rm(So, SK_F64, false, false, cols, k, p, 1.0, P, p, Uc, k, 0.0, V, ldv, st));  // V = P Vhat
+  SK_TRY2(mk.mark());  // 3: factors
+  SK_HIP(hipMemcpyAsync(h, rk, sizeof(int), hipMemcpyDeviceToHost, st));
+  SK_HIP(hipMemcpyAsync(h + 2, ok_.fail, sizeof(int), hipMemcpyDeviceToHost, st));
+  SK_HIP(hipMemcpyAsync(h + 3, op_.fail, sizeof(int), hipMemcpyDeviceToHost, st));
+  SK_HIP(hipStreamSynchronize(st));
+  if (info) {
+    info->rank = h[0];
+    info->t_sketch_ms = mk.ms(0, 1);
+    info->t_core_ms = mk.ms(1, 2);
+    info->t_factors_ms = mk.ms(2, 3);
+    info->t_total_ms = mk.ms(0, 3);
+    info->jacobi_sweeps = sw1 + sw2;
+  }
+  if (h[2] || h[3]) {
+    set_error("gen_nystrom_svd: Cholesky QR of Y or X met a non-positive pivot (numerically rank deficient)");
     return SK_W_RANKDEF;
   }
   return SK_OK;

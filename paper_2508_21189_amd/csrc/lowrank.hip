@@ -12,6 +12,7 @@
 #include "sk_lowrank.hpp"
 
 #include <algorithm>
+#include <climits>
 #include <cstdlib>
 
 namespace sk {
@@ -172,15 +173,19 @@ __global__ void zero_lower_kernel(double* __restrict__ R, int k) {
 // Jacobi SVD, one workgroup per column pair
 // ---------------------------------------------------------------------------
 // Uc, Vc: column-major working copies (column j at j * k).
-__global__ void jacobi_init_kernel(const double* __restrict__ M, int k, int input_colmajor, double* __restrict__ Uc,
-                                   double* __restrict__ Vc) {
-  const int64_t total = (int64_t)k * k;
+// Uc (k columns of length rows) = M (rows x k; row-major, or column-major
+// when input_colmajor), Vc (k columns of length k) = I.
+__global__ void jacobi_init_kernel(const double* __restrict__ M, int rows, int k, int input_colmajor,
+                                   double* __restrict__ Uc, double* __restrict__ Vc) {
+  const int64_t total = (int64_t)rows * k;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t col = idx / k, row = idx - col * k;
+    const int64_t col = idx / rows, row = idx - col * rows;
     Uc[idx] = input_colmajor ? M[idx] : M[row * k + col];
-    Vc[idx] = row == col ? 1.0 : 0.0;
   }
+  const int64_t tv = (int64_t)k * k;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tv; idx += (int64_t)gridDim.x * blockDim.x)
+    Vc[idx] = (idx / k == idx % k) ? 1.0 : 0.0;
 }
 
 __device__ inline void rr_pair_g(int kp, int r, int i, int* p, int* q) {
@@ -230,13 +235,13 @@ __device__ inline double wave_sum_dpp(double v) {
 // Columns past k (and blocks past the last) are absent: zero, never rotated,
 // never written.
 template <int BS>
-__global__ void __launch_bounds__(1024) jacobi_block_kernel(double* __restrict__ Uc, double* __restrict__ Vc, int k,
-                                                            int nbp, int round, int diag, double tol,
+__global__ void __launch_bounds__(1024) jacobi_block_kernel(double* __restrict__ Uc, double* __restrict__ Vc, int rows,
+                                                            int k, int nbp, int round, int diag, double tol,
                                                             int* __restrict__ rotated) {
   constexpr int NC = 2 * BS;
   extern __shared__ double lds[];
-  double* X = lds;                   // [NC][k]: local column c at X + c k
-  double* W = lds + (size_t)NC * k;  // [NC][NC]: local column c at W + c NC
+  double* X = lds;                      // [NC][rows]: local column c at X + c rows
+  double* W = lds + (size_t)NC * rows;  // [NC][NC]: local column c at W + c NC
   __shared__ int any;
   const int tid = threadIdx.x, lane = tid & 63, nt = blockDim.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -251,10 +256,10 @@ __global__ void __launch_bounds__(1024) jacobi_block_kernel(double* __restrict__
     return (b >= 0 && j < k) ? j : -1;
   };
   const int ncols = diag ? BS : NC;
-  for (int idx = tid; idx < ncols * k; idx += nt) {
-    const int c = idx / k, i = idx - c * k;
+  for (int idx = tid; idx < ncols * rows; idx += nt) {
+    const int c = idx / rows, i = idx - c * rows;
     const int j = gcol(c);
-    X[idx] = j >= 0 ? Uc[(int64_t)j * k + i] : 0.0;
+    X[idx] = j >= 0 ? Uc[(int64_t)j * rows + i] : 0.0;
   }
   for (int idx = tid; idx < NC * NC; idx += nt) W[idx] = (idx / NC == idx % NC) ? 1.0 : 0.0;
   if (tid == 0) any = 0;
@@ -271,8 +276,8 @@ __global__ void __launch_bounds__(1024) jacobi_block_kernel(double* __restrict__
         p = wave;
         q = BS + (wave + r) % BS;
       }
-      double* xp = X + (size_t)p * k;
-      double* xq = X + (size_t)q * k;
+      double* xp = X + (size_t)p * rows;
+      double* xq = X + (size_t)q * rows;
       // the first 8 rows of each lane stay in registers from the dot products
       // to the rotation; rows past 512 are read again
       double xr[8], yr[8];
@@ -280,13 +285,13 @@ __global__ void __launch_bounds__(1024) jacobi_block_kernel(double* __restrict__
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
         const int i = lane + 64 * t;
-        xr[t] = i < k ? xp[i] : 0.0;
-        yr[t] = i < k ? xq[i] : 0.0;
+        xr[t] = i < rows ? xp[i] : 0.0;
+        yr[t] = i < rows ? xq[i] : 0.0;
         a += xr[t] * xr[t];
         b += yr[t] * yr[t];
         g += xr[t] * yr[t];
       }
-      for (int i = lane + 512; i < k; i += 64) {
+      for (int i = lane + 512; i < rows; i += 64) {
         const double x = xp[i], y = xq[i];
         a += x * x;
         b += y * y;
@@ -302,12 +307,12 @@ __global__ void __launch_bounds__(1024) jacobi_block_kernel(double* __restrict__
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int i = lane + 64 * u;
-          if (i < k) {
+          if (i < rows) {
             xp[i] = c * xr[u] - sn * yr[u];
             xq[i] = sn * xr[u] + c * yr[u];
           }
         }
-        for (int i = lane + 512; i < k; i += 64) {
+        for (int i = lane + 512; i < rows; i += 64) {
           const double x = xp[i], y = xq[i];
           xp[i] = c * x - sn * y;
           xq[i] = sn * x + c * y;
@@ -323,10 +328,10 @@ __global__ void __launch_bounds__(1024) jacobi_block_kernel(double* __restrict__
     __syncthreads();
   }
   if (!any) return;  // nothing rotated: Uc and Vc are unchanged
-  for (int idx = tid; idx < ncols * k; idx += nt) {
-    const int c = idx / k, i = idx - c * k;
+  for (int idx = tid; idx < ncols * rows; idx += nt) {
+    const int c = idx / rows, i = idx - c * rows;
     const int j = gcol(c);
-    if (j >= 0) Uc[(int64_t)j * k + i] = X[idx];
+    if (j >= 0) Uc[(int64_t)j * rows + i] = X[idx];
   }
   // V_J <- V_J W: thread i keeps row i of the old V_J in registers
   for (int i = tid; i < k; i += nt) {
@@ -352,14 +357,14 @@ __global__ void __launch_bounds__(1024) jacobi_block_kernel(double* __restrict__
 // s_j = ||u_j||, U = normalized columns; columns ranked by descending s
 // (ties by index); U, V written row-major k x k.
 __global__ void __launch_bounds__(1024) jacobi_finish_kernel(const double* __restrict__ Uc,
-                                                             const double* __restrict__ Vc, int k,
+                                                             const double* __restrict__ Vc, int rows, int k,
                                                              double* __restrict__ U, double* __restrict__ s,
                                                              double* __restrict__ V, double* __restrict__ sig) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   for (int j = wave; j < k; j += nw) {
-    const double* uj = Uc + (int64_t)j * k;
+    const double* uj = Uc + (int64_t)j * rows;
     double a = 0;
-    for (int i = lane; i < k; i += 64) a += uj[i] * uj[i];
+    for (int i = lane; i < rows; i += 64) a += uj[i] * uj[i];
     for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
     if (lane == 0) sig[j] = sqrt(a);
   }
@@ -370,10 +375,8 @@ __global__ void __launch_bounds__(1024) jacobi_finish_kernel(const double* __res
     for (int i = 0; i < k; ++i) rank += (sig[i] > sj) || (sig[i] == sj && i < j);
     s[rank] = sj;
     const double inv = sj > 0 ? 1.0 / sj : 0.0;
-    for (int row = 0; row < k; ++row) {
-      U[(int64_t)row * k + rank] = Uc[(int64_t)j * k + row] * inv;
-      V[(int64_t)row * k + rank] = Vc[(int64_t)j * k + row];
-    }
+    for (int row = 0; row < rows; ++row) U[(int64_t)row * k + rank] = Uc[(int64_t)j * rows + row] * inv;
+    for (int row = 0; row < k; ++row) V[(int64_t)row * k + rank] = Vc[(int64_t)j * k + row];
   }
 }
 
@@ -446,15 +449,54 @@ int launch_sum_partials(const double* P, int np, int64_t count, double* out, hip
   return SK_OK;
 }
 
-size_t jacobi_work_doubles(int k) { return (size_t)3 * k * k + k; }
+// Numerical rank r = #{i : s_i > 5 eps s_0} (eps = 2^-52, s descending) and
+// the truncated factors: Vs[i][j] = V[i][j] / s_j and Ur[i][j] = U[i][j] for
+// j < r, zero for j >= r (V k x k, U p x k, row-major). One workgroup.
+__global__ void __launch_bounds__(256) gn_truncate_kernel(const double* __restrict__ s, int k,
+                                                          const double* __restrict__ V, double* __restrict__ Vs,
+                                                          const double* __restrict__ U, int p, double* __restrict__ Ur,
+                                                          int* __restrict__ rank) {
+  __shared__ int r_sh;
+  if (threadIdx.x == 0) {
+    const double thr = 5.0 * 0x1p-52 * s[0];
+    int r = 0;
+    while (r < k && s[r] > thr) ++r;
+    r_sh = r;
+    *rank = r;
+  }
+  __syncthreads();
+  const int r = r_sh;
+  for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
+    const int j = idx % k;
+    Vs[idx] = j < r ? V[idx] / s[j] : 0.0;
+  }
+  for (int idx = threadIdx.x; idx < p * k; idx += blockDim.x) {
+    const int j = idx % k;
+    Ur[idx] = j < r ? U[idx] : 0.0;
+  }
+}
 
-int jacobi_svd_rounds(const double* M, int k, int input_colmajor, double* U, double* s, double* V, double* work,
-                      int* flag, int* h_flag, int max_sweeps, int* sweeps, hipStream_t st) {
+int launch_gn_truncate(const double* s, int k, const double* V, double* Vs, const double* U, int p, double* Ur,
+                       int* rank, hipStream_t st) {
+  hipLaunchKernelGGL(gn_truncate_kernel, dim3(1), dim3(256), 0, st, s, k, V, Vs, U, p, Ur, rank);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+size_t jacobi_work_doubles(int64_t rows, int k) { return (size_t)rows * k + (size_t)k * k + k; }
+
+int jacobi_svd_rounds(const double* M, int64_t rows, int k, int input_colmajor, double* U, double* s, double* V,
+                      double* work, int* flag, int* h_flag, int max_sweeps, int* sweeps, hipStream_t st) {
+  if (rows < k || rows > INT_MAX) {
+    set_error("Jacobi SVD: need k <= rows");
+    return SK_E_INVAL;
+  }
+  const int nr = (int)rows;
   double* Uc = work;
-  double* Vc = work + (size_t)k * k;
-  double* sig = work + (size_t)2 * k * k;
-  hipLaunchKernelGGL(jacobi_init_kernel, dim3(grid_for((int64_t)k * k)), dim3(256), 0, st, M, k, input_colmajor, Uc,
-                     Vc);
+  double* Vc = work + (size_t)nr * k;
+  double* sig = Vc + (size_t)k * k;
+  hipLaunchKernelGGL(jacobi_init_kernel, dim3(grid_for((int64_t)nr * k)), dim3(256), 0, st, M, nr, k, input_colmajor,
+                     Uc, Vc);
   SK_HIP(hipGetLastError());
   // block size: about k / 64 (enough block pairs per round to spread over
   // the CUs), 2 to 16, and small enough for a visit (2 BS columns of k
@@ -465,11 +507,12 @@ int jacobi_svd_rounds(const double* M, int k, int input_colmajor, double* U, dou
     return v ? std::atoi(v) : 0;
   }();
   int bs = (bs_env == 2 || bs_env == 4 || bs_env == 8 || bs_env == 16) ? bs_env : 16;
-  while (bs > 2 && ((bs_env == 0 && bs * 64 > k) || ((size_t)2 * bs * k + (size_t)4 * bs * bs) * sizeof(double) > cap))
+  while (bs > 2 &&
+         ((bs_env == 0 && bs * 64 > k) || ((size_t)2 * bs * nr + (size_t)4 * bs * bs) * sizeof(double) > cap))
     bs /= 2;
-  const size_t lds = ((size_t)2 * bs * k + (size_t)4 * bs * bs) * sizeof(double);
+  const size_t lds = ((size_t)2 * bs * nr + (size_t)4 * bs * bs) * sizeof(double);
   if (lds > cap) {
-    set_error("Jacobi SVD: k too large for the block visits");
+    set_error("Jacobi SVD: columns too long for the block visits");
     return SK_E_NOTSUP;
   }
   const int nblk = (k + bs - 1) / bs;
@@ -480,8 +523,8 @@ int jacobi_svd_rounds(const double* M, int k, int input_colmajor, double* U, dou
   case B:                                                                                                       \
     SK_HIP(hipFuncSetAttribute((const void*)jacobi_block_kernel<B>, hipFuncAttributeMaxDynamicSharedMemorySize, \
                                (int)lds));                                                                      \
-    hipLaunchKernelGGL(jacobi_block_kernel<B>, dim3(grid), dim3(64 * B), lds, st, Uc, Vc, k, nbp, round, diag,  \
-                       1e-15, flag);                                                                            \
+    hipLaunchKernelGGL(jacobi_block_kernel<B>, dim3(grid), dim3(64 * B), lds, st, Uc, Vc, nr, k, nbp, round,    \
+                       diag, 1e-15, flag);                                                                            \
     break;
       SK_JB(16)
       SK_JB(8)
@@ -511,8 +554,8 @@ int jacobi_svd_rounds(const double* M, int k, int input_colmajor, double* U, dou
     }
   }
   if (sweeps) *sweeps = sw;
-  hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(1024), 0, st, (const double*)Uc, (const double*)Vc, k, U, s,
-                     V, sig);
+  hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(1024), 0, st, (const double*)Uc, (const double*)Vc, nr, k, U,
+                     s, V, sig);
   SK_HIP(hipGetLastError());
   return SK_OK;
 }

@@ -12,14 +12,22 @@ int launch_cholesky_upper(double* G, int k, double shift_coef, double* Dinv, int
 int launch_set_int(int* p, int v, hipStream_t st);
 // Y (c x r) = X^T for X r x c row-major.
 int launch_transpose(const double* X, int64_t r, int64_t c, double* Y, hipStream_t st);
-// One-sided Jacobi SVD M = U diag(s) V^T (k x k; M row-major, or column-major
-// when input_colmajor), by block visits (one launch for the diagonal blocks
-// and one per round of block pairs in every sweep); U, V row-major, s
-// descending. work: jacobi_work_doubles(k); flag: one device int; h_flag:
-// pinned host int. Synchronizes the stream once per sweep.
-size_t jacobi_work_doubles(int k);
-int jacobi_svd_rounds(const double* M, int k, int input_colmajor, double* U, double* s, double* V, double* work,
-                      int* flag, int* h_flag, int max_sweeps, int* sweeps, hipStream_t st);
+// One-sided Jacobi SVD M = U diag(s) V^T of a rows x k matrix (rows >= k; M
+// row-major, or column-major when input_colmajor), by block visits (one
+// launch for the diagonal blocks and one per round of block pairs in every
+// sweep); U (rows x k) and V (k x k) row-major, s descending. Columns of U
+// whose singular value is 0 are 0. work: jacobi_work_doubles(rows, k); flag:
+// one device int; h_flag: pinned host int. Synchronizes the stream once per
+// sweep.
+size_t jacobi_work_doubles(int64_t rows, int k);
+int jacobi_svd_rounds(const double* M, int64_t rows, int k, int input_colmajor, double* U, double* s, double* V,
+                      double* work, int* flag, int* h_flag, int max_sweeps, int* sweeps, hipStream_t st);
+
+// Numerical rank r = #{i : s_i > 5 eps s_0} of a descending s (k), written to
+// *rank (device), and the truncated factors Vs = V[:, :r] diag(1/s[:r]) and
+// Ur = U[:, :r] (zero past r; V k x k, U p x k, row-major).
+int launch_gn_truncate(const double* s, int k, const double* V, double* Vs, const double* U, int p, double* Ur,
+                       int* rank, hipStream_t st);
 
 // Row-major GEMM on the handle's rocBLAS handle and stream:
 // C (M x N) = alpha op(A) op(B) + beta C; dtype SK_F64 or SK_F32.

@@ -90,6 +90,12 @@ class RsvdInfo(ctypes.Structure):
                 ("t_svd_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double), ("jacobi_sweeps", ctypes.c_int)]
 
 
+class GnInfo(ctypes.Structure):
+    """sk_gn_info."""
+    _fields_ = [("rank", ctypes.c_int), ("jacobi_sweeps", ctypes.c_int), ("t_sketch_ms", ctypes.c_double),
+                ("t_core_ms", ctypes.c_double), ("t_factors_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
+
+
 def _as_dict(st):
     return {name: getattr(st, name) for name, _ in st._fields_}
 
@@ -100,6 +106,9 @@ _DRIVER_SIGS = {
                              ctypes.c_int, ctypes.POINTER(LsqrInfo), _vp],
     "lstsq_residual": [_vp, _i64, _vp, _i64, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp],
     "rsvd": [_vp, ctypes.c_int, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, ctypes.POINTER(RsvdInfo), _vp],
+    "gen_nystrom": [_vp, _vp, ctypes.c_int, _i64, _vp, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(GnInfo), _vp],
+    "gen_nystrom_svd": [_vp, _vp, ctypes.c_int, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, ctypes.POINTER(GnInfo),
+                        _vp],
 }
 
 
@@ -259,3 +268,32 @@ class Sketch:
                                _ptr(sig), _ptr(Vt) if Vt is not None else None, self.n,
                                ctypes.byref(info), _stream(stream)))
         return U, sig, Vt, rc, _as_dict(info)
+
+
+def gen_nystrom(S_omega, S_psi, A, form="outer", stream=None):
+    """Generalized Nystrom with Omega = S_omega^T (k x cols sketch) and Psi = S_psi^T (p x rows sketch).
+
+    form "outer" (Alg. 4): returns (F, G, status, info), A ~ F G^T.
+    form "svd" (Alg. 5): returns (U, sigma, V, status, info), A ~ U diag(sigma) V^T.
+    """
+    assert A.is_cuda and A.dim() == 2 and A.stride(1) == 1 and A.dtype in (torch.float32, torch.float64)
+    rows, cols = A.shape
+    assert S_omega.n == cols and S_psi.n == rows
+    k = S_omega.d
+    dev = A.device
+    info = GnInfo()
+    lib = load()
+    if form == "outer":
+        F = torch.empty((rows, k), dtype=torch.float64, device=dev)
+        G = torch.empty((cols, k), dtype=torch.float64, device=dev)
+        rc = check(lib.gen_nystrom(S_omega.h, S_psi.h, _DT[A.dtype], rows, _ptr(A), A.stride(0), _ptr(F), k, _ptr(G),
+                                   k, ctypes.byref(info), _stream(stream)))
+        return F, G, rc, _as_dict(info)
+    if form == "svd":
+        U = torch.empty((rows, k), dtype=torch.float64, device=dev)
+        V = torch.empty((cols, k), dtype=torch.float64, device=dev)
+        sig = torch.empty(k, dtype=torch.float64, device=dev)
+        rc = check(lib.gen_nystrom_svd(S_omega.h, S_psi.h, _DT[A.dtype], rows, _ptr(A), A.stride(0), _ptr(U), k,
+                                       _ptr(sig), _ptr(V), k, ctypes.byref(info), _stream(stream)))
+        return U, sig, V, rc, _as_dict(info)
+    raise ValueError("form must be 'outer' or 'svd'")

@@ -62,7 +62,7 @@ def _header_struct_fields(name):
 
 
 @pytest.mark.parametrize("cname,pyname", [("sk_solve_info", "SolveInfo"), ("sk_lsqr_info", "LsqrInfo"),
-                                           ("sk_rsvd_info", "RsvdInfo")])
+                                           ("sk_rsvd_info", "RsvdInfo"), ("sk_gn_info", "GnInfo")])
 def test_info_structs_match_header(cname, pyname):
     import ctypes as ct
     from paper_2508_21189_amd import libsketch
@@ -83,3 +83,5 @@ def test_driver_null_handle_fails_cleanly():
     assert "invalid" in libsketch.last_error()
     sig = ctypes.c_void_p(0)
     assert lib.rsvd(None, 1, 4, None, 4, None, 4, None, None, 4, None, None) == libsketch.SK_E_INVAL
+    assert lib.gen_nystrom(None, None, 1, 4, None, 4, None, 4, None, 4, None, None) == libsketch.SK_E_INVAL
+    assert lib.gen_nystrom_svd(None, None, 1, 4, None, 4, None, 4, None, None, 4, None, None) == libsketch.SK_E_INVAL
