@@ -94,8 +94,13 @@ int sketch_info(sketch_t S, int* kind, int64_t* d, int64_t* n, int* zeta, uint64
  *       BF16 inputs accumulate in F32 (BF16 values are exact in F32).
  *   ws  device workspace of ws_bytes >= sketch_workspace_size(...), or NULL
  *       to use a workspace owned by the handle.
- * The result is deterministic: the same inputs give bitwise identical SA on
- * every run (no atomics; fixed summation order).
+ * Kinds: SparseStack takes every input type. Gaussian takes F64 input (F64
+ * output; G generated inside the MFMA kernel, never stored) or F32 input
+ * (G, d x n F32, written into the workspace and one SGEMM; needs
+ * d * n * 4 <= 8 GB). SRTT takes F64 input (F64 output).
+ * The result is deterministic (the same inputs give bitwise identical SA on
+ * every run: no atomics, fixed summation order), except the F32 Gaussian
+ * path, whose GEMM follows rocBLAS.
  */
 int sketch_apply(sketch_t S, int dtype_in, int layout, int64_t m, const void* A, int64_t lda,
                  int dtype_out, void* SA, int64_t ldsa, void* ws, size_t ws_bytes, void* stream);

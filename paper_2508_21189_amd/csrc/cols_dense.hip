@@ -98,6 +98,45 @@ __global__ void __launch_bounds__(1024) srtt_cols_kernel(const Tin* __restrict__
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
+// Row mode with F32 input (SA = G A, A n x m): G (d x n, F32) is written out
+// with the same entries and SA is one rocBLAS SGEMM, F32 accumulation; F64
+// output goes through an F32 staging buffer. Used where G is small next to A
+// (d x n x 4 bytes <= 8 GB).
+size_t gauss_rows_f32_workspace(const sk_sketch* S, int64_t m, int dtype_out) {
+  size_t b = ((size_t)S->d * S->n * 4 + 255) & ~(size_t)255;
+  if (dtype_out == SK_F64) b += (size_t)S->d * m * 4;
+  return b;
+}
+
+int launch_gauss_rows_f32(sk_sketch* S, int64_t m, const float* A, int64_t lda, int dtype_out, void* SA, int64_t ldsa,
+                          void* ws, size_t ws_bytes, hipStream_t st) {
+  if ((double)S->d * (double)S->n * 4.0 > 8.0 * (1ull << 30)) {
+    set_error("sketch_apply: the F32 Gaussian row mode writes G out and needs d * n * 4 <= 8 GB");
+    return SK_E_NOTSUP;
+  }
+  if (ws_bytes < gauss_rows_f32_workspace(S, m, dtype_out)) {
+    set_error("sketch_apply: workspace too small (see sketch_workspace_size)");
+    return SK_E_INVAL;
+  }
+  const int64_t pairs = ((S->d + 1) / 2) * S->n;
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((pairs + 255) / 256, 16384));
+  hipLaunchKernelGGL(gauss_fill_kernel<float>, dim3(blocks), dim3(256), 0, st, (float*)ws, S->d, S->n, S->k0, S->k1,
+                     inv_sqrt_host((double)S->d));
+  SK_HIP(hipGetLastError());
+  const size_t gbytes = ((size_t)S->d * S->n * 4 + 255) & ~(size_t)255;
+  if (dtype_out == SK_F32) {
+    KernelTimer timer(S, st);
+    return gemm_rm(S, SK_F32, false, false, S->d, m, S->n, 1.0, ws, S->n, A, lda, 0.0, SA, ldsa, st);
+  }
+  float* Yf = (float*)((char*)ws + gbytes);
+  {
+    KernelTimer timer(S, st);
+    int rc = gemm_rm(S, SK_F32, false, false, S->d, m, S->n, 1.0, ws, S->n, A, lda, 0.0, Yf, m, st);
+    if (rc != SK_OK) return rc;
+  }
+  return launch_convert(SK_F32, Yf, m, SK_F64, SA, ldsa, S->d, m, st);
+}
+
 int cols_dense_workspace(const sk_sketch* S, int dtype_in, int dtype_out, int64_t rows, size_t* bytes) {
   *bytes = 0;
   if (S->kind == SK_GAUSSIAN) {

@@ -68,7 +68,9 @@ int apply_workspace(const sk_sketch* S, int op, int dtype_in, int64_t m, size_t*
     }
     *bytes = p.partial_bytes + p.plan_bytes;
   } else if (op == 0 && S->kind == SK_GAUSSIAN) {
-    *bytes = gauss_workspace(S, (int)m);
+    // F64 input: split-K partials; F32 input: G written out (+ F32 staging
+    // of an F64 result)
+    *bytes = dtype_in == SK_F32 ? gauss_rows_f32_workspace(S, m, SK_F64) : gauss_workspace(S, (int)m);
   } else if (op == 0 && S->kind == SK_SRTT) {
     *bytes = srtt_workspace(S, (int)m);
   } else if (op == 1 && S->kind == SK_SPARSESTACK) {
@@ -114,8 +116,22 @@ int apply_dispatch(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t
       return launch_rows_apply(S, p, dtype_in, m, A, lda, dtype_out, SA, ldsa, w, st);
     }
     case SK_GAUSSIAN: {
+      if (dtype_in == SK_F32) {
+        const size_t need = gauss_rows_f32_workspace(S, m, dtype_out);
+        void* w = ws;
+        if (w) {
+          if (ws_bytes < need) {
+            set_error("sketch_apply: workspace too small (see sketch_workspace_size)");
+            return SK_E_INVAL;
+          }
+        } else {
+          int rc = handle_workspace(S, need, &w);
+          if (rc != SK_OK) return rc;
+        }
+        return launch_gauss_rows_f32(S, m, (const float*)A, lda, dtype_out, SA, ldsa, w, need, st);
+      }
       if (dtype_in != SK_F64 || dtype_out != SK_F64) {
-        set_error("sketch_apply: the Gaussian sketch takes and returns F64");
+        set_error("sketch_apply: the Gaussian sketch takes F64 (F64 output) or F32 input");
         return SK_E_NOTSUP;
       }
       const size_t need = gauss_workspace(S, (int)m);

@@ -21,6 +21,12 @@ int apply_T_dispatch(sk_sketch* S, int dtype_in, int64_t rows, const void* A, in
 int launch_convert(int dtype_in, const void* in, int64_t ldi, int dtype_out, void* out, int64_t ldo, int64_t rows,
                    int64_t cols, hipStream_t st);
 
+// Row mode of the Gaussian sketch for F32 input (cols_dense.hip): G written
+// out (d x n F32) and one SGEMM; F32 or F64 output.
+size_t gauss_rows_f32_workspace(const sk_sketch* S, int64_t m, int dtype_out);
+int launch_gauss_rows_f32(sk_sketch* S, int64_t m, const float* A, int64_t lda, int dtype_out, void* SA, int64_t ldsa,
+                          void* ws, size_t ws_bytes, hipStream_t st);
+
 // Column mode of the Gaussian and SRTT sketches (cols_dense.hip).
 int cols_dense_workspace(const sk_sketch* S, int dtype_in, int dtype_out, int64_t rows, size_t* bytes);
 int launch_cols_dense(sk_sketch* S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out, void* Y,

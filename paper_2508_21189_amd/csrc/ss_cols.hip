@@ -148,6 +148,171 @@ __global__ void __launch_bounds__(1024) ss_cols_kernel(ColsArgs a) {
   }
 }
 
+// The same walk with the tile loads taken off the critical path: each thread
+// fetches its 16-byte chunks of the next tile (and of its plan records) into
+// registers before walking the current tile, and stores them to LDS after
+// the walk. Needs 16-byte aligned rows and n * element size a multiple of 16
+// (a chunk never straddles the end of a row). 8 waves (at most 8 walkers);
+// waves past the walkers only load.
+template <typename Tin, int JB>
+__global__ void __launch_bounds__(512) ss_cols_vec_kernel(ColsArgs a) {
+  using Tacc = typename ColsAcc<Tin>::type;
+  constexpr int ES = sizeof(Tin);
+  constexpr int VPL = 16 / ES;  // values per 16-byte chunk
+  constexpr int NCH = 8;        // chunks per thread (tile <= 64 KB, >= 512 threads)
+  constexpr int NPL = 2;        // plan chunks per thread
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int TS = a.TC + 1;
+  Tacc* T = (Tacc*)smem;  // [64][TS]
+  unsigned char* pl = smem + (((size_t)64 * TS * sizeof(Tacc) + 15) & ~(size_t)15);
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nthreads = blockDim.x;
+  const int L = blockIdx.x;
+  const int group = L % a.n_groups;
+  const int64_t r0 = (int64_t)(L / a.n_groups) * 64;
+  const int t0 = group * a.bpg;
+  const int bpg = min(a.bpg, a.zeta - t0);
+  const int tl = wave / a.H, hr = wave - (wave / a.H) * a.H;
+  const bool walker = tl < bpg;
+  const int s_begin = hr * a.per_range;
+  const int s_cnt = walker ? max(0, min(a.per_range, a.nb - s_begin)) : 0;
+  const int64_t nrows = min((int64_t)64, a.rows - r0);
+  const int cpr = a.TC / VPL;       // chunks per tile row
+  const int nchunks = 64 * cpr;     // chunks per tile
+  const int pchunks = bpg * a.rec_bytes / 16;
+
+  uint4 ra[NCH], rp[NPL];
+  uint32_t valid = 0;
+  auto fetch = [&](int64_t tile) {
+    const int64_t c0 = tile * a.TC;
+    valid = 0;
+#pragma unroll
+    for (int u = 0; u < NCH; ++u) {
+      const int f = tid + u * nthreads;
+      const int rr = f / cpr, cq = f - (f / cpr) * cpr;
+      const int64_t col = c0 + (int64_t)cq * VPL;
+      const bool ok = f < nchunks && rr < nrows && col < a.n;
+      const unsigned char* src = ok ? a.A + (r0 + rr) * a.lda_bytes + col * ES : a.A;
+      ra[u] = *(const uint4*)src;
+      valid |= (uint32_t)ok << u;
+    }
+    const uint4* ps = (const uint4*)(a.plan + (tile * a.zeta + t0) * (int64_t)a.rec_bytes);
+#pragma unroll
+    for (int u = 0; u < NPL; ++u) {
+      const int f = tid + u * nthreads;
+      rp[u] = f < pchunks ? ps[f] : uint4{0, 0, 0, 0};
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int u = 0; u < NCH; ++u) {
+      const int f = tid + u * nthreads;
+      if (f < nchunks) {
+        const int rr = f / cpr, cq = f - (f / cpr) * cpr;
+        const bool ok = (valid >> u) & 1u;
+        const Tin* v = (const Tin*)&ra[u];
+        Tacc* dst = T + rr * TS + cq * VPL;
+#pragma unroll
+        for (int q = 0; q < VPL; ++q) {
+          Tacc x;
+          if constexpr (sizeof(Tin) == 2)
+            x = bf16_to_f32(v[q]);
+          else
+            x = (Tacc)v[q];
+          dst[q] = ok ? x : (Tacc)0;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NPL; ++u) {
+      const int f = tid + u * nthreads;
+      if (f < pchunks) ((uint4*)pl)[f] = rp[u];
+    }
+  };
+
+  Tacc acc[JB];
+#pragma unroll
+  for (int j = 0; j < JB; ++j) acc[j] = 0;
+
+  // the pad column TC of every tile row stays zero (absent list slots read it)
+  for (int rr = tid; rr < 64; rr += nthreads) T[rr * TS + a.TC] = (Tacc)0;
+  if (a.n_tiles > 0) fetch(0);
+  for (int64_t tile = 0; tile < a.n_tiles; ++tile) {
+    __syncthreads();  // previous tile fully consumed
+    stage();
+    __syncthreads();
+    if (tile + 1 < a.n_tiles) fetch(tile + 1);
+    if (walker) {
+      // Lane j describes bucket s_begin + j: its first NU list entries are
+      // preloaded (absent ones point at the zero pad column TC), so the first
+      // NU passes over all buckets are unrolled and branch-free with their
+      // LDS reads independent; buckets with more entries walk the rest.
+      constexpr int NU = 8;
+      const unsigned char* rec = pl + tl * a.rec_bytes;
+      const uint16_t* of = (const uint16_t*)rec;
+      const uint32_t* lst = (const uint32_t*)(rec + a.lst_off);
+      const Tacc* Tl = T + lane * TS;
+      uint32_t kbeg = 0, kcnt = 0;
+      if (lane < s_cnt) {
+        kbeg = of[s_begin + lane];
+        kcnt = (uint32_t)of[s_begin + lane + 1] - kbeg;
+      }
+      uint32_t ev[NU];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) ev[u] = kcnt > (uint32_t)u ? lst[kbeg + u] : (uint32_t)a.TC;
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+#pragma unroll
+        for (int g = 0; g < JB; g += 8) {
+          Tacc v[8];
+          uint32_t e[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            if (g + q < JB) {
+              e[q] = (uint32_t)__builtin_amdgcn_readlane((int)ev[u], g + q);
+              v[q] = Tl[e[q] & 0x7fffffffu];
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            if (g + q < JB) acc[g + q] += flip_c(v[q], e[q]);
+        }
+      }
+      const uint64_t more = __ballot(kcnt > (uint32_t)NU);
+      if (more) {
+#pragma unroll
+        for (int j = 0; j < JB; ++j) {
+          if ((more >> j) & 1ull) {
+            const uint32_t kb = (uint32_t)__builtin_amdgcn_readlane((int)kbeg, j);
+            const uint32_t ke = kb + (uint32_t)__builtin_amdgcn_readlane((int)kcnt, j);
+            for (uint32_t kk = kb + NU; kk < ke; ++kk) {
+              const uint32_t ea = lst[kk];
+              acc[j] += flip_c(Tl[ea & 0x7fffffffu], ea);
+            }
+          }
+        }
+      }
+    }
+  }
+
+  if (walker && lane < nrows) {
+    const int64_t col0 = (int64_t)(t0 + tl) * a.nb + s_begin;
+    if (a.out_f64) {
+      double* Y = (double*)a.Y + (r0 + lane) * a.ldy + col0;
+#pragma unroll
+      for (int j = 0; j < JB; ++j)
+        if (j < s_cnt) Y[j] = (double)acc[j] * a.scale_d;
+    } else {
+      float* Y = (float*)a.Y + (r0 + lane) * a.ldy + col0;
+#pragma unroll
+      for (int j = 0; j < JB; ++j)
+        if (j < s_cnt) Y[j] = (float)(acc[j] * (Tacc)(sizeof(Tacc) == 8 ? a.scale_d : a.scale_f));
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
@@ -233,11 +398,21 @@ static int launch_cols_t(const sk_sketch* S, const ColsPlan& p, int64_t rows, co
   a.out_f64 = out_f64;
   a.scale_d = inv_sqrt_host((double)S->zeta);
   a.scale_f = (float)a.scale_d;
-  auto kern = ss_cols_kernel<Tin, JB>;
-  SK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds));
   const int64_t grid = ((rows + 63) / 64) * p.n_groups;
-  {
-    KernelTimer timer(S, st);
+  // the prefetching kernel: 16-byte aligned rows, whole chunks per row, the
+  // tile within 8 chunks a thread and the plan records within 2
+  const int threads = 512;
+  const bool vec = p.W <= 8 && ((uintptr_t)A % 16 == 0) && (a.lda_bytes % 16 == 0) && ((S->n * (int64_t)sizeof(Tin)) % 16 == 0) &&
+                   (64 * p.TC * (int64_t)sizeof(Tin) / 16 <= 8 * threads) &&
+                   ((int64_t)p.bpg * p.rec_bytes / 16 <= 2 * threads);
+  KernelTimer timer(S, st);
+  if (vec) {
+    auto kern = ss_cols_vec_kernel<Tin, JB>;
+    SK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds));
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), p.lds, st, a);
+  } else {
+    auto kern = ss_cols_kernel<Tin, JB>;
+    SK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds));
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * p.W), p.lds, st, a);
   }
   SK_HIP(hipGetLastError());

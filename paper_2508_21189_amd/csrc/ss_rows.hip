@@ -697,6 +697,9 @@ int plan_rows(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_
   const int64_t items = (int64_t)p->n_slabs * p->n_groups;
   const int target = env_int("SKETCH_WG_TARGET", 256);
   int64_t nc = std::max<int64_t>(1, (target + items - 1) / items);
+  // chunk c runs on XCD c mod 8: at least 8 chunks, a multiple of 8, so that
+  // no XCD idles (wide inputs have many slabs and would otherwise get one)
+  nc = ((std::max<int64_t>(nc, 8) + 7) / 8) * 8;
   nc = std::min<int64_t>(nc, (n + p->R - 1) / p->R);
   int64_t rpc = (n + nc - 1) / nc;
   rpc = ((rpc + p->R - 1) / p->R) * p->R;

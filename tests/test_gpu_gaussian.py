@@ -51,6 +51,23 @@ def test_apply_parity(lib, n, m, d, seed):
     assert np.all(err <= bound), "max err/bound %g" % np.max(err / bound)
 
 
+@pytest.mark.parametrize("n,m,d,seed", [(5000, 33, 60, 21), (20000, 200, 300, 22)])
+def test_apply_f32_input(lib, n, m, d, seed):
+    """F32 input: G written out in F32 and one SGEMM. Against the oracle on
+    the F32-rounded A: per entry of G one F32 rounding, then n-term F32 sums,
+    so |SA - G A| <= (n + 2) 2^-24 (|G| |A|)."""
+    rng = np.random.default_rng(seed)
+    A32 = rng.standard_normal((n, m)).astype(np.float32)
+    A = A32.astype(np.float64)
+    S = lib.Sketch("gaussian", d, n, 1, seed)
+    G = sk.gaussian_dense(n, d, seed)
+    ref = G @ A
+    bound = (n + 2) * 2.0 ** -24 * (np.abs(G) @ np.abs(A))
+    for odt in (torch.float32, torch.float64):
+        got = S.apply(torch.from_numpy(A32).cuda(), out_dtype=odt).to(torch.float64).cpu().numpy()
+        assert np.all(np.abs(got - ref) <= bound + 2.0 ** -24 * np.abs(ref))
+
+
 def test_bitwise_reproducible(lib):
     rng = np.random.default_rng(0)
     A = torch.from_numpy(rng.standard_normal((30000, 100))).cuda()

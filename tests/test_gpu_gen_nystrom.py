@@ -120,6 +120,28 @@ def test_forms_agree_on_gpu(lib):
     assert d.item() <= 1e-8
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_outer_with_gaussian_tests(lib, dtype):
+    """The comparison in the paper's compression experiment: Gaussian Omega
+    and Psi (Def. 1.4; Psi^T A through the F64 MFMA kernel or, for F32 input,
+    G written out and one SGEMM)."""
+    rows, cols, k, p = 2500, 1800, 32, 48
+    A = _lowrank_plus_noise(rows, cols, 24, 1e-3, seed=12).astype(dtype)
+    A64 = A.astype(np.float64)
+    So = lib.Sketch("gaussian", k, cols, 1, 400)
+    Sp = lib.Sketch("gaussian", p, rows, 1, 401)
+    Omega = sk.gaussian_dense(cols, k, 400).T
+    Psi = sk.gaussian_dense(rows, p, 401).T
+    F, G, rc, info = lib.gen_nystrom(So, Sp, torch.from_numpy(A).cuda(), form="outer")
+    assert rc == 0
+    Fr, Gr, r = lr.gen_nystrom_outer(A64, Omega, Psi)
+    assert info["rank"] == r
+    got = F.cpu().numpy() @ G.cpu().numpy().T
+    u = 2.0 ** -53 if dtype == np.float64 else (rows + cols) * 2.0 ** -24
+    tol = 50 * _kappa(A64, Omega, Psi) * u * np.linalg.norm(A64)
+    assert np.linalg.norm(got - Fr @ Gr.T) <= tol
+
+
 def test_invalid_shapes_fail_cleanly(lib):
     A = torch.zeros((100, 80), dtype=torch.float64, device="cuda")
     So = lib.Sketch("sparsestack", 16, 80, 4, 1)
