@@ -198,6 +198,59 @@ def rsvd_variants(libsketch, inputs, torch, reps):
     return out
 
 
+def gn_variants(libsketch, inputs, torch, reps):
+    """Generalized Nystrom (Alg. 4 outer form, Alg. 5 SVD form) on the
+    131072 x 40000 float32 snapshot stand-in, k = 200, p = ceil(1.5 k) = 300,
+    with SparseStack (zeta = 4) and Gaussian test matrices; the relative error
+    ||A - A_hat||_F / ||A||_F is computed on the device afterwards."""
+    import statistics
+    rows, cols, k, p = 131072, 40000, 200, 300
+    print("bench: generating the %d x %d snapshot stand-in" % (rows, cols), file=sys.stderr, flush=True)
+    A = inputs.snapshots_stand_in(rows, cols, seed=DATA_SEED + 3)
+    nA = sum(float(torch.sum(A[r0:r0 + 8192].double() ** 2)) for r0 in range(0, rows, 8192)) ** 0.5
+
+    def rel_err(L, R, s=None):
+        # ||A - L diag(s) R^T||_F / ||A||_F in row blocks
+        acc = 0.0
+        Rs = (R * s[None, :]) if s is not None else R
+        for r0 in range(0, rows, 8192):
+            E = A[r0:r0 + 8192].double() - L[r0:r0 + 8192] @ Rs.T
+            acc += float(torch.sum(E * E))
+        return (acc ** 0.5) / nA
+
+    out = {"workload": "snapshot stand-in A %dx%d f32 (rank-300 i^-2 spectrum + noise 1e-6, centred), k=%d p=%d"
+                       % (rows, cols, k, p)}
+    for kind, zeta in (("sparsestack", 4), ("gaussian", 1)):
+        So = libsketch.Sketch(kind, k, cols, zeta, SKETCH_SEED + 3)
+        Sp = libsketch.Sketch(kind, p, rows, zeta, SKETCH_SEED + 4)
+        res = {}
+        for form in ("outer", "svd"):
+            r = libsketch.gen_nystrom(So, Sp, A, form=form)
+            walls = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = libsketch.gen_nystrom(So, Sp, A, form=form)
+                torch.cuda.synchronize()
+                walls.append((time.perf_counter() - t0) * 1e3)
+            info = r[-1]
+            err = rel_err(r[0], r[1]) if form == "outer" else rel_err(r[0], r[2], r[1])
+            res[form] = {"total_ms": round(statistics.median(walls), 3), "status": r[-2], "rank": info["rank"],
+                         "t_sketch_ms": round(info["t_sketch_ms"], 3), "t_core_ms": round(info["t_core_ms"], 3),
+                         "t_factors_ms": round(info["t_factors_ms"], 3), "rel_error_fro": err}
+            print("bench: gen_nystrom %s %s %.2f ms, error %.3e" % (kind, form, res[form]["total_ms"], err),
+                  file=sys.stderr, flush=True)
+            del r
+            torch.cuda.empty_cache()
+        out[kind] = res
+        del So, Sp
+    out["speedup_vs_gaussian"] = {f: round(out["gaussian"][f]["total_ms"] / out["sparsestack"][f]["total_ms"], 3)
+                                  for f in ("outer", "svd")}
+    del A
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,6 +264,8 @@ def main():
     ap.add_argument("--mixed-reps", type=int, default=2,
                     help="timed solves per precision of the 8388608 x 500 mixed-precision system (0 = skip)")
     ap.add_argument("--rsvd-reps", type=int, default=1, help="timed randomized SVDs per sketch kind (0 = skip)")
+    ap.add_argument("--gn-reps", type=int, default=1,
+                    help="timed generalized Nystrom calls per sketch kind and form (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -280,6 +335,8 @@ def main():
         rec["lsqr_mixed"] = lsqr_mixed(libsketch, inputs, torch, args.mixed_reps)
     if args.rsvd_reps > 0:
         rec["rsvd"] = rsvd_variants(libsketch, inputs, torch, args.rsvd_reps)
+    if args.gn_reps > 0:
+        rec["gen_nystrom"] = gn_variants(libsketch, inputs, torch, args.gn_reps)
     if not args.no_cpu:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(cpu_sample, args.cpu_rows)

@@ -498,17 +498,17 @@ int jacobi_svd_rounds(const double* M, int64_t rows, int k, int input_colmajor, 
   hipLaunchKernelGGL(jacobi_init_kernel, dim3(grid_for((int64_t)nr * k)), dim3(256), 0, st, M, nr, k, input_colmajor,
                      Uc, Vc);
   SK_HIP(hipGetLastError());
-  // block size: about k / 64 (enough block pairs per round to spread over
-  // the CUs), 2 to 16, and small enough for a visit (2 BS columns of k
-  // doubles + W) to fit in LDS
+  // block size 8 (measured best at k = 512 against 4 and 16: the rounds of a
+  // sweep are latency-bound launches, so fewer rounds win until a visit's own
+  // work dominates), smaller for tiny k or when a visit (2 BS columns of
+  // `rows` doubles + W) would not fit in LDS
   const size_t cap = 160 * 1024;
   static const int bs_env = [] {
     const char* v = std::getenv("SKETCH_JACOBI_BS");
     return v ? std::atoi(v) : 0;
   }();
-  int bs = (bs_env == 2 || bs_env == 4 || bs_env == 8 || bs_env == 16) ? bs_env : 16;
-  while (bs > 2 &&
-         ((bs_env == 0 && bs * 64 > k) || ((size_t)2 * bs * nr + (size_t)4 * bs * bs) * sizeof(double) > cap))
+  int bs = (bs_env == 2 || bs_env == 4 || bs_env == 8 || bs_env == 16) ? bs_env : 8;
+  while (bs > 2 && ((bs_env == 0 && 2 * bs > k) || ((size_t)2 * bs * nr + (size_t)4 * bs * bs) * sizeof(double) > cap))
     bs /= 2;
   const size_t lds = ((size_t)2 * bs * nr + (size_t)4 * bs * bs) * sizeof(double);
   if (lds > cap) {

@@ -78,3 +78,29 @@ def lowrank_decay(rows, cols, seed=0, device="cuda", dtype=torch.float32):
     sig = torch.arange(1, k + 1, dtype=torch.float64, device=device) ** -2.0
     A = (U * sig[None, :]) @ V.T
     return A.to(dtype), sig
+
+
+def snapshots_stand_in(rows=131072, cols=40000, rank=300, noise=1e-6, seed=0, device="cuda", dtype=torch.float32):
+    """Synthetic stand-in for a matrix of simulation snapshots (the paper's
+    compression experiment uses 131072 x 40000 real-ified Gross-Pitaevskii
+    snapshots, which are not available): A = U diag(s) V^T + noise * N with
+    U, V Haar-orthonormal (rows x rank, cols x rank), s_i = i^-2, N iid
+    N(0, 1) scaled by 1/sqrt(cols); then every column is centred to zero mean,
+    as the paper does with the snapshots. Built in F32 on the device in
+    blocks of rows."""
+    g = _gen(device, seed)
+    U, _ = torch.linalg.qr(torch.randn((rows, rank), generator=g, dtype=torch.float64, device=device))
+    V, _ = torch.linalg.qr(torch.randn((cols, rank), generator=g, dtype=torch.float64, device=device))
+    s = torch.arange(1, rank + 1, dtype=torch.float64, device=device) ** -2.0
+    Us = (U * s[None, :]).to(dtype)
+    Vt = V.T.contiguous().to(dtype)
+    del U, V
+    A = torch.empty((rows, cols), dtype=dtype, device=device)
+    blk = 16384
+    for r0 in range(0, rows, blk):
+        r1 = min(rows, r0 + blk)
+        torch.matmul(Us[r0:r1], Vt, out=A[r0:r1])
+        A[r0:r1].add_(torch.randn((r1 - r0, cols), generator=g, dtype=dtype, device=device),
+                      alpha=noise / cols ** 0.5)
+    A -= A.mean(dim=0, keepdim=True)
+    return A
