@@ -291,6 +291,32 @@ int gen_nystrom(sketch_t So, sketch_t Sp, int dtype, int64_t rows, const void* A
 int gen_nystrom_svd(sketch_t So, sketch_t Sp, int dtype, int64_t rows, const void* A, int64_t lda, double* U,
                     int64_t ldu, double* sigma, double* V, int64_t ldv, sk_gn_info* info, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Nystrom approximation of a psd matrix (Section "Nystrom approximation",
+ * Alg. 2): A ~ U diag(lambda) U^T for a symmetric psd A (n x n, row-major,
+ * dtype SK_F32 or SK_F64, lda >= n), with Omega = S^T, S a k x n sketch
+ * (SparseStack or Gaussian; k = S's d <= min(n, 4096)). Steps: Y = A Omega
+ * (the column-mode apply, stored F64); nu = sqrt(n) eps ||Y||_2 with
+ * eps = 2^-52 and ||Y||_2 from 100 power iterations on Y^T Y (a reading:
+ * the paper writes ||Y|| and eps_mach); Y_nu = Y + nu Omega;
+ * C = chol(Omega^T Y_nu) (the row-mode apply of S to Y_nu, symmetrized);
+ * B = Y_nu C^-1; [U, Sigma, ~] = svd_econ(B) by shifted Cholesky QR of B and
+ * the Jacobi SVD of its triangular factor; lambda = max(0, Sigma^2 - nu),
+ * descending. U: n x k (ldu >= k), lambda: k doubles. Synchronous at its
+ * end. Returns SK_W_RANKDEF if a Cholesky factorization met a non-positive
+ * pivot. info may be NULL.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  double nu;           /* the shift */
+  double t_sketch_ms;  /* Y = A Omega */
+  double t_core_ms;    /* shift, Cholesky, triangular solve, SVD */
+  double t_total_ms;   /* device time of the whole call */
+  int jacobi_sweeps;   /* sweeps of the k x k Jacobi SVD */
+} sk_nystrom_info;
+
+int nystrom_psd(sketch_t S, int dtype, const void* A, int64_t lda, double* U, int64_t ldu, double* lambda,
+                sk_nystrom_info* info, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,10 +1,11 @@
-"""Randomized SVD (Alg. 1), generalized Nystrom (Alg. 4 and 5) and their error
-measures (oracle; test infrastructure only).
+"""Randomized SVD (Alg. 1), Nystrom (Alg. 2), generalized Nystrom (Alg. 4 and
+5) and their error measures (oracle; test infrastructure only).
 
 Readings where the paper is silent: orth() and qr_econ() are Householder QR
 (numpy/LAPACK); svd_econ() is LAPACK's SVD; there is no oversampling and no
 power iteration (Alg. 1 has none); eps_mach in the rank rule of Alg. 4 and 5
-is the FP64 unit roundoff 2^-52.
+is the FP64 unit roundoff 2^-52; in Alg. 2, ||Y|| is the spectral norm and
+chol() factors the symmetrized Omega^T Y_nu (its upper factor C, B = C^T C).
 """
 import numpy as np
 
@@ -86,3 +87,24 @@ def gen_nystrom_svd(A, Omega, Psi, eps=EPS_MACH):
     C = V1t[:r].T @ ((U1[:, :r].T @ T.T) / s1[:r, None])
     Uh, sig, Vht = np.linalg.svd(C, full_matrices=False)
     return Q @ Uh, sig, P @ Vht.T, r
+
+
+def nystrom_psd(A, Omega, eps=EPS_MACH):
+    """Alg. 2: A ~ U diag(lam) U^T for a psd A (n x n).
+
+    Y = A Omega; nu = sqrt(n) eps ||Y||_2; Y_nu = Y + nu Omega;
+    C = chol(Omega^T Y_nu) (upper, symmetrized input); B = Y_nu C^-1;
+    [U, S, ~] = svd_econ(B); lam = max(0, S^2 - nu). Returns (U, lam, nu).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[0]
+    Y = A @ Omega
+    nu = np.sqrt(n) * eps * np.linalg.norm(Y, 2)
+    Ynu = Y + nu * Omega
+    M = Omega.T @ Ynu
+    M = 0.5 * (M + M.T)
+    C = np.linalg.cholesky(M).T  # upper: M = C^T C
+    B = np.linalg.solve(C.T, Ynu.T).T  # B C = Y_nu
+    U, s, _ = np.linalg.svd(B, full_matrices=False)
+    lam = np.maximum(0.0, s * s - nu)
+    return U, lam, nu

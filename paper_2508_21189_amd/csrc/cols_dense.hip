@@ -98,6 +98,15 @@ __global__ void __launch_bounds__(1024) srtt_cols_kernel(const Tin* __restrict__
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
+int launch_gauss_fill_f64(const sk_sketch* S, double* G, hipStream_t st) {
+  const int64_t pairs = ((S->d + 1) / 2) * S->n;
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((pairs + 255) / 256, 16384));
+  hipLaunchKernelGGL(gauss_fill_kernel<double>, dim3(blocks), dim3(256), 0, st, G, S->d, S->n, S->k0, S->k1,
+                     inv_sqrt_host((double)S->d));
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
 // Row mode with F32 input (SA = G A, A n x m): G (d x n, F32) is written out
 // with the same entries and SA is one rocBLAS SGEMM, F32 accumulation; F64
 // output goes through an F32 staging buffer. Used where G is small next to A

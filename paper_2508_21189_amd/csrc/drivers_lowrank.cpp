@@ -436,3 +436,111 @@ extern "C" int gen_nystrom_svd(sketch_t So, sketch_t Sp, int dtype, int64_t rows
   }
   return SK_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Nystrom approximation of a psd matrix (Alg. 2), Omega = S^T (n x k).
+// ---------------------------------------------------------------------------
+extern "C" int nystrom_psd(sketch_t S, int dtype, const void* A, int64_t lda, double* U, int64_t ldu, double* lambda,
+                           sk_nystrom_info* info, void* stream) {
+  if (!S || !A || !U || !lambda || (dtype != SK_F64 && dtype != SK_F32)) {
+    set_error("nystrom_psd: invalid argument");
+    return SK_E_INVAL;
+  }
+  const int64_t n = S->n;
+  const int k = (int)S->d;
+  if (lda < n || ldu < k || k > n || k > 4096) {
+    set_error("nystrom_psd: need A n x n (lda >= n), U n x k (ldu >= k), k = d <= min(n, 4096)");
+    return SK_E_INVAL;
+  }
+  if (S->kind != SK_SPARSESTACK && S->kind != SK_GAUSSIAN) {
+    set_error("nystrom_psd: Omega must be a SparseStack or Gaussian sketch");
+    return SK_E_NOTSUP;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  size_t wT = 0, wY = 0;
+  SK_TRY2(apply_workspace(S, 1, dtype, n, &wT));
+  SK_TRY2(apply_workspace(S, 0, SK_F64, k, &wY));
+  void *awT, *awY;
+  double *Y, *B, *B2, *Om, *C, *Cinv, *CinvT, *R, *Ur, *sv, *Vr, *jw, *nu;
+  OrthBufs ob;
+  int* jflag;
+  auto carve = [&](Carve& cv) {
+    awT = cv.take<char>(wT);
+    awY = cv.take<char>(wY);
+    Y = cv.take<double>((size_t)n * k);
+    B = cv.take<double>((size_t)n * k);
+    B2 = cv.take<double>((size_t)n * k);
+    Om = S->kind == SK_GAUSSIAN ? cv.take<double>((size_t)n * k) : nullptr;
+    C = cv.take<double>((size_t)k * k);
+    Cinv = cv.take<double>((size_t)k * k);
+    CinvT = cv.take<double>((size_t)k * k);
+    R = cv.take<double>((size_t)k * k);
+    Ur = cv.take<double>((size_t)k * k);
+    sv = cv.take<double>(k);
+    Vr = cv.take<double>((size_t)k * k);
+    jw = cv.take<double>(jacobi_work_doubles(k, k));
+    nu = cv.take<double>(1);
+    ob.G = cv.take<double>((size_t)k * k);
+    ob.Rinv = cv.take<double>((size_t)k * k);
+    ob.RinvT = cv.take<double>((size_t)k * k);
+    ob.Rtmp = cv.take<double>((size_t)k * k);
+    ob.Dinv = cv.take<double>(32 * 32);
+    ob.Gpart = cv.take<double>((size_t)kGramChunks * k * k);
+    ob.fail = cv.take<int>(1);
+    jflag = cv.take<int>(1);
+  };
+  Carve c0;
+  carve(c0);
+  char* base = nullptr;
+  SK_TRY2(lowrank_workspace(S, c0.off, &base));
+  Carve c1{base, 0};
+  carve(c1);
+  int* h = static_cast<int*>(S->h_pinned);
+
+  Marks mk(st);
+  SK_TRY2(mk.mark());  // 0
+  SK_TRY2(launch_set_int(ob.fail, 0, st));
+  SK_TRY2(apply_T_dispatch(S, dtype, n, A, lda, SK_F64, Y, k, awT, wT, st));  // Y = A Omega
+  SK_TRY2(mk.mark());                                                         // 1: sketch
+  // nu = sqrt(n) eps ||Y||_2
+  SK_TRY2(gram_rm(S, Y, k, n, k, ob.G, ob.Gpart, kGramChunks, st));
+  SK_TRY2(launch_nystrom_shift(ob.G, k, n, nu, st));
+  // Y_nu = Y + nu Omega
+  if (S->kind == SK_SPARSESTACK) {
+    SK_TRY2(launch_add_omega_ss(Y, n, k, S->zeta, (int)S->nb, S->k0, S->k1, inv_sqrt_host((double)S->zeta), nu, st));
+  } else {
+    SK_TRY2(launch_gauss_fill_f64(S, Om, st));
+    SK_TRY2(launch_add_omega_dense(Y, n, k, Om, nu, st));
+  }
+  // C = chol(Omega^T Y_nu): Omega^T Y_nu = S Y_nu, symmetrized, upper factor
+  SK_TRY2(apply_into(S, SK_F64, k, Y, k, C, k, awY, wY, st));
+  SK_TRY2(launch_symmetrize(C, k, st));
+  SK_TRY2(launch_cholesky_upper(C, k, 0.0, ob.Dinv, ob.fail, st));
+  // B = Y_nu C^-1; [U, Sigma, ~] = svd_econ(B) by Cholesky QR of B and the
+  // Jacobi SVD of its triangular factor
+  SK_TRY2(launch_trinv(C, k, Cinv, CinvT, st));
+  SK_TRY2(gemm_rm(S, SK_F64, false, false, n, k, k, 1.0, Y, k, Cinv, k, 0.0, B, k, st));
+  double* Q = nullptr;
+  SK_TRY2(orth_cholqr3(S, B, B2, n, k, ob, R, &Q, st));
+  int sweeps = 0;
+  SK_TRY2(jacobi_svd_rounds(R, k, k, 0, Ur, sv, Vr, jw, jflag, h + 1, 60, &sweeps, st));
+  SK_TRY2(gemm_rm(S, SK_F64, false, false, n, k, k, 1.0, Q, k, Ur, k, 0.0, U, ldu, st));
+  SK_TRY2(launch_remove_shift(sv, k, nu, lambda, st));  // Lambda = max(0, Sigma^2 - nu)
+  SK_TRY2(mk.mark());                                     // 2: core
+  double hnu = 0.0;
+  SK_HIP(hipMemcpyAsync(h + 2, ob.fail, sizeof(int), hipMemcpyDeviceToHost, st));
+  SK_HIP(hipMemcpyAsync(&hnu, nu, sizeof(double), hipMemcpyDeviceToHost, st));
+  SK_HIP(hipStreamSynchronize(st));
+  if (info) {
+    info->nu = hnu;
+    info->t_sketch_ms = mk.ms(0, 1);
+    info->t_core_ms = mk.ms(1, 2);
+    info->t_total_ms = mk.ms(0, 2);
+    info->jacobi_sweeps = sweeps;
+  }
+  if (h[2]) {
+    set_error("nystrom_psd: a Cholesky factorization met a non-positive pivot (A not psd to working precision?)");
+    return SK_W_RANKDEF;
+  }
+  return SK_OK;
+}

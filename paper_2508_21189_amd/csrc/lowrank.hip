@@ -12,6 +12,7 @@
 #include "sk_lowrank.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <climits>
 #include <cstdlib>
 
@@ -479,6 +480,135 @@ __global__ void __launch_bounds__(256) gn_truncate_kernel(const double* __restri
 int launch_gn_truncate(const double* s, int k, const double* V, double* Vs, const double* U, int p, double* Ur,
                        int* rank, hipStream_t st) {
   hipLaunchKernelGGL(gn_truncate_kernel, dim3(1), dim3(256), 0, st, s, k, V, Vs, U, p, Ur, rank);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+// Nystrom (Alg. 2) helpers --------------------------------------------------
+
+// *nu = coef * sqrt(lambda_max(G)) for a k x k psd G (row-major): 100 power
+// iterations from the all-ones vector, then the Rayleigh quotient. One
+// workgroup; x and G x live in LDS.
+__global__ void __launch_bounds__(1024) power_norm_kernel(const double* __restrict__ G, int k, double coef,
+                                                          double* __restrict__ nu) {
+  extern __shared__ double xs[];  // x[k], y[k]
+  __shared__ double red[16];
+  double* x = xs;
+  double* y = xs + k;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) x[i] = 1.0;
+  __syncthreads();
+  double lam = 0.0;
+  for (int it = 0; it <= 100; ++it) {
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+      const double* g = G + (int64_t)i * k;
+      double acc = 0.0;
+      for (int j = 0; j < k; ++j) acc += g[j] * x[j];
+      y[i] = acc;
+    }
+    __syncthreads();
+    double xy = 0.0, yy = 0.0, xx = 0.0;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+      xy += x[i] * y[i];
+      yy += y[i] * y[i];
+      xx += x[i] * x[i];
+    }
+    xy = wg_reduce_sum(xy, red);
+    yy = wg_reduce_sum(yy, red);
+    xx = wg_reduce_sum(xx, red);
+    lam = xx > 0 ? xy / xx : 0.0;  // Rayleigh quotient of x
+    const double inv = yy > 0 ? 1.0 / sqrt(yy) : 0.0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < k; i += blockDim.x) x[i] = y[i] * inv;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *nu = coef * sqrt(fmax(lam, 0.0));
+}
+
+// Y (n x k, ld k) += nu Omega with Omega = S^T for a SparseStack S (k x n):
+// row i gets rho_it / sqrt(zeta) * nu in column t nb + s_it.
+__global__ void add_omega_ss_kernel(double* __restrict__ Y, int64_t n, int k, int zeta, int nb, uint32_t k0, uint32_t k1,
+                                    double scale, const double* __restrict__ nup) {
+  const double nu = *nup;
+  const int ng = (zeta + 3) / 4;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n * ng;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / ng;
+    const int g = (int)(idx - i * ng);
+    const U4 w = philox4x32_10(U4{(uint32_t)i, (uint32_t)((uint64_t)i >> 32), (uint32_t)g, kTagSparseStack}, k0, k1);
+    for (int j = 0; j < 4; ++j) {
+      const int t = 4 * g + j;
+      if (t < zeta) {
+        const uint32_t word = word_of(w, j);
+        const double v = (ss_negative(word) ? -scale : scale) * nu;
+        Y[i * k + (int64_t)t * nb + ss_bucket(word, (uint32_t)nb)] += v;
+      }
+    }
+  }
+}
+
+// Y (n x k) += nu Omega with Omega = G^T, G (k x n, row-major) written out.
+__global__ void add_omega_dense_kernel(double* __restrict__ Y, int64_t n, int k, const double* __restrict__ G,
+                                       const double* __restrict__ nup) {
+  const double nu = *nup;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n * k;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / k, j = idx - i * k;
+    Y[idx] += nu * G[j * n + i];
+  }
+}
+
+// B (k x k) <- (B + B^T) / 2
+__global__ void symmetrize_kernel(double* __restrict__ B, int k) {
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (int64_t)k * k;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / k, j = idx - i * k;
+    if (i < j) {
+      const double v = 0.5 * (B[i * k + j] + B[j * k + i]);
+      B[i * k + j] = v;
+      B[j * k + i] = v;
+    }
+  }
+}
+
+// lambda_j = max(0, s_j^2 - nu)
+__global__ void remove_shift_kernel(const double* __restrict__ s, int k, const double* __restrict__ nup,
+                                    double* __restrict__ lambda) {
+  const double nu = *nup;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < k; j += gridDim.x * blockDim.x)
+    lambda[j] = fmax(0.0, s[j] * s[j] - nu);
+}
+
+int launch_nystrom_shift(const double* G, int k, int64_t n, double* nu, hipStream_t st) {
+  const double coef = std::sqrt((double)n) * 0x1p-52;
+  const size_t lds = (size_t)2 * k * sizeof(double);
+  SK_HIP(hipFuncSetAttribute((const void*)power_norm_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(power_norm_kernel, dim3(1), dim3(1024), lds, st, G, k, coef, nu);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+int launch_add_omega_ss(double* Y, int64_t n, int k, int zeta, int nb, uint32_t k0, uint32_t k1, double scale,
+                        const double* nu, hipStream_t st) {
+  hipLaunchKernelGGL(add_omega_ss_kernel, dim3(grid_for(n * ((zeta + 3) / 4))), dim3(256), 0, st, Y, n, k, zeta, nb,
+                     k0, k1, scale, nu);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+int launch_add_omega_dense(double* Y, int64_t n, int k, const double* G, const double* nu, hipStream_t st) {
+  hipLaunchKernelGGL(add_omega_dense_kernel, dim3(grid_for(n * k)), dim3(256), 0, st, Y, n, k, G, nu);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+int launch_symmetrize(double* B, int k, hipStream_t st) {
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(grid_for((int64_t)k * k)), dim3(256), 0, st, B, k);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+int launch_remove_shift(const double* s, int k, const double* nu, double* lambda, hipStream_t st) {
+  hipLaunchKernelGGL(remove_shift_kernel, dim3((k + 255) / 256), dim3(256), 0, st, s, k, nu, lambda);
   SK_HIP(hipGetLastError());
   return SK_OK;
 }

@@ -29,6 +29,18 @@ int jacobi_svd_rounds(const double* M, int64_t rows, int k, int input_colmajor, 
 int launch_gn_truncate(const double* s, int k, const double* V, double* Vs, const double* U, int p, double* Ur,
                        int* rank, hipStream_t st);
 
+// Nystrom (Alg. 2) helpers: *nu = sqrt(n) 2^-52 sqrt(lambda_max(G)) (G = Y^T Y,
+// power iteration); Y += nu Omega for Omega = S^T of a SparseStack sketch, or
+// of a dense G (k x n) written out; B <- (B + B^T)/2; lambda = max(0, s^2 - nu).
+int launch_nystrom_shift(const double* G, int k, int64_t n, double* nu, hipStream_t st);
+int launch_add_omega_ss(double* Y, int64_t n, int k, int zeta, int nb, uint32_t k0, uint32_t k1, double scale,
+                        const double* nu, hipStream_t st);
+int launch_add_omega_dense(double* Y, int64_t n, int k, const double* G, const double* nu, hipStream_t st);
+int launch_symmetrize(double* B, int k, hipStream_t st);
+int launch_remove_shift(const double* s, int k, const double* nu, double* lambda, hipStream_t st);
+// G (d x n, F64 row-major) = the entries of a Gaussian sketch.
+int launch_gauss_fill_f64(const sk_sketch* S, double* G, hipStream_t st);
+
 // Row-major GEMM on the handle's rocBLAS handle and stream:
 // C (M x N) = alpha op(A) op(B) + beta C; dtype SK_F64 or SK_F32.
 int gemm_rm(sk_sketch* S, int dtype, bool transA, bool transB, int64_t M, int64_t N, int64_t K, double alpha,

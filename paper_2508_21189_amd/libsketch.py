@@ -96,6 +96,12 @@ class GnInfo(ctypes.Structure):
                 ("t_core_ms", ctypes.c_double), ("t_factors_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
 
 
+class NystromInfo(ctypes.Structure):
+    """sk_nystrom_info."""
+    _fields_ = [("nu", ctypes.c_double), ("t_sketch_ms", ctypes.c_double), ("t_core_ms", ctypes.c_double),
+                ("t_total_ms", ctypes.c_double), ("jacobi_sweeps", ctypes.c_int)]
+
+
 def _as_dict(st):
     return {name: getattr(st, name) for name, _ in st._fields_}
 
@@ -109,6 +115,7 @@ _DRIVER_SIGS = {
     "gen_nystrom": [_vp, _vp, ctypes.c_int, _i64, _vp, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(GnInfo), _vp],
     "gen_nystrom_svd": [_vp, _vp, ctypes.c_int, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, ctypes.POINTER(GnInfo),
                         _vp],
+    "nystrom_psd": [_vp, ctypes.c_int, _vp, _i64, _vp, _i64, _vp, ctypes.POINTER(NystromInfo), _vp],
 }
 
 
@@ -297,3 +304,16 @@ def gen_nystrom(S_omega, S_psi, A, form="outer", stream=None):
                                        _ptr(sig), _ptr(V), k, ctypes.byref(info), _stream(stream)))
         return U, sig, V, rc, _as_dict(info)
     raise ValueError("form must be 'outer' or 'svd'")
+
+
+def nystrom_psd(S, A, stream=None):
+    """Alg. 2 with Omega = S^T (S a k x n sketch): returns (U, lambda, status, info), A ~ U diag(lambda) U^T."""
+    assert A.is_cuda and A.dim() == 2 and A.shape[0] == A.shape[1] == S.n and A.stride(1) == 1
+    assert A.dtype in (torch.float32, torch.float64)
+    n, k = S.n, S.d
+    U = torch.empty((n, k), dtype=torch.float64, device=A.device)
+    lam = torch.empty(k, dtype=torch.float64, device=A.device)
+    info = NystromInfo()
+    rc = check(load().nystrom_psd(S.h, _DT[A.dtype], _ptr(A), A.stride(0), _ptr(U), k, _ptr(lam), ctypes.byref(info),
+                                  _stream(stream)))
+    return U, lam, rc, _as_dict(info)

@@ -62,7 +62,8 @@ def _header_struct_fields(name):
 
 
 @pytest.mark.parametrize("cname,pyname", [("sk_solve_info", "SolveInfo"), ("sk_lsqr_info", "LsqrInfo"),
-                                           ("sk_rsvd_info", "RsvdInfo"), ("sk_gn_info", "GnInfo")])
+                                           ("sk_rsvd_info", "RsvdInfo"), ("sk_gn_info", "GnInfo"),
+                                           ("sk_nystrom_info", "NystromInfo")])
 def test_info_structs_match_header(cname, pyname):
     import ctypes as ct
     from paper_2508_21189_amd import libsketch
@@ -85,3 +86,4 @@ def test_driver_null_handle_fails_cleanly():
     assert lib.rsvd(None, 1, 4, None, 4, None, 4, None, None, 4, None, None) == libsketch.SK_E_INVAL
     assert lib.gen_nystrom(None, None, 1, 4, None, 4, None, 4, None, 4, None, None) == libsketch.SK_E_INVAL
     assert lib.gen_nystrom_svd(None, None, 1, 4, None, 4, None, 4, None, None, 4, None, None) == libsketch.SK_E_INVAL
+    assert lib.nystrom_psd(None, 1, None, 4, None, 4, None, None, None) == libsketch.SK_E_INVAL
