@@ -251,6 +251,45 @@ def gn_variants(libsketch, inputs, torch, reps):
     return out
 
 
+def nystrom_variants(libsketch, inputs, torch, reps):
+    """Nystrom (Alg. 2) on a 32768 x 32768 float32 psd stand-in (rank 1000,
+    i^-2 spectrum, + 1e-6 I), k = 512, SparseStack (zeta = 4) and Gaussian
+    Omega; relative error ||A - U diag(lam) U^T||_F / ||A||_F on the device."""
+    import statistics
+    n, k = 32768, 512
+    print("bench: generating the %d x %d psd stand-in" % (n, n), file=sys.stderr, flush=True)
+    A = inputs.psd_stand_in(n, seed=DATA_SEED + 4)
+    nA = sum(float(torch.sum(A[r0:r0 + 4096].double() ** 2)) for r0 in range(0, n, 4096)) ** 0.5
+    out = {"workload": "psd stand-in A %dx%d f32 (rank 1000, i^-2 spectrum, + 1e-6 I), k=%d" % (n, n, k)}
+    for kind, zeta in (("sparsestack", 4), ("gaussian", 1)):
+        S = libsketch.Sketch(kind, k, n, zeta, SKETCH_SEED + 5)
+        r = libsketch.nystrom_psd(S, A)
+        walls = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = libsketch.nystrom_psd(S, A)
+            torch.cuda.synchronize()
+            walls.append((time.perf_counter() - t0) * 1e3)
+        U, lam, rc, info = r
+        acc = 0.0
+        Ul = U * lam[None, :]
+        for r0 in range(0, n, 4096):
+            E = A[r0:r0 + 4096].double() - Ul[r0:r0 + 4096] @ U.T
+            acc += float(torch.sum(E * E))
+        out[kind] = {"total_ms": round(statistics.median(walls), 3), "status": rc,
+                     "t_sketch_ms": round(info["t_sketch_ms"], 3), "t_core_ms": round(info["t_core_ms"], 3),
+                     "jacobi_sweeps": info["jacobi_sweeps"], "rel_error_fro": acc ** 0.5 / nA}
+        print("bench: nystrom %s %.2f ms, error %.3e" % (kind, out[kind]["total_ms"], out[kind]["rel_error_fro"]),
+              file=sys.stderr, flush=True)
+        del U, lam, Ul, r, S
+        torch.cuda.empty_cache()
+    out["speedup_vs_gaussian"] = round(out["gaussian"]["total_ms"] / out["sparsestack"]["total_ms"], 3)
+    del A
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,6 +305,7 @@ def main():
     ap.add_argument("--rsvd-reps", type=int, default=1, help="timed randomized SVDs per sketch kind (0 = skip)")
     ap.add_argument("--gn-reps", type=int, default=1,
                     help="timed generalized Nystrom calls per sketch kind and form (0 = skip)")
+    ap.add_argument("--nystrom-reps", type=int, default=1, help="timed Nystrom calls per sketch kind (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -337,6 +377,8 @@ def main():
         rec["rsvd"] = rsvd_variants(libsketch, inputs, torch, args.rsvd_reps)
     if args.gn_reps > 0:
         rec["gen_nystrom"] = gn_variants(libsketch, inputs, torch, args.gn_reps)
+    if args.nystrom_reps > 0:
+        rec["nystrom"] = nystrom_variants(libsketch, inputs, torch, args.nystrom_reps)
     if not args.no_cpu:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(cpu_sample, args.cpu_rows)

@@ -104,3 +104,21 @@ def snapshots_stand_in(rows=131072, cols=40000, rank=300, noise=1e-6, seed=0, de
                       alpha=noise / cols ** 0.5)
     A -= A.mean(dim=0, keepdim=True)
     return A
+
+
+def psd_stand_in(n=32768, rank=1000, delta=1e-6, seed=0, device="cuda", dtype=torch.float32):
+    """Synthetic psd matrix (kernel/covariance stand-in): A = V diag(i^-2) V^T +
+    delta I with V Haar-orthonormal (n x rank), built in F64 in row blocks
+    and cast to dtype."""
+    g = _gen(device, seed)
+    V, _ = torch.linalg.qr(torch.randn((n, rank), generator=g, dtype=torch.float64, device=device))
+    lam = torch.arange(1, rank + 1, dtype=torch.float64, device=device) ** -2.0
+    Vl = V * lam[None, :]
+    A = torch.empty((n, n), dtype=dtype, device=device)
+    blk = 4096
+    for r0 in range(0, n, blk):
+        r1 = min(n, r0 + blk)
+        B = Vl[r0:r1] @ V.T
+        B[:, r0:r1].diagonal().add_(delta)
+        A[r0:r1] = B.to(dtype)
+    return A
