@@ -189,6 +189,12 @@ struct RowsArgs {
   void* P;
   int buf_stride, off_zero, off_plan, plan_dma_bytes, off_xtra;
   int rowb;  // LDS bytes of a tile row: the slab's columns, rounded up to 16
+  // Direct loads: load k of a tile covers tile bytes [k*64*LB, (k+1)*64*LB);
+  // a wave issues loads wave, wave + W, ... so from one of its loads to the
+  // next every lane advances by step_rows rows and step_cb bytes (step_cb <
+  // rowb), with a carry into the row when the byte offset passes rowb.
+  int step_rows, step_cb;
+  uint32_t rowb_magic;  // ceil(2^32 / rowb): x / rowb = umulhi(x, rowb_magic) for x < 2^23
 };
 
 template <typename Tin>
@@ -286,34 +292,50 @@ __global__ void __launch_bounds__(1024) ss_rows_kernel(RowsArgs a) {
     ((uint32_t*)(smem + b * a.buf_stride + a.off_zero))[i - b * (ZROWB / 4)] = 0u;
   }
 
+  const int rowb = a.rowb;
+  const int n_instr = (R * rowb + 64 * LB - 1) / (64 * LB);
+
   auto issue_loads = [&](int st, int buf) {
     const int64_t r0 = r_begin + (int64_t)st * R;
     const int rv = (int)min((int64_t)R, r_end - r0);
     unsigned char* dst = smem + buf * a.buf_stride;
-    const int rowb = a.rowb;
-    const int tile_bytes = R * rowb;
-    const int n_instr = (tile_bytes + 64 * LB - 1) / (64 * LB);
+    const unsigned char* tsrc = a.A + r0 * a.lda_bytes + col0 * ES;
+    // (row, byte in row) of this lane in the wave's first load; later loads
+    // advance incrementally. Recomputed per tile (a multiply-high; the byte
+    // offset is below 2^14 and rowb at most 512, so the quotient is exact)
+    // rather than kept live across the tile loop.
+    uint32_t fb = (uint32_t)(wave * 64 + lane) * LB;
+    asm volatile("" : "+v"(fb));
+    int row = (int)__umulhi(fb, a.rowb_magic);
+    int cb = (int)fb - row * rowb;
     for (int k = wave; k < n_instr; k += nwaves) {
-      const int byte = (k * 64 + lane) * LB;
-      const int row = byte / rowb;
-      const int cb = byte - row * rowb;
       const unsigned char* src = a.A;  // in-bounds stand-in for padding lanes
-      if (row < rv && cb < slab_bytes) src = a.A + (r0 + row) * a.lda_bytes + col0 * ES + cb;
+      if (row < rv && cb < slab_bytes) src = tsrc + (int64_t)row * a.lda_bytes + cb;
       const uint32_t la = (uint32_t)__builtin_amdgcn_readfirstlane((int)lds_addr_of(dst + k * 64 * LB));
-      // lanes past the tile stay inactive: their slots hold the zero row
-      if (byte < tile_bytes) {
+      // lanes past the tile (row >= R) stay inactive: their slots hold the zero row
+      if (row < R) {
         if constexpr (LB == 16)
           dma_to_lds16(src, la);
         else
           dma_to_lds4(src, la);
       }
+      row += a.step_rows;
+      cb += a.step_cb;
+      if (cb >= rowb) {
+        cb -= rowb;
+        row += 1;
+      }
     }
     // the tile's plan records for this group's blocks (contiguous)
     const unsigned char* psrc = a.plan + ((r0 / R) * a.zeta + t0) * (int64_t)a.rec_bytes;
     unsigned char* pdst = dst + a.off_plan;
+    // lane * 16 is recomputed here rather than kept live across the tile
+    // loop: that would take a register the accumulators need
+    int l16 = lane * 16;
+    asm volatile("" : "+v"(l16));
     for (int k = wave; k * 1024 < a.plan_dma_bytes; k += nwaves) {
       const uint32_t la = (uint32_t)__builtin_amdgcn_readfirstlane((int)lds_addr_of(pdst + k * 1024));
-      dma_to_lds16(psrc + k * 1024 + lane * 16, la);
+      dma_to_lds16(psrc + k * 1024 + l16, la);
     }
   };
 
@@ -770,6 +792,12 @@ static int launch_rows_t(const sk_sketch* S, const RowsPlan& p, int64_t m, const
   a.P = P;
   const RowsLds l = rows_lds(es, p.R, p.rowb, p.bpg, p.rec_bytes, p.W);
   a.rowb = p.rowb;
+  {
+    const int step = 64 * p.W * p.load_bytes;
+    a.step_rows = step / p.rowb;
+    a.step_cb = step % p.rowb;
+    a.rowb_magic = (uint32_t)(((1ull << 32) + (uint64_t)p.rowb - 1) / (uint64_t)p.rowb);
+  }
   a.buf_stride = (int)l.buf_stride;
   a.off_zero = (int)l.zero;
   a.off_plan = (int)l.plan;
