@@ -16,6 +16,7 @@ Modules
   philox     Philox4x32-10 counter-based generator (Salmon et al., SC'11),
              the random source for every sketch (readings: see each function).
   sketches   SparseStack (Def. 1.5), CountSketch (eq. B.1), SRTT (eq. 1.1),
+             SparseRTT (Def. 1.7, SparseCol of Def. 4.1),
              Gaussian test matrix (Def. 1.4): dense construction and
              application S @ A, A @ S^T, S^T @ Y.
   lstsq      sketch-and-solve (Alg. 3), exact least squares by Householder

@@ -30,6 +30,7 @@ TAG_SPARSESTACK = 1
 TAG_SRTT_SIGN = 2
 TAG_SRTT_SAMPLE = 3
 TAG_GAUSS = 4
+TAG_SPARSECOL = 5
 
 
 def philox4x32_10(c0, c1, c2, c3, k0, k1):

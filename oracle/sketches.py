@@ -210,6 +210,90 @@ def srtt_dense(n, d, seed):
 
 
 # ----------------------------------------------------------------------------
+# SparseRTT (Def. 1.7) with a SparseCol sparse factor (Def. 4.1)
+# ----------------------------------------------------------------------------
+def sparsertt_default_xi(d, npad):
+    """Column sparsity xi = ceil(1.5 log k) at embedding dimension k = d (Sec. 4.3).
+
+    Reading: log is the natural logarithm; xi is clamped to [1, npad].
+    """
+    return int(min(max(1, math.ceil(1.5 * math.log(d))), npad))
+
+
+def sparsecol_selectors(npad, d, xi, seed):
+    """Selectors and signs of the SparseCol matrix (Def. 4.1): for each column j < d,
+    xi distinct indices of [0, npad) and xi Rademacher signs.
+
+    Column j draws its selectors without replacement by Floyd's algorithm: for
+    t = npad-xi .. npad-1, the Philox words of counter (t mod 2^32, t >> 32, j,
+    TAG_SPARSECOL) give u = (w0 * (t+1)) >> 32, uniform on {0..t}; the index
+    taken at this step is u, or t if u was taken before, and its sign is -1
+    iff bit 0 of w1 is 1. Returns (sel, sgn), each d x xi, every row sorted by
+    index (the order in which the sketch adds the selected rows).
+    """
+    if not 1 <= xi <= npad:
+        raise ValueError("SparseCol needs 1 <= xi <= npad")
+    k0, k1 = px.key_of_seed(seed)
+    t = np.arange(npad - xi, npad, dtype=np.uint64)
+    sel = np.zeros((d, xi), dtype=np.int64)
+    sgn = np.zeros((d, xi))
+    for j in range(d):
+        w0, w1, _, _ = px.philox4x32_10(t & np.uint64(0xFFFFFFFF), t >> np.uint64(32), j, px.TAG_SPARSECOL, k0, k1)
+        taken = {}
+        for q in range(xi):
+            tq = int(t[q])
+            u = (int(w0[q]) * (tq + 1)) >> 32
+            idx = tq if u in taken else u
+            taken[idx] = -1.0 if (int(w1[q]) & 1) else 1.0
+        order = sorted(taken)
+        sel[j] = order
+        sgn[j] = [taken[i] for i in order]
+    return sel, sgn
+
+
+def sparsecol_dense(npad, d, xi, seed):
+    """The SparseCol matrix (npad x d) of Def. 4.1: column j is
+    (1/sqrt(d)) sqrt(npad/xi) sum_i rho_ji e_{s_ji}."""
+    sel, sgn = sparsecol_selectors(npad, d, xi, seed)
+    M = np.zeros((npad, d))
+    for j in range(d):
+        M[sel[j], j] = sgn[j] * math.sqrt(npad / xi) / math.sqrt(d)
+    return M
+
+
+def sparsertt_apply(A, d, xi, seed):
+    """SA = Omega^T A for the SparseRTT Omega = D F S (Def. 1.7), S = SparseCol.
+
+    A is padded with zero rows to npad = 2^ceil(log2 n) (the WHT needs a power
+    of two); D is the SRTT's Rademacher diagonal, F = H/sqrt(npad) the unitary
+    WHT. Since F and D are symmetric, row j of Omega^T A_pad is
+    (1/sqrt(d)) sqrt(npad/xi) (1/sqrt(npad)) sum_i rho_ji (H D A_pad)[s_ji]
+    = (1/sqrt(d xi)) sum_i rho_ji (H D A_pad)[s_ji]; the selected rows are
+    added in increasing index order and the sum is scaled once.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[0]
+    npad = srtt_padded_length(n)
+    Dsig = srtt_signs(npad, seed)
+    Ap = np.zeros((npad,) + A.shape[1:])
+    Ap[:n] = A * Dsig[:n].reshape((n,) + (1,) * (A.ndim - 1))
+    HA = fwht_rows(Ap)
+    sel, sgn = sparsecol_selectors(npad, d, xi, seed)
+    out = np.zeros((d,) + A.shape[1:])
+    for j in range(d):
+        acc = np.zeros(A.shape[1:])
+        for q in range(xi):
+            acc = acc + sgn[j, q] * HA[sel[j, q]]
+        out[j] = acc
+    return out * inv_sqrt(d * xi)
+
+
+def sparsertt_dense(n, d, xi, seed):
+    """The SparseRTT sketch S = Omega^T (d x n) formed explicitly (small n only)."""
+    return sparsertt_apply(np.eye(n), d, xi, seed)
+
+
+# ----------------------------------------------------------------------------
 # Gaussian test matrix (Def. 1.4): iid N(0, 1/d) entries for S (d x n)
 # ----------------------------------------------------------------------------
 TWO_PI = 2.0 * math.pi
@@ -269,6 +353,7 @@ def gaussian_apply(A, d, seed, chunk=1 << 16):
 KIND_SPARSESTACK = 0
 KIND_GAUSSIAN = 1
 KIND_SRTT = 2
+KIND_SPARSERTT = 3
 KIND_IDENTITY = 99
 
 
@@ -280,6 +365,9 @@ def apply(kind, A, d, zeta, seed):
         return gaussian_apply(A, d, seed)
     if kind == KIND_SRTT:
         return srtt_apply(A, d, seed)
+    if kind == KIND_SPARSERTT:
+        npad = srtt_padded_length(np.asarray(A).shape[0])
+        return sparsertt_apply(A, d, zeta if zeta else sparsertt_default_xi(d, npad), seed)
     if kind == KIND_IDENTITY:
         return np.asarray(A, dtype=np.float64).copy()
     raise ValueError(kind)
@@ -292,6 +380,8 @@ def dense(kind, n, d, zeta, seed):
         return gaussian_dense(n, d, seed)
     if kind == KIND_SRTT:
         return srtt_dense(n, d, seed)
+    if kind == KIND_SPARSERTT:
+        return sparsertt_dense(n, d, zeta if zeta else sparsertt_default_xi(d, srtt_padded_length(n)), seed)
     if kind == KIND_IDENTITY:
         return np.eye(n)
     raise ValueError(kind)
