@@ -41,6 +41,7 @@ enum {
   SK_SPARSESTACK = 0, /* Def. 1.5: d rows in zeta blocks of d/zeta; one +-1/sqrt(zeta) per block per column */
   SK_GAUSSIAN = 1,    /* Def. 1.4: iid N(0, 1/d) entries */
   SK_SRTT = 2,        /* eq. (1.1) with a uniform restriction: (1/sqrt(d)) R H D, H = Walsh-Hadamard */
+  SK_SPARSERTT = 3,   /* Def. 1.7: Omega^T for Omega = D F S, F = unitary WHT, S = SparseCol (Def. 4.1) */
   SK_IDENTITY_TEST = 99 /* S = I (d = n); exists to test the drivers against exact least squares */
 };
 
@@ -69,9 +70,22 @@ enum {
  *         Row t*(d/zeta) + s of S holds rho/sqrt(zeta) (Def. 1.5).
  *   kind  SK_GAUSSIAN: zeta ignored; entries from Philox + Box-Muller.
  *   kind  SK_SRTT: zeta ignored; requires d <= 2^ceil(log2 n).
+ *   kind  SK_SPARSERTT: zeta is the column sparsity xi of the SparseCol
+ *         factor (Def. 4.1), 1 <= xi <= npad = 2^ceil(log2 n); zeta = 0
+ *         selects xi = ceil(1.5 ln d) (Sec. 4.3), clamped to [1, npad].
+ *         Row j of S A is (1/sqrt(d xi)) sum_i rho_ji (H D A_pad)[s_ji]: D
+ *         is the SRTT's sign diagonal, H the unnormalized Walsh-Hadamard
+ *         matrix, A_pad A with zero rows up to npad. Row j's xi selectors
+ *         are distinct, drawn by Floyd's algorithm: for t = npad-xi ..
+ *         npad-1, Philox counter (t mod 2^32, t >> 32, j, 5) gives words
+ *         w0, w1; u = (w0 (t+1)) >> 32; the index taken is u, or t if u was
+ *         taken before; its sign rho is -1 iff bit 0 of w1 is 1. Selected
+ *         rows are added in increasing index order. sketch_info reports xi
+ *         as zeta.
  *   kind  SK_IDENTITY_TEST: requires d == n.
  * Nothing about S is stored beyond its parameters (and, for SRTT, the d
- * sampled row indices): entries are regenerated from the seed on demand.
+ * sampled row indices; for SparseRTT, the d xi selectors and signs):
+ * entries are regenerated from the seed on demand.
  * Returns NULL on error (see sketch_last_error). Synchronizes the device.
  */
 sketch_t sketch_create(int kind, int64_t d, int64_t n, int zeta, uint64_t seed);
@@ -97,7 +111,7 @@ int sketch_info(sketch_t S, int* kind, int64_t* d, int64_t* n, int* zeta, uint64
  * Kinds: SparseStack takes every input type. Gaussian takes F64 input (F64
  * output; G generated inside the MFMA kernel, never stored) or F32 input
  * (G, d x n F32, written into the workspace and one SGEMM; needs
- * d * n * 4 <= 8 GB). SRTT takes F64 input (F64 output).
+ * d * n * 4 <= 8 GB). SRTT and SparseRTT take F64 input (F64 output).
  * The result is deterministic (the same inputs give bitwise identical SA on
  * every run: no atomics, fixed summation order), except the F32 Gaussian
  * path, whose GEMM follows rocBLAS.
@@ -111,9 +125,10 @@ int sketch_apply(sketch_t S, int dtype_in, int layout, int64_t m, const void* A,
  *   SparseStack: any input type, F32 accumulation for F32/BF16, F64 for F64.
  *   Gaussian: F64 or F32 input; G (d x n) is generated into the workspace and
  *     Y = A G^T is one GEMM on the matrix cores (F32 GEMM for F32 input).
- *   SRTT: one Walsh-Hadamard transform per row in LDS; needs
+ *   SRTT and SparseRTT: one Walsh-Hadamard transform per row in LDS; needs
  *     npad * element size <= 160 KB (npad <= 2^15 for F32/BF16, 2^14 for F64).
- * Deterministic for SparseStack and SRTT; the Gaussian GEMM follows rocBLAS.
+ * Deterministic for SparseStack, SRTT and SparseRTT; the Gaussian GEMM
+ * follows rocBLAS.
  */
 int sketch_apply_T(sketch_t S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out,
                    void* Y, int64_t ldy, void* ws, size_t ws_bytes, void* stream);

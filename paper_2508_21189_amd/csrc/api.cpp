@@ -36,6 +36,35 @@ static std::vector<int64_t> srtt_sample_host(int64_t npad, int64_t d, uint32_t k
   return std::vector<int64_t>(chosen.begin(), chosen.end());
 }
 
+// SparseCol selectors (Def. 4.1): for each output row j, xi distinct
+// indices of [0, npad) by Floyd's algorithm with Philox counter
+// (t, j, TAG) for t = npad-xi .. npad-1: u = (w0 * (t+1)) >> 32 is uniform
+// on {0..t}; the index taken is u, or t if u is taken; its sign is -1 iff
+// bit 0 of w1 is 1. Each row's selectors are sorted by index.
+static void sparsecol_host(int64_t npad, int64_t d, int xi, uint32_t k0, uint32_t k1, std::vector<int64_t>& sel,
+                           std::vector<int8_t>& sgn) {
+  sel.resize((size_t)d * xi);
+  sgn.resize((size_t)d * xi);
+  std::vector<std::pair<int64_t, int8_t>> picks;
+  std::set<int64_t> taken;
+  for (int64_t j = 0; j < d; ++j) {
+    picks.clear();
+    taken.clear();
+    for (int64_t t = npad - xi; t < npad; ++t) {
+      const U4 w = philox4x32_10(U4{(uint32_t)t, (uint32_t)((uint64_t)t >> 32), (uint32_t)j, kTagSparseCol}, k0, k1);
+      const int64_t u = (int64_t)(((uint64_t)w.x * (uint64_t)(t + 1)) >> 32);
+      const int64_t idx = taken.count(u) ? t : u;
+      taken.insert(idx);
+      picks.push_back({idx, (int8_t)((w.y & 1u) ? -1 : 1)});
+    }
+    std::sort(picks.begin(), picks.end());
+    for (int q = 0; q < xi; ++q) {
+      sel[(size_t)j * xi + q] = picks[q].first;
+      sgn[(size_t)j * xi + q] = picks[q].second;
+    }
+  }
+}
+
 // Grows the handle-owned workspace (used when the caller passes ws = NULL).
 int handle_workspace(sk_sketch* S, size_t bytes, void** out) {
   if (bytes == 0) {
@@ -89,6 +118,17 @@ sketch_t sketch_create(int kind, int64_t d, int64_t n, int zeta, uint64_t seed) 
       set_error("sketch_create: SRTT needs d <= 2^ceil(log2 n)");
       return nullptr;
     }
+  } else if (kind == SK_SPARSERTT) {
+    int64_t np = 1;
+    while (np < n) np <<= 1;
+    if (zeta < 0 || zeta > np) {
+      set_error("sketch_create: SparseRTT needs 0 <= zeta (column sparsity) <= 2^ceil(log2 n)");
+      return nullptr;
+    }
+    if (d > (int64_t)0xFFFFFFFF) {
+      set_error("sketch_create: SparseRTT needs d < 2^32");
+      return nullptr;
+    }
   } else if (kind == SK_IDENTITY_TEST) {
     if (d != n) {
       set_error("sketch_create: identity sketch needs d == n");
@@ -103,6 +143,15 @@ sketch_t sketch_create(int kind, int64_t d, int64_t n, int zeta, uint64_t seed) 
   S->d = d;
   S->n = n;
   S->zeta = kind == SK_SPARSESTACK ? zeta : 1;
+  if (kind == SK_SPARSERTT) {
+    int64_t np = 1;
+    while (np < n) np <<= 1;
+    int64_t xi = zeta;
+    if (xi == 0) xi = (int64_t)std::ceil(1.5 * std::log((double)d));
+    xi = std::max<int64_t>(1, std::min<int64_t>(xi, np));
+    S->xi = (int)xi;
+    S->zeta = (int)xi;
+  }
   S->seed = seed;
   S->nb = kind == SK_SPARSESTACK ? d / zeta : 0;
   S->k0 = (uint32_t)seed;
@@ -112,18 +161,28 @@ sketch_t sketch_create(int kind, int64_t d, int64_t n, int zeta, uint64_t seed) 
     delete S;
     return nullptr;
   }
-  if (kind == SK_SRTT) {
+  if (trig_kind(kind)) {
     S->npad = 1;
     S->log2npad = 0;
     while (S->npad < n) {
       S->npad <<= 1;
       S->log2npad++;
     }
-    S->h_sample = srtt_sample_host(S->npad, d, S->k0, S->k1);
-    if (hipMalloc(&S->d_sample, sizeof(int64_t) * d) != hipSuccess ||
-        hipMemcpy(S->d_sample, S->h_sample.data(), sizeof(int64_t) * d, hipMemcpyHostToDevice) != hipSuccess) {
-      set_error("sketch_create: device allocation for the SRTT sample failed");
+    std::vector<int8_t> h_sgn;
+    if (kind == SK_SRTT)
+      S->h_sample = srtt_sample_host(S->npad, d, S->k0, S->k1);
+    else
+      sparsecol_host(S->npad, d, S->xi, S->k0, S->k1, S->h_sample, h_sgn);
+    const size_t cnt = S->h_sample.size();
+    bool ok = hipMalloc(&S->d_sample, sizeof(int64_t) * cnt) == hipSuccess &&
+              hipMemcpy(S->d_sample, S->h_sample.data(), sizeof(int64_t) * cnt, hipMemcpyHostToDevice) == hipSuccess;
+    if (ok && kind == SK_SPARSERTT)
+      ok = hipMalloc(&S->d_sgn, cnt) == hipSuccess &&
+           hipMemcpy(S->d_sgn, h_sgn.data(), cnt, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+      set_error("sketch_create: device allocation for the transform sketch's selectors failed");
       if (S->d_sample) (void)hipFree(S->d_sample);
+      if (S->d_sgn) (void)hipFree(S->d_sgn);
       delete S;
       return nullptr;
     }
@@ -168,6 +227,7 @@ int sketch_destroy(sketch_t S) {
   drop_events(S);
   if (S->ws) (void)hipFree(S->ws);
   if (S->d_sample) (void)hipFree(S->d_sample);
+  if (S->d_sgn) (void)hipFree(S->d_sgn);
   drivers_release(S);
   delete S;
   return SK_OK;

@@ -3,10 +3,12 @@
 //   * Gaussian (Def. 1.4): S = G is d x n, small enough in this orientation
 //     to be written out once (the same Philox + Box-Muller entries as the row
 //     mode), after which Y = A G^T is one GEMM on the matrix cores (rocBLAS);
-//   * SRTT (eq. 1.1): every row of A is one length-npad Walsh-Hadamard
-//     transform, done in LDS by one workgroup per row (npad <= 2^15 for
-//     32-bit input, 2^14 for 64-bit), followed by the gather of the d sampled
-//     entries. The Rademacher signs are the row mode's (index = column).
+//   * SRTT (eq. 1.1) and SparseRTT (Def. 1.7): every row of A is one
+//     length-npad Walsh-Hadamard transform, done in LDS by one workgroup per
+//     row (npad <= 2^15 for 32-bit input, 2^14 for 64-bit), followed by the
+//     gather of the d sampled entries (SRTT) or the signed sums of xi
+//     selected entries per output (SparseRTT). The Rademacher signs are the
+//     row mode's (index = column).
 #include <algorithm>
 
 #include "sk_drivers.hpp"
@@ -50,12 +52,14 @@ __device__ inline float srtt_ld<uint16_t>(const uint16_t* p) {
 }
 
 // One row per workgroup iteration: x = D a (padded), x = H x in LDS, then
-// Y[r][j] = x[sample[j]] / sqrt(d). Tacc: float for 32-bit and 16-bit
-// input, double for 64-bit input.
+// Y[r][j] = scale * sum_{i < xi} rho_ji x[sample[j*xi + i]] (SRTT: xi = 1,
+// no signs, scale 1/sqrt(d)). Tacc: float for 32-bit and 16-bit input,
+// double for 64-bit input.
 template <typename Tin, typename Tacc>
 __global__ void __launch_bounds__(1024) srtt_cols_kernel(const Tin* __restrict__ A, int64_t lda, int64_t rows,
                                                          int64_t n, int p, const int64_t* __restrict__ sample,
-                                                         int64_t d, double scale, uint32_t k0, uint32_t k1,
+                                                         const int8_t* __restrict__ sgn, int xi, int64_t d,
+                                                         double scale, uint32_t k0, uint32_t k1,
                                                          void* __restrict__ Y, int64_t ldy, int out_f64) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   Tacc* x = (Tacc*)smem;
@@ -85,7 +89,11 @@ __global__ void __launch_bounds__(1024) srtt_cols_kernel(const Tin* __restrict__
       __syncthreads();
     }
     for (int64_t j = tid; j < d; j += nt) {
-      const Tacc v = x[sample[j]];
+      Tacc v = 0;
+      for (int i = 0; i < xi; ++i) {
+        const Tacc u = x[sample[j * xi + i]];
+        v += (sgn && sgn[j * xi + i] < 0) ? -u : u;
+      }
       if (out_f64)
         ((double*)Y)[r * ldy + j] = (double)v * scale;
       else
@@ -200,33 +208,33 @@ int launch_cols_dense(sk_sketch* S, int dtype_in, int64_t rows, const void* A, i
     }
     return launch_convert(SK_F32, Yf, S->d, SK_F64, Y, ldy, rows, S->d, st);
   }
-  // SRTT
+  // SRTT and SparseRTT
   const int p = S->log2npad;
   const size_t es = dtype_in == SK_F64 ? 8 : 4;
   const size_t lds = ((size_t)1 << p) * es;
   if (lds > 160 * 1024) {
-    set_error("sketch_apply_T: SRTT column mode needs npad * element size <= 160 KB");
+    set_error("sketch_apply_T: SRTT/SparseRTT column mode needs npad * element size <= 160 KB");
     return SK_E_NOTSUP;
   }
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(rows, 4096));
-  const double scale = inv_sqrt_host((double)S->d);
+  const double scale = trig_scale(S);
   const int of64 = dtype_out == SK_F64;
   KernelTimer timer(S, st);
   if (dtype_in == SK_F64) {
     auto kern = srtt_cols_kernel<double, double>;
     SK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(1024), lds, st, (const double*)A, lda, rows, S->n, p, S->d_sample, S->d,
-                       scale, S->k0, S->k1, Y, ldy, of64);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(1024), lds, st, (const double*)A, lda, rows, S->n, p, S->d_sample, S->d_sgn,
+                       S->xi, S->d, scale, S->k0, S->k1, Y, ldy, of64);
   } else if (dtype_in == SK_F32) {
     auto kern = srtt_cols_kernel<float, float>;
     SK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(1024), lds, st, (const float*)A, lda, rows, S->n, p, S->d_sample, S->d,
-                       scale, S->k0, S->k1, Y, ldy, of64);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(1024), lds, st, (const float*)A, lda, rows, S->n, p, S->d_sample, S->d_sgn,
+                       S->xi, S->d, scale, S->k0, S->k1, Y, ldy, of64);
   } else {
     auto kern = srtt_cols_kernel<uint16_t, float>;
     SK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(kern, dim3(grid), dim3(1024), lds, st, (const uint16_t*)A, lda, rows, S->n, p, S->d_sample,
-                       S->d, scale, S->k0, S->k1, Y, ldy, of64);
+                       S->d_sgn, S->xi, S->d, scale, S->k0, S->k1, Y, ldy, of64);
   }
   SK_HIP(hipGetLastError());
   return SK_OK;

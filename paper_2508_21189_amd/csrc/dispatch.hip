@@ -71,11 +71,11 @@ int apply_workspace(const sk_sketch* S, int op, int dtype_in, int64_t m, size_t*
     // F64 input: split-K partials; F32 input: G written out (+ F32 staging
     // of an F64 result)
     *bytes = dtype_in == SK_F32 ? gauss_rows_f32_workspace(S, m, SK_F64) : gauss_workspace(S, (int)m);
-  } else if (op == 0 && S->kind == SK_SRTT) {
+  } else if (op == 0 && trig_kind(S->kind)) {
     *bytes = srtt_workspace(S, (int)m);
   } else if (op == 1 && S->kind == SK_SPARSESTACK) {
     return cols_workspace(S, dtype_in, bytes);
-  } else if (op == 1 && (S->kind == SK_GAUSSIAN || S->kind == SK_SRTT)) {
+  } else if (op == 1 && (S->kind == SK_GAUSSIAN || trig_kind(S->kind))) {
     // m is the number of rows of A in this orientation; F64 output is the worst case
     return cols_dense_workspace(S, dtype_in, SK_F64, m, bytes);
   }
@@ -147,9 +147,10 @@ int apply_dispatch(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t
       }
       return launch_gauss_rows(S, m, (const double*)A, lda, nullptr, (double*)SA, ldsa, nullptr, w, need, st);
     }
-    case SK_SRTT: {
+    case SK_SRTT:
+    case SK_SPARSERTT: {
       if (dtype_in != SK_F64 || dtype_out != SK_F64) {
-        set_error("sketch_apply: the SRTT sketch takes and returns F64");
+        set_error("sketch_apply: the SRTT and SparseRTT sketches take and return F64");
         return SK_E_NOTSUP;
       }
       const size_t need = srtt_workspace(S, (int)m);
@@ -190,7 +191,7 @@ int apply_T_dispatch(sk_sketch* S, int dtype_in, int64_t rows, const void* A, in
     }
     return launch_cols_apply(S, dtype_in, rows, A, lda, dtype_out, Y, ldy, w, need, st);
   }
-  if (S->kind == SK_GAUSSIAN || S->kind == SK_SRTT) {
+  if (S->kind == SK_GAUSSIAN || trig_kind(S->kind)) {
     size_t need = 0;
     int rc = cols_dense_workspace(S, dtype_in, dtype_out, rows, &need);
     if (rc != SK_OK) return rc;

@@ -106,9 +106,9 @@ struct SketchBufs {
 int sketch_bufs(Carver& cv, const sk_sketch* S, int k, int dts, const void* As, int64_t ldas, const double* b,
                 SketchBufs* B) {
   size_t wa = 0, wb = 0;
-  if (S->kind == SK_GAUSSIAN || S->kind == SK_SRTT) {
+  if (S->kind == SK_GAUSSIAN || trig_kind(S->kind)) {
     if (dts != SK_F64) {
-      set_error("the Gaussian and SRTT sketches read F64 only");
+      set_error("the Gaussian, SRTT and SparseRTT sketches read F64 only");
       return SK_E_NOTSUP;
     }
     // one pass over [A | b]
@@ -137,7 +137,7 @@ int sketch_and_factor(sk_sketch* S, int k, int dts, const void* As, int64_t ldas
   const int64_t d = S->d;
   if (S->kind == SK_GAUSSIAN) {
     SK_TRY(launch_gauss_rows(S, k, (const double*)As, ldas, b, B.SA, k, B.Sb, B.aws, B.aws_bytes, st));
-  } else if (S->kind == SK_SRTT) {
+  } else if (trig_kind(S->kind)) {
     SK_TRY(launch_srtt_rows(S, k, (const double*)As, ldas, b, B.SA, k, B.Sb, B.aws, B.aws_bytes, st));
   } else {
     SK_TRY(apply_dispatch(S, dts, k, As, ldas, SK_F64, B.SA, k, B.aws, B.aws_bytes, st));

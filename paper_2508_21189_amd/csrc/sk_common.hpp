@@ -24,6 +24,7 @@ constexpr uint32_t kTagSparseStack = 1;
 constexpr uint32_t kTagSrttSign = 2;
 constexpr uint32_t kTagSrttSample = 3;
 constexpr uint32_t kTagGauss = 4;
+constexpr uint32_t kTagSparseCol = 5;
 
 struct U4 {
   uint32_t x, y, z, w;
@@ -93,10 +94,14 @@ struct sk_sketch {
   int64_t nb = 0;  // SparseStack buckets per block (d / zeta)
   int device = 0;
   uint32_t k0 = 0, k1 = 0;
-  // SRTT: padded length 2^p >= n and the d sampled rows (device, sorted).
+  // SRTT and SparseRTT: padded length 2^p >= n and the selected rows
+  // (device): SRTT d sorted rows (xi = 1, no signs); SparseRTT xi sorted
+  // rows per output row j at [j*xi, (j+1)*xi) with signs d_sgn (+1 / -1).
   int64_t npad = 0;
   int log2npad = 0;
+  int xi = 1;
   int64_t* d_sample = nullptr;
+  int8_t* d_sgn = nullptr;
   std::vector<int64_t> h_sample;
   // internal workspace (used when the caller passes ws = NULL)
   void* ws = nullptr;
@@ -133,4 +138,13 @@ struct KernelTimer {
     if (e1) (void)hipEventRecord(e1, st);
   }
 };
+
+// The two trigonometric-transform sketches share the transform kernels.
+inline bool trig_kind(int kind) { return kind == SK_SRTT || kind == SK_SPARSERTT; }
+// Scale of a selected-row sum: 1/sqrt(d) (SRTT, eq. 1.1), 1/sqrt(d xi)
+// (SparseRTT: (1/sqrt(d)) sqrt(npad/xi) from SparseCol times 1/sqrt(npad)
+// from the unitary WHT).
+inline double trig_scale(const sk_sketch* S) {
+  return inv_sqrt_host((double)S->d * (S->kind == SK_SPARSERTT ? (double)S->xi : 1.0));
+}
 }  // namespace sk

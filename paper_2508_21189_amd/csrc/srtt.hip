@@ -1,5 +1,8 @@
 // Subsampled randomized trigonometric transform (eq. 1.1, Walsh-Hadamard
-// version) applied on the left: SA = (1/sqrt(d)) R H D A_pad.
+// version) applied on the left: SA = (1/sqrt(d)) R H D A_pad, and the
+// SparseRTT (Def. 1.7), whose output row j is the signed sum of xi selected
+// rows of H D A_pad (the SparseCol factor of Def. 4.1), scaled by
+// 1/sqrt(d xi). Both share the transform; only the last step differs.
 //
 // A (n x m) is padded with zero rows to npad = 2^p, D is a Rademacher
 // diagonal (bit i mod 128 of Philox block i / 128, tag 2), H the unnormalized
@@ -102,33 +105,39 @@ __global__ void __launch_bounds__(512) srtt_pass_kernel(SrttPassArgs a) {
   }
 }
 
-// Output row j (sampled row r = sample[j] = hi * 2^q + low):
-// out[j][c] = scale * sum_{h' < 2^abits} (-1)^popcount(hi & h') Src[h' * 2^q + low][c],
+// Output row j from its selected rows r = sample[j*xi + i] (i < xi; xi = 1
+// and no signs for the SRTT), each r = hi * 2^q + low:
+// out[j][c] = scale * sum_i rho_i sum_{h' < 2^abits} (-1)^popcount(hi & h') Src[h' * 2^q + low][c],
 // Src = Z after the full passes, or D A_pad when there were none (q = 0).
 __global__ void __launch_bounds__(256) srtt_sample_kernel(const double* __restrict__ Z, const double* __restrict__ A,
                                                           int64_t lda, const double* __restrict__ rhs, int64_t n,
-                                                          int m, int m_eff, const int64_t* __restrict__ sample, int q,
-                                                          int abits, double scale, uint32_t k0, uint32_t k1,
+                                                          int m, int m_eff, const int64_t* __restrict__ sample,
+                                                          const int8_t* __restrict__ sgn, int xi, int q, int abits,
+                                                          double scale, uint32_t k0, uint32_t k1,
                                                           double* __restrict__ out, int64_t ldo,
                                                           double* __restrict__ rhs_out) {
   const int64_t j = blockIdx.x;
-  const int64_t r = sample[j];
-  const int64_t hi = r >> q, low = r & ((1ll << q) - 1);
   for (int c = threadIdx.x; c < m_eff; c += blockDim.x) {
     double s = 0.0;
-    for (int64_t hp = 0; hp < (1ll << abits); ++hp) {
-      const int64_t src = (hp << q) | low;
-      double v;
-      if (Z) {
-        v = Z[src * m_eff + c];
-      } else {
-        v = 0.0;
-        if (src < n) {
-          v = c < m ? A[src * lda + c] : rhs[src];
-          if ((srtt_word((uint64_t)src, k0, k1) >> (src & 31)) & 1u) v = -v;
+    for (int i = 0; i < xi; ++i) {
+      const int64_t r = sample[j * xi + i];
+      const int64_t hi = r >> q, low = r & ((1ll << q) - 1);
+      double t = 0.0;
+      for (int64_t hp = 0; hp < (1ll << abits); ++hp) {
+        const int64_t src = (hp << q) | low;
+        double v;
+        if (Z) {
+          v = Z[src * m_eff + c];
+        } else {
+          v = 0.0;
+          if (src < n) {
+            v = c < m ? A[src * lda + c] : rhs[src];
+            if ((srtt_word((uint64_t)src, k0, k1) >> (src & 31)) & 1u) v = -v;
+          }
         }
+        t += (__popcll((uint64_t)(hi & hp)) & 1) ? -v : v;
       }
-      s += (__popcll((uint64_t)(hi & hp)) & 1) ? -v : v;
+      s += (sgn && sgn[j * xi + i] < 0) ? -t : t;
     }
     if (c < m)
       out[j * ldo + c] = s * scale;
@@ -187,7 +196,7 @@ int launch_srtt_rows(const sk_sketch* S, int64_t m, const double* A, int64_t lda
     SK_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(srtt_sample_kernel, dim3((unsigned)S->d), dim3(256), 0, st, Z, A, lda, rhs, S->n, (int)m, m_eff,
-                     S->d_sample, q, abits, inv_sqrt_host((double)S->d), S->k0, S->k1, SA, ldsa, Srhs);
+                     S->d_sample, S->d_sgn, S->xi, q, abits, trig_scale(S), S->k0, S->k1, SA, ldsa, Srhs);
   SK_HIP(hipGetLastError());
   return SK_OK;
 }

@@ -13,13 +13,14 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libsketch.so")
 
-SK_SPARSESTACK, SK_GAUSSIAN, SK_SRTT, SK_IDENTITY_TEST = 0, 1, 2, 99
+SK_SPARSESTACK, SK_GAUSSIAN, SK_SRTT, SK_SPARSERTT, SK_IDENTITY_TEST = 0, 1, 2, 3, 99
 SK_F64, SK_F32, SK_BF16 = 0, 1, 2
 SK_ROW_MAJOR, SK_COL_MAJOR = 0, 1
 SK_OK, SK_E_INVAL, SK_E_NOMEM, SK_E_HIP, SK_E_NOTSUP = 0, -1, -2, -3, -4
 SK_W_RANKDEF, SK_W_NOCONV = 1, 2
 
-KINDS = {"sparsestack": SK_SPARSESTACK, "gaussian": SK_GAUSSIAN, "srtt": SK_SRTT, "identity": SK_IDENTITY_TEST}
+KINDS = {"sparsestack": SK_SPARSESTACK, "gaussian": SK_GAUSSIAN, "srtt": SK_SRTT, "sparsertt": SK_SPARSERTT,
+         "identity": SK_IDENTITY_TEST}
 _DT = {torch.float64: SK_F64, torch.float32: SK_F32, torch.bfloat16: SK_BF16}
 _TORCH = {SK_F64: torch.float64, SK_F32: torch.float32, SK_BF16: torch.bfloat16}
 
@@ -155,6 +156,10 @@ class Sketch:
             raise SketchError(SK_E_INVAL, last_error())
         self.h = ctypes.c_void_p(h)
         self.kind, self.d, self.n, self.zeta, self.seed = k, int(d), int(n), int(zeta), int(seed)
+        if k == SK_SPARSERTT:  # zeta = 0 asks for the default column sparsity
+            z = ctypes.c_int(0)
+            check(lib.sketch_info(self.h, None, None, None, ctypes.byref(z), None))
+            self.zeta = z.value
 
     def close(self):
         if getattr(self, "h", None):
