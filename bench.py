@@ -104,11 +104,12 @@ def _solve_stats(libsketch, torch, S, A, b, reps, tol, As=None):
 def lsqr_variants(libsketch, torch, A, b, reps, tol=1e-10):
     """Sketch-and-precondition solves of the coherent system: SparseStack with
     the sketch reading float64 / float32 / bfloat16 copies of A, and the
-    Gaussian (matrix-core GEMM) and SRTT (Walsh-Hadamard) sketches."""
+    Gaussian (matrix-core GEMM), SRTT and SparseRTT (Walsh-Hadamard; SparseRTT
+    with the default column sparsity ceil(1.5 ln d)) sketches."""
     out = {}
     variants = (("sparsestack_f64", "sparsestack", ZETA, None), ("sparsestack_f32", "sparsestack", ZETA, torch.float32),
                 ("sparsestack_bf16", "sparsestack", ZETA, torch.bfloat16), ("gaussian_f64", "gaussian", 1, None),
-                ("srtt_f64", "srtt", 1, None))
+                ("srtt_f64", "srtt", 1, None), ("sparsertt_f64", "sparsertt", 0, None))
     for name, kind, zeta, dt in variants:
         S = libsketch.Sketch(kind, D, N, zeta, SKETCH_SEED)
         As = A.to(dt) if dt is not None else None
@@ -155,7 +156,7 @@ def lsqr_mixed(libsketch, inputs, torch, reps, tol=1e-10):
 
 def rsvd_variants(libsketch, inputs, torch, reps):
     """Alg. 1 on A = U diag(i^-2) V^T (65536 x 16384, float32), k = 512, with
-    SparseStack (zeta = 8), SRTT and Gaussian sketches; the spectral error
+    SparseStack (zeta = 8), SRTT, SparseRTT (default xi) and Gaussian sketches; the spectral error
     ||A - U S V^T||_2 is estimated on the device by 30 power iterations."""
     import statistics
     rows, cols, k = 65536, 16384, 512
@@ -163,7 +164,7 @@ def rsvd_variants(libsketch, inputs, torch, reps):
     A, sig = inputs.lowrank_decay(rows, cols, seed=DATA_SEED + 2, dtype=torch.float32)
     A64 = A.double()
     out = {"workload": "A %dx%d f32 = U diag(i^-2) V^T, k=%d" % (rows, cols, k), "floor_sigma_k+1": float(sig[k])}
-    for kind, zeta in (("sparsestack", 8), ("srtt", 1), ("gaussian", 1)):
+    for kind, zeta in (("sparsestack", 8), ("srtt", 1), ("sparsertt", 0), ("gaussian", 1)):
         S = libsketch.Sketch(kind, k, cols, zeta, SKETCH_SEED + 2)
         S.rsvd(A)
         walls, infos = [], []
