@@ -291,6 +291,36 @@ def nystrom_variants(libsketch, inputs, torch, reps):
     return out
 
 
+def injectivity_sweep(libsketch, torch, trials, trials_1e7, steps):
+    """Fig. 2: injectivity alpha and dilation beta of SparseStack on the
+    coordinate basis Q = [e_1 ... e_r], k = 2r, r = 10^2 .. 10^7, zeta in
+    {1, 2, 4, 8}; median and 10% / 90% quantiles over trials (sketch seeds),
+    each estimate from `steps` Lanczos steps on S^T S (sketch_sv_extremes)."""
+    import numpy as np
+    out = {"workload": "SparseStack on Q = [e_1..e_r], k = 2r, Lanczos %d steps" % steps,
+           "gaussian_limit": {"alpha": (1 - 2 ** -0.5) ** 2, "beta": (1 + 2 ** -0.5) ** 2}, "points": []}
+    t_all = time.perf_counter()
+    for e in range(2, 8):
+        r = 10 ** e
+        nt = trials if e < 7 else trials_1e7
+        for zeta in (1, 2, 4, 8):
+            al, be, t_ms = [], [], []
+            for t in range(nt):
+                S = libsketch.Sketch("sparsestack", 2 * r, r, zeta, SKETCH_SEED + 100 * e + t)
+                a, b, rc, info = libsketch.sv_extremes(S, steps=steps, start_seed=t)
+                al.append(a)
+                be.append(b)
+                t_ms.append(info["t_build_ms"] + info["t_iter_ms"])
+                del S
+            q = lambda x: [float(v) for v in np.quantile(x, [0.1, 0.5, 0.9])]
+            out["points"].append({"r": r, "zeta": zeta, "trials": nt, "alpha_q10_med_q90": q(al),
+                                  "beta_q10_med_q90": q(be), "ms_per_estimate": round(float(np.median(t_ms)), 2)})
+        print("bench: injectivity r=1e%d done" % e, file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    out["total_s"] = round(time.perf_counter() - t_all, 2)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -307,6 +337,10 @@ def main():
     ap.add_argument("--gn-reps", type=int, default=1,
                     help="timed generalized Nystrom calls per sketch kind and form (0 = skip)")
     ap.add_argument("--nystrom-reps", type=int, default=1, help="timed Nystrom calls per sketch kind (0 = skip)")
+    ap.add_argument("--inj-trials", type=int, default=10,
+                    help="trials per point of the injectivity sweep for r <= 1e6 (0 = skip the sweep)")
+    ap.add_argument("--inj-trials-1e7", type=int, default=3, help="trials per point at r = 1e7")
+    ap.add_argument("--inj-steps", type=int, default=400, help="Lanczos steps per estimate")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -380,6 +414,9 @@ def main():
         rec["gen_nystrom"] = gn_variants(libsketch, inputs, torch, args.gn_reps)
     if args.nystrom_reps > 0:
         rec["nystrom"] = nystrom_variants(libsketch, inputs, torch, args.nystrom_reps)
+    if args.inj_trials > 0:
+        rec["injectivity"] = injectivity_sweep(libsketch, torch, args.inj_trials, max(1, args.inj_trials_1e7),
+                                               args.inj_steps)
     if not args.no_cpu:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(cpu_sample, args.cpu_rows)

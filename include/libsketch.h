@@ -62,7 +62,9 @@ enum {
 
 /*
  * Create a sketch S (d x n) on the current HIP device.
- *   kind  SK_SPARSESTACK: requires 1 <= zeta <= d and d % zeta == 0.
+ *   kind  SK_SPARSESTACK: requires 1 <= zeta <= d and d % zeta == 0 and
+ *         d / zeta < 2^31 (the row and column applies take at most 16384
+ *         and 16383 buckets per block and refuse more with SK_E_NOTSUP).
  *         The bucket s_it in [0, d/zeta) and sign rho_it of column i,
  *         block t are drawn from Philox4x32-10 (Salmon et al., SC'11) with
  *         key = seed and counter (i mod 2^32, i >> 32, t / 4, 1), word t % 4:
@@ -132,6 +134,32 @@ int sketch_apply(sketch_t S, int dtype_in, int layout, int64_t m, const void* A,
  */
 int sketch_apply_T(sketch_t S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out,
                    void* Y, int64_t ldy, void* ws, size_t ws_bytes, void* stream);
+
+/* Result details of sketch_sv_extremes. */
+typedef struct {
+  int steps;           /* Lanczos steps taken (fewer than asked after an invariant subspace) */
+  double alpha_at_3_4; /* the two estimates after 3/4 of the steps: their change from the */
+  double beta_at_3_4;  /*   final values shows how far the estimates still move */
+  double t_build_ms;   /* building the row-sorted form of S (device time) */
+  double t_iter_ms;    /* the Lanczos steps (device time) */
+} sk_extremes_info;
+
+/*
+ * Injectivity alpha = sigma_min(S Q)^2 and dilation beta = sigma_max(S Q)^2
+ * of a SparseStack S (d x n) on the coordinate basis Q = [e_1 ... e_n]
+ * (Prop. 1.9; the experiment of Fig. 2 takes d = k = 2r, n = r), i.e. the
+ * extreme eigenvalues of S^T S. Estimated by min(steps, n) Lanczos steps on
+ * S^T S from a Gaussian start (Philox counter (i mod 2^32, i >> 32, 0, 6)
+ * under key start_seed, Box-Muller; no reorthogonalization):
+ * the extreme eigenvalues of the Lanczos tridiagonal, found by Sturm
+ * bisection on the host. Each estimate lies inside [lambda_min, lambda_max]
+ * of S^T S and converges to its end as steps grow. Bitwise reproducible.
+ * Needs kind SK_SPARSESTACK, n < 2^31, d < 2^32, n * zeta < 2^31; uses the
+ * handle's driver workspace (about 16 n zeta + 8 d + 24 n bytes).
+ * Synchronizes the stream.
+ */
+int sketch_sv_extremes(sketch_t S, int steps, uint64_t start_seed, double* alpha, double* beta,
+                       sk_extremes_info* info, void* stream);
 
 /* Workspace bytes needed by sketch_apply (op 0, m = columns of A) or
  * sketch_apply_T (op 1, m = rows of A). */

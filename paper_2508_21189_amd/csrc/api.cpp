@@ -107,8 +107,8 @@ sketch_t sketch_create(int kind, int64_t d, int64_t n, int zeta, uint64_t seed) 
       set_error("sketch_create: SparseStack needs 1 <= zeta <= d and d % zeta == 0");
       return nullptr;
     }
-    if (d / zeta > 32767) {
-      set_error("sketch_create: SparseStack needs d/zeta <= 32767");
+    if (d / zeta >= ((int64_t)1 << 31)) {
+      set_error("sketch_create: SparseStack needs d/zeta < 2^31");
       return nullptr;
     }
   } else if (kind == SK_SRTT) {

@@ -103,6 +103,12 @@ class NystromInfo(ctypes.Structure):
                 ("t_total_ms", ctypes.c_double), ("jacobi_sweeps", ctypes.c_int)]
 
 
+class ExtremesInfo(ctypes.Structure):
+    """sk_extremes_info."""
+    _fields_ = [("steps", ctypes.c_int), ("alpha_at_3_4", ctypes.c_double), ("beta_at_3_4", ctypes.c_double),
+                ("t_build_ms", ctypes.c_double), ("t_iter_ms", ctypes.c_double)]
+
+
 def _as_dict(st):
     return {name: getattr(st, name) for name, _ in st._fields_}
 
@@ -117,6 +123,8 @@ _DRIVER_SIGS = {
     "gen_nystrom_svd": [_vp, _vp, ctypes.c_int, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, ctypes.POINTER(GnInfo),
                         _vp],
     "nystrom_psd": [_vp, ctypes.c_int, _vp, _i64, _vp, _i64, _vp, ctypes.POINTER(NystromInfo), _vp],
+    "sketch_sv_extremes": [_vp, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ExtremesInfo), _vp],
 }
 
 
@@ -309,6 +317,17 @@ def gen_nystrom(S_omega, S_psi, A, form="outer", stream=None):
                                        _ptr(sig), _ptr(V), k, ctypes.byref(info), _stream(stream)))
         return U, sig, V, rc, _as_dict(info)
     raise ValueError("form must be 'outer' or 'svd'")
+
+
+def sv_extremes(S, steps=300, start_seed=0, stream=None):
+    """Injectivity and dilation of a SparseStack S on Q = [e_1 ... e_n] (Fig. 2):
+    returns (alpha, beta, status, info), the extreme eigenvalues of S^T S
+    estimated by `steps` Lanczos steps on the device."""
+    a, b = ctypes.c_double(0), ctypes.c_double(0)
+    info = ExtremesInfo()
+    rc = check(load().sketch_sv_extremes(S.h, int(steps), ctypes.c_uint64(int(start_seed) & 0xFFFFFFFFFFFFFFFF),
+                                         ctypes.byref(a), ctypes.byref(b), ctypes.byref(info), _stream(stream)))
+    return a.value, b.value, rc, _as_dict(info)
 
 
 def nystrom_psd(S, A, stream=None):
