@@ -63,7 +63,7 @@ def _header_struct_fields(name):
 
 @pytest.mark.parametrize("cname,pyname", [("sk_solve_info", "SolveInfo"), ("sk_lsqr_info", "LsqrInfo"),
                                            ("sk_rsvd_info", "RsvdInfo"), ("sk_gn_info", "GnInfo"),
-                                           ("sk_nystrom_info", "NystromInfo")])
+                                           ("sk_nystrom_info", "NystromInfo"), ("sk_extremes_info", "ExtremesInfo")])
 def test_info_structs_match_header(cname, pyname):
     import ctypes as ct
     from paper_2508_21189_amd import libsketch
@@ -87,3 +87,5 @@ def test_driver_null_handle_fails_cleanly():
     assert lib.gen_nystrom(None, None, 1, 4, None, 4, None, 4, None, 4, None, None) == libsketch.SK_E_INVAL
     assert lib.gen_nystrom_svd(None, None, 1, 4, None, 4, None, 4, None, None, 4, None, None) == libsketch.SK_E_INVAL
     assert lib.nystrom_psd(None, 1, None, 4, None, 4, None, None, None) == libsketch.SK_E_INVAL
+    a, b = ctypes.c_double(0), ctypes.c_double(0)
+    assert lib.sketch_sv_extremes(None, 10, 0, ctypes.byref(a), ctypes.byref(b), None, None) == libsketch.SK_E_INVAL
