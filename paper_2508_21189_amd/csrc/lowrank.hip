@@ -486,9 +486,11 @@ int launch_gn_truncate(const double* s, int k, const double* V, double* Vs, cons
 
 // Nystrom (Alg. 2) helpers --------------------------------------------------
 
-// *nu = coef * sqrt(lambda_max(G)) for a k x k psd G (row-major): 100 power
-// iterations from the all-ones vector, then the Rayleigh quotient. One
-// workgroup; x and G x live in LDS.
+// *nu = coef * sqrt(lambda_max(G)) for a k x k symmetric psd G: power
+// iterations from the all-ones vector, stopped when the Rayleigh quotient
+// changes by at most 1e-12 relative (at most 100). G is symmetric, so y = G x
+// reads G by columns (thread i walks column i: consecutive threads read
+// consecutive addresses). One workgroup; x and G x live in LDS.
 __global__ void __launch_bounds__(1024) power_norm_kernel(const double* __restrict__ G, int k, double coef,
                                                           double* __restrict__ nu) {
   extern __shared__ double xs[];  // x[k], y[k]
@@ -497,12 +499,11 @@ __global__ void __launch_bounds__(1024) power_norm_kernel(const double* __restri
   double* y = xs + k;
   for (int i = threadIdx.x; i < k; i += blockDim.x) x[i] = 1.0;
   __syncthreads();
-  double lam = 0.0;
+  double lam = 0.0, lam_prev = -1.0;
   for (int it = 0; it <= 100; ++it) {
     for (int i = threadIdx.x; i < k; i += blockDim.x) {
-      const double* g = G + (int64_t)i * k;
       double acc = 0.0;
-      for (int j = 0; j < k; ++j) acc += g[j] * x[j];
+      for (int j = 0; j < k; ++j) acc += G[(int64_t)j * k + i] * x[j];
       y[i] = acc;
     }
     __syncthreads();
@@ -518,6 +519,9 @@ __global__ void __launch_bounds__(1024) power_norm_kernel(const double* __restri
     lam = xx > 0 ? xy / xx : 0.0;  // Rayleigh quotient of x
     const double inv = yy > 0 ? 1.0 / sqrt(yy) : 0.0;
     __syncthreads();
+    // every thread holds the same reduced values: the exit is uniform
+    if (fabs(lam - lam_prev) <= 1e-12 * fabs(lam)) break;
+    lam_prev = lam;
     for (int i = threadIdx.x; i < k; i += blockDim.x) x[i] = y[i] * inv;
     __syncthreads();
   }
