@@ -16,6 +16,9 @@
 #include "sk_launch.hpp"
 
 #include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <vector>
 
 namespace sk {
 
@@ -32,6 +35,7 @@ struct ColsArgs {
   int out_f64;
   float scale_f;
   double scale_d;
+  int nu;  // branch-free passes of the prefetching kernel (1 .. 8)
 };
 
 template <typename Tin>
@@ -245,11 +249,14 @@ __global__ void __launch_bounds__(512) ss_cols_vec_kernel(ColsArgs a) {
     __syncthreads();
     if (tile + 1 < a.n_tiles) fetch(tile + 1);
     if (walker) {
-      // Lane j describes bucket s_begin + j: its first NU list entries are
+      // Lane j describes bucket s_begin + j: its first nu list entries are
       // preloaded (absent ones point at the zero pad column TC), so the first
-      // NU passes over all buckets are unrolled and branch-free with their
-      // LDS reads independent; buckets with more entries walk the rest.
+      // nu passes over all buckets are unrolled and branch-free with their
+      // LDS reads independent; buckets with more entries walk the rest. nu
+      // (at most NU) is chosen on the host from the expected entries per
+      // bucket and tile.
       constexpr int NU = 8;
+      const int nu = a.nu;
       const unsigned char* rec = pl + tl * a.rec_bytes;
       const uint16_t* of = (const uint16_t*)rec;
       const uint32_t* lst = (const uint32_t*)(rec + a.lst_off);
@@ -261,9 +268,10 @@ __global__ void __launch_bounds__(512) ss_cols_vec_kernel(ColsArgs a) {
       }
       uint32_t ev[NU];
 #pragma unroll
-      for (int u = 0; u < NU; ++u) ev[u] = kcnt > (uint32_t)u ? lst[kbeg + u] : (uint32_t)a.TC;
+      for (int u = 0; u < NU; ++u) ev[u] = (u < nu && kcnt > (uint32_t)u) ? lst[kbeg + u] : (uint32_t)a.TC;
 #pragma unroll
       for (int u = 0; u < NU; ++u) {
+        if (u >= nu) break;
 #pragma unroll
         for (int g = 0; g < JB; g += 8) {
           Tacc v[8];
@@ -280,14 +288,14 @@ __global__ void __launch_bounds__(512) ss_cols_vec_kernel(ColsArgs a) {
             if (g + q < JB) acc[g + q] += flip_c(v[q], e[q]);
         }
       }
-      const uint64_t more = __ballot(kcnt > (uint32_t)NU);
+      const uint64_t more = __ballot(kcnt > (uint32_t)nu);
       if (more) {
 #pragma unroll
         for (int j = 0; j < JB; ++j) {
           if ((more >> j) & 1ull) {
             const uint32_t kb = (uint32_t)__builtin_amdgcn_readlane((int)kbeg, j);
             const uint32_t ke = kb + (uint32_t)__builtin_amdgcn_readlane((int)kcnt, j);
-            for (uint32_t kk = kb + NU; kk < ke; ++kk) {
+            for (uint32_t kk = kb + (uint32_t)nu; kk < ke; ++kk) {
               const uint32_t ea = lst[kk];
               acc[j] += flip_c(Tl[ea & 0x7fffffffu], ea);
             }
@@ -362,6 +370,34 @@ static int cols_plan(const sk_sketch* S, int dtype_in, ColsPlan* p) {
   return SK_OK;
 }
 
+// Branch-free passes of the prefetching kernel: with lambda = TC / nb entries
+// expected per bucket and tile (Poisson), nu passes cost nu loads per bucket
+// and the entries past them cost about 3 loads each when walked; nu in 1 .. 8
+// minimizes nu + 3 E[(X - nu)+]. SKETCH_COLS_NU overrides.
+static int cols_passes(int TC, int64_t nb) {
+  static const int env = [] {
+    const char* v = std::getenv("SKETCH_COLS_NU");
+    return v ? std::atoi(v) : 0;
+  }();
+  if (env >= 1 && env <= 8) return env;
+  const double lam = (double)TC / (double)nb;
+  std::vector<double> pmf(64);
+  pmf[0] = std::exp(-lam);
+  for (int x = 1; x < 64; ++x) pmf[x] = pmf[x - 1] * lam / x;
+  int best = 8;
+  double best_cost = 1e300;
+  for (int nu = 1; nu <= 8; ++nu) {
+    double tail = 0.0;
+    for (int x = nu + 1; x < 64; ++x) tail += (x - nu) * pmf[x];
+    const double cost = nu + 3.0 * tail;
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = nu;
+    }
+  }
+  return best;
+}
+
 int cols_workspace(const sk_sketch* S, int dtype_in, size_t* bytes) {
   ColsPlan p;
   int rc = cols_plan(S, dtype_in, &p);
@@ -398,6 +434,7 @@ static int launch_cols_t(const sk_sketch* S, const ColsPlan& p, int64_t rows, co
   a.out_f64 = out_f64;
   a.scale_d = inv_sqrt_host((double)S->zeta);
   a.scale_f = (float)a.scale_d;
+  a.nu = cols_passes(p.TC, S->nb);
   const int64_t grid = ((rows + 63) / 64) * p.n_groups;
   // the prefetching kernel: 16-byte aligned rows, whole chunks per row, the
   // tile within 8 chunks a thread and the plan records within 2
