@@ -347,7 +347,9 @@ static int cols_plan(const sk_sketch* S, int dtype_in, ColsPlan* p) {
   if ((int64_t)S->zeta * Hmin <= 16) {
     p->bpg = S->zeta;
     p->n_groups = 1;
-    p->H = Hmin;
+    // up to 8 waves (the prefetching kernel's size): with few blocks, split
+    // each block's buckets over more waves so that more waves walk
+    p->H = std::max<int>(Hmin, (int)std::min<int64_t>(nb, std::max(1, 8 / S->zeta)));
   } else {
     p->bpg = 16 / Hmin;
     p->n_groups = (S->zeta + p->bpg - 1) / p->bpg;
