@@ -461,7 +461,7 @@ extern "C" int nystrom_psd(sketch_t S, int dtype, const void* A, int64_t lda, do
   SK_TRY2(apply_workspace(S, 1, dtype, n, &wT));
   SK_TRY2(apply_workspace(S, 0, SK_F64, k, &wY));
   void *awT, *awY;
-  double *Y, *B, *B2, *Om, *C, *Cinv, *CinvT, *R, *Ur, *sv, *Vr, *jw, *nu;
+  double *Y, *B, *B2, *Om, *C, *Cinv, *CinvT, *R, *Ur, *sv, *jw, *nu;
   OrthBufs ob;
   int* jflag;
   auto carve = [&](Carve& cv) {
@@ -477,7 +477,6 @@ extern "C" int nystrom_psd(sketch_t S, int dtype, const void* A, int64_t lda, do
     R = cv.take<double>((size_t)k * k);
     Ur = cv.take<double>((size_t)k * k);
     sv = cv.take<double>(k);
-    Vr = cv.take<double>((size_t)k * k);
     jw = cv.take<double>(jacobi_work_doubles(k, k));
     nu = cv.take<double>(1);
     ob.G = cv.take<double>((size_t)k * k);
@@ -523,7 +522,8 @@ extern "C" int nystrom_psd(sketch_t S, int dtype, const void* A, int64_t lda, do
   double* Q = nullptr;
   SK_TRY2(orth_cholqr3(S, B, B2, n, k, ob, R, &Q, st));
   int sweeps = 0;
-  SK_TRY2(jacobi_svd_rounds(R, k, k, 0, Ur, sv, Vr, jw, jflag, h + 1, 60, &sweeps, st));
+  // only the left singular vectors of B are needed: no V accumulation
+  SK_TRY2(jacobi_svd_rounds(R, k, k, 0, Ur, sv, nullptr, jw, jflag, h + 1, 60, &sweeps, st));
   SK_TRY2(gemm_rm(S, SK_F64, false, false, n, k, k, 1.0, Q, k, Ur, k, 0.0, U, ldu, st));
   SK_TRY2(launch_remove_shift(sv, k, nu, lambda, st));  // Lambda = max(0, Sigma^2 - nu)
   SK_TRY2(mk.mark());                                     // 2: core

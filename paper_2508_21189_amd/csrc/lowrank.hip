@@ -184,6 +184,7 @@ __global__ void jacobi_init_kernel(const double* __restrict__ M, int rows, int k
     const int64_t col = idx / rows, row = idx - col * rows;
     Uc[idx] = input_colmajor ? M[idx] : M[row * k + col];
   }
+  if (!Vc) return;  // left singular vectors only
   const int64_t tv = (int64_t)k * k;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tv; idx += (int64_t)gridDim.x * blockDim.x)
     Vc[idx] = (idx / k == idx % k) ? 1.0 : 0.0;
@@ -234,7 +235,7 @@ __device__ inline double wave_sum_dpp(double v) {
 // one row of V_J per thread. Rotation and skip test are those of the pairwise
 // method: a pair is rotated when |x_p . x_q| > tol sqrt(|x_p|^2 |x_q|^2).
 // Columns past k (and blocks past the last) are absent: zero, never rotated,
-// never written.
+// never written. Vc = null skips W and the V update (left vectors only).
 template <int BS>
 __global__ void __launch_bounds__(1024) jacobi_block_kernel(double* __restrict__ Uc, double* __restrict__ Vc, int rows,
                                                             int k, int nbp, int round, int diag, double tol,
@@ -318,7 +319,7 @@ __global__ void __launch_bounds__(1024) jacobi_block_kernel(double* __restrict__
           xp[i] = c * x - sn * y;
           xq[i] = sn * x + c * y;
         }
-        if (lane < NC) {
+        if (Vc && lane < NC) {
           const double x = W[p * NC + lane], y = W[q * NC + lane];
           W[p * NC + lane] = c * x - sn * y;
           W[q * NC + lane] = sn * x + c * y;
@@ -335,7 +336,7 @@ __global__ void __launch_bounds__(1024) jacobi_block_kernel(double* __restrict__
     if (j >= 0) Uc[(int64_t)j * rows + i] = X[idx];
   }
   // V_J <- V_J W: thread i keeps row i of the old V_J in registers
-  for (int i = tid; i < k; i += nt) {
+  for (int i = tid; Vc && i < k; i += nt) {
     double v[NC];
 #pragma unroll
     for (int r = 0; r < NC; ++r) {
@@ -377,7 +378,8 @@ __global__ void __launch_bounds__(1024) jacobi_finish_kernel(const double* __res
     s[rank] = sj;
     const double inv = sj > 0 ? 1.0 / sj : 0.0;
     for (int row = 0; row < rows; ++row) U[(int64_t)row * k + rank] = Uc[(int64_t)j * rows + row] * inv;
-    for (int row = 0; row < k; ++row) V[(int64_t)row * k + rank] = Vc[(int64_t)j * k + row];
+    if (V)
+      for (int row = 0; row < k; ++row) V[(int64_t)row * k + rank] = Vc[(int64_t)j * k + row];
   }
 }
 
@@ -627,8 +629,9 @@ int jacobi_svd_rounds(const double* M, int64_t rows, int k, int input_colmajor, 
   }
   const int nr = (int)rows;
   double* Uc = work;
-  double* Vc = work + (size_t)nr * k;
-  double* sig = Vc + (size_t)k * k;
+  double* Vbuf = work + (size_t)nr * k;
+  double* sig = Vbuf + (size_t)k * k;
+  double* Vc = V ? Vbuf : nullptr;  // V = null: left singular vectors only
   hipLaunchKernelGGL(jacobi_init_kernel, dim3(grid_for((int64_t)nr * k)), dim3(256), 0, st, M, nr, k, input_colmajor,
                      Uc, Vc);
   SK_HIP(hipGetLastError());
@@ -651,6 +654,11 @@ int jacobi_svd_rounds(const double* M, int64_t rows, int k, int input_colmajor, 
   }
   const int nblk = (k + bs - 1) / bs;
   const int nbp = nblk + (nblk & 1);
+  // rotation threshold sqrt(rows) u (u = 2^-53), the rounding level of the
+  // computed column dot products (as in one-sided Jacobi codes such as
+  // LAPACK's): a stricter threshold only rotates pairs whose computed product
+  // is rounding noise and adds sweeps
+  const double tol = std::sqrt((double)nr) * 0x1p-53;
   auto visit = [&](int grid, int round, int diag) -> int {
     switch (bs) {
 #define SK_JB(B)                                                                                                  \
@@ -658,7 +666,7 @@ int jacobi_svd_rounds(const double* M, int64_t rows, int k, int input_colmajor, 
     SK_HIP(hipFuncSetAttribute((const void*)jacobi_block_kernel<B>, hipFuncAttributeMaxDynamicSharedMemorySize, \
                                (int)lds));                                                                      \
     hipLaunchKernelGGL(jacobi_block_kernel<B>, dim3(grid), dim3(64 * B), lds, st, Uc, Vc, nr, k, nbp, round,    \
-                       diag, 1e-15, flag);                                                                            \
+                       diag, tol, flag);                                                                            \
     break;
       SK_JB(16)
       SK_JB(8)

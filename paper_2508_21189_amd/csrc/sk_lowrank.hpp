@@ -16,9 +16,9 @@ int launch_transpose(const double* X, int64_t r, int64_t c, double* Y, hipStream
 // row-major, or column-major when input_colmajor), by block visits (one
 // launch for the diagonal blocks and one per round of block pairs in every
 // sweep); U (rows x k) and V (k x k) row-major, s descending. Columns of U
-// whose singular value is 0 are 0. work: jacobi_work_doubles(rows, k); flag:
-// one device int; h_flag: pinned host int. Synchronizes the stream once per
-// sweep.
+// whose singular value is 0 are 0. V = null skips the right vectors (no
+// rotation accumulation). work: jacobi_work_doubles(rows, k); flag: one
+// device int; h_flag: pinned host int. Synchronizes the stream once per sweep.
 size_t jacobi_work_doubles(int64_t rows, int k);
 int jacobi_svd_rounds(const double* M, int64_t rows, int k, int input_colmajor, double* U, double* s, double* V,
                       double* work, int* flag, int* h_flag, int max_sweeps, int* sweeps, hipStream_t st);
