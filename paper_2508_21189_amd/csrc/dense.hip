@@ -182,10 +182,9 @@ __global__ void __launch_bounds__(NTH) hh_panel_reg_kernel(double* __restrict__ 
       if (lr > jj) part += pc[i] * pc[i];
       if (lr == jj) alpha_part = pc[i];
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      part += __shfl_xor(part, o, 64);
-      alpha_part += __shfl_xor(alpha_part, o, 64);
-    }
+    // wave sums by DPP row rotations and broadcasts (no LDS traffic)
+    part = wave_sum_dpp(part);
+    alpha_part = wave_sum_dpp(alpha_part);
     if (lane == 0) {
       red[wave][0] = part;
       red[wave][1] = alpha_part;
@@ -222,8 +221,7 @@ __global__ void __launch_bounds__(NTH) hh_panel_reg_kernel(double* __restrict__ 
     __syncthreads();  // red is reused
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-      double v = acc[q];
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      const double v = wave_sum_dpp(acc[q]);
       if (lane == 0) red[wave][q] = v;
     }
     __syncthreads();
@@ -303,8 +301,7 @@ __global__ void __launch_bounds__(256) hh_trail_kernel(double* __restrict__ W, i
   }
 #pragma unroll
   for (int p = 0; p < kPanel; ++p) {
-    double v = acc[p];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const double v = wave_sum_dpp(acc[p]);
     if (lane == 0) red[wave][p] = v;
   }
   __syncthreads();

@@ -139,6 +139,30 @@ struct KernelTimer {
   }
 };
 
+// 64-bit DPP move of v (dpp_ctrl C, row mask RM); disabled rows give 0.
+template <int C, int RM>
+__device__ inline double dpp64(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, C, RM, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), C, RM, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+// Sum of v over the wave, returned uniformly (the value that ends in lane 63):
+// row_ror 8, 4, 2, 1 inside each 16-lane row, then row_bcast 15 and 31 carry
+// the row sums up to the last row.
+__device__ inline double wave_sum_dpp(double v) {
+  v += dpp64<0x128, 0xF>(v);
+  v += dpp64<0x124, 0xF>(v);
+  v += dpp64<0x122, 0xF>(v);
+  v += dpp64<0x121, 0xF>(v);
+  v += dpp64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // The two trigonometric-transform sketches share the transform kernels.
 inline bool trig_kind(int kind) { return kind == SK_SRTT || kind == SK_SPARSERTT; }
 // Scale of a selected-row sum: 1/sqrt(d) (SRTT, eq. 1.1), 1/sqrt(d xi)
