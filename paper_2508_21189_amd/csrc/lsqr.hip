@@ -264,6 +264,8 @@ __device__ inline void tri_cols(const double* __restrict__ M, int k, const doubl
   double acc[8];
 #pragma unroll
   for (int p = 0; p < 8; ++p) acc[p] = 0;
+  // rows are independent: unrolled so that several rows' loads are in flight
+#pragma unroll 4
   for (int i = wave; i < k; i += nw) {
     const double xi = xs[i];
     const double* row = M + (int64_t)i * k;
