@@ -104,7 +104,13 @@ int sketch_info(sketch_t S, int* kind, int64_t* d, int64_t* n, int* zeta, uint64
 /*
  * SA = S A.
  *   A   n x m matrix of dtype_in (SK_F64, SK_F32 or SK_BF16), layout
- *       SK_ROW_MAJOR (element (i,c) at A[i*lda + c], lda >= m).
+ *       SK_ROW_MAJOR (element (i,c) at A[i*lda + c], lda >= m) or
+ *       SK_COL_MAJOR (element (i,c) at A[c*lda + i], lda >= n). Column-major
+ *       A is first copied to row-major in the workspace (a tiled transpose:
+ *       one more read and write of A), then sketched exactly as the same
+ *       matrix in row-major order: the results are bitwise equal.
+ *       Rows must be 4-byte multiples (m * element size, and for row-major
+ *       A also lda * element size and the address): BF16 needs m even.
  *   SA  d x m row-major (element (j,c) at SA[j*ldsa + c], ldsa >= m) of
  *       dtype_out: SK_F64 or SK_F32. F64 input accumulates in F64; F32 and
  *       BF16 inputs accumulate in F32 (BF16 values are exact in F32).
@@ -161,7 +167,8 @@ typedef struct {
 int sketch_sv_extremes(sketch_t S, int steps, uint64_t start_seed, double* alpha, double* beta,
                        sk_extremes_info* info, void* stream);
 
-/* Workspace bytes needed by sketch_apply (op 0, m = columns of A) or
+/* Workspace bytes needed by sketch_apply (op 0: row-major A, m = columns of
+ * A; op 2: column-major A, which adds the row-major copy, n * m elements) or
  * sketch_apply_T (op 1, m = rows of A). */
 int sketch_workspace_size(sketch_t S, int op, int dtype_in, int64_t m, size_t* bytes);
 

@@ -247,7 +247,7 @@ int sketch_info(sketch_t S, int* kind, int64_t* d, int64_t* n, int* zeta, uint64
 }
 
 int sketch_workspace_size(sketch_t S, int op, int dtype_in, int64_t m, size_t* bytes) {
-  if (!S || !bytes || m < 1 || !valid_dtype(dtype_in) || (op != 0 && op != 1)) {
+  if (!S || !bytes || m < 1 || !valid_dtype(dtype_in) || op < 0 || op > 2) {
     set_error("sketch_workspace_size: invalid argument");
     return SK_E_INVAL;
   }
@@ -264,9 +264,16 @@ int sketch_apply(sketch_t S, int dtype_in, int layout, int64_t m, const void* A,
     set_error("sketch_apply: need m >= 1, dtype_in in {F64, F32, BF16}, dtype_out in {F64, F32}");
     return SK_E_INVAL;
   }
+  if (layout == SK_COL_MAJOR) {
+    if (lda < S->n || ldsa < m) {
+      set_error("sketch_apply: column-major A needs lda >= n, and ldsa >= m");
+      return SK_E_INVAL;
+    }
+    return apply_colmajor(S, dtype_in, m, A, lda, dtype_out, SA, ldsa, ws, ws_bytes, (hipStream_t)stream);
+  }
   if (layout != SK_ROW_MAJOR) {
-    set_error("sketch_apply: only SK_ROW_MAJOR is supported");
-    return SK_E_NOTSUP;
+    set_error("sketch_apply: layout must be SK_ROW_MAJOR or SK_COL_MAJOR");
+    return SK_E_INVAL;
   }
   if (lda < m || ldsa < m) {
     set_error("sketch_apply: need lda >= m and ldsa >= m");

@@ -54,7 +54,65 @@ int launch_convert(int dtype_in, const void* in, int64_t ldi, int dtype_out, voi
   return SK_OK;
 }
 
+// Column-major A (n x m, column c at A + c*lda) to row-major At (n x m,
+// ld ldt >= m), through 64 x 64 tiles in LDS so that both the reads (along a column)
+// and the writes (along a row) are coalesced. Elements are moved as raw
+// bytes of their type.
+template <typename T>
+__global__ void __launch_bounds__(256) colmajor_to_rowmajor_kernel(const T* __restrict__ A, int64_t lda, int64_t n,
+                                                                    int64_t m, T* __restrict__ At, int64_t ldt) {
+  __shared__ T tile[64][65];
+  const int64_t i0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4 threads
+  for (int cc = ty; cc < 64; cc += 4) {
+    const int64_t i = i0 + tx, c = c0 + cc;
+    if (i < n && c < m) tile[cc][tx] = A[c * lda + i];
+  }
+  __syncthreads();
+  for (int ii = ty; ii < 64; ii += 4) {
+    const int64_t i = i0 + ii, c = c0 + tx;
+    if (i < n && c < m) At[i * ldt + c] = tile[tx][ii];
+  }
+}
+
+static int launch_colmajor_to_rowmajor(int dtype, const void* A, int64_t lda, int64_t n, int64_t m, void* At,
+                                       int64_t ldt, hipStream_t st) {
+  const int64_t gx = (n + 63) / 64, gy = (m + 63) / 64;
+  if (gx > 0x7fffffff || gy > 65535) {
+    set_error("sketch_apply: column-major A too large for the transpose grid");
+    return SK_E_NOTSUP;
+  }
+  const dim3 grid((unsigned)gx, (unsigned)gy);
+  if (dtype == SK_F64)
+    hipLaunchKernelGGL(colmajor_to_rowmajor_kernel<double>, grid, dim3(256), 0, st, (const double*)A, lda, n, m,
+                       (double*)At, ldt);
+  else if (dtype == SK_F32)
+    hipLaunchKernelGGL(colmajor_to_rowmajor_kernel<float>, grid, dim3(256), 0, st, (const float*)A, lda, n, m,
+                       (float*)At, ldt);
+  else
+    hipLaunchKernelGGL(colmajor_to_rowmajor_kernel<uint16_t>, grid, dim3(256), 0, st, (const uint16_t*)A, lda, n,
+                       m, (uint16_t*)At, ldt);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+// The row-major copy of a column-major A: rows padded to a multiple of 8
+// elements, so that every row starts 16-byte aligned and the apply takes its
+// 16-byte loads whatever m is (the summation order does not depend on the
+// padding); its bytes, 256-aligned.
+static int64_t colmajor_copy_ld(int64_t m) { return (m + 7) & ~(int64_t)7; }
+static size_t colmajor_copy_bytes(const sk_sketch* S, int dtype_in, int64_t m) {
+  return ((size_t)S->n * colmajor_copy_ld(m) * dtype_size(dtype_in) + 255) & ~(size_t)255;
+}
+
 int apply_workspace(const sk_sketch* S, int op, int dtype_in, int64_t m, size_t* bytes) {
+  if (op == 2) {  // sketch_apply with column-major A: the row-major copy, then op 0 on it
+    size_t rest = 0;
+    int rc = apply_workspace(S, 0, dtype_in, m, &rest);
+    if (rc != SK_OK) return rc;
+    *bytes = colmajor_copy_bytes(S, dtype_in, m) + rest;
+    return SK_OK;
+  }
   *bytes = 0;
   if (op == 0 && S->kind == SK_SPARSESTACK) {
     RowsPlan p;
@@ -92,6 +150,28 @@ int apply_workspace_for(const sk_sketch* S, int dtype_in, int64_t m, const void*
     return SK_OK;
   }
   return apply_workspace(S, 0, dtype_in, m, bytes);
+}
+
+int apply_colmajor(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t lda, int dtype_out, void* SA,
+                   int64_t ldsa, void* ws, size_t ws_bytes, hipStream_t st) {
+  size_t need = 0;
+  int rc = apply_workspace(S, 2, dtype_in, m, &need);
+  if (rc != SK_OK) return rc;
+  void* w = ws;
+  if (w) {
+    if (ws_bytes < need) {
+      set_error("sketch_apply: workspace too small for column-major A (see sketch_workspace_size, op 2)");
+      return SK_E_INVAL;
+    }
+  } else {
+    rc = handle_workspace(S, need, &w);
+    if (rc != SK_OK) return rc;
+  }
+  const size_t cb = colmajor_copy_bytes(S, dtype_in, m);
+  const int64_t ldt = colmajor_copy_ld(m);
+  rc = launch_colmajor_to_rowmajor(dtype_in, A, lda, S->n, m, w, ldt, st);
+  if (rc != SK_OK) return rc;
+  return apply_dispatch(S, dtype_in, m, w, ldt, dtype_out, SA, ldsa, (char*)w + cb, need - cb, st);
 }
 
 int apply_dispatch(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t lda, int dtype_out, void* SA,

@@ -186,15 +186,21 @@ class Sketch:
         return b.value
 
     def apply(self, A, out_dtype=None, out=None, ws=None, stream=None):
-        """SA = S @ A for a row-major (n x m) CUDA tensor A (float64/float32/bfloat16)."""
-        assert A.is_cuda and A.dim() == 2 and A.shape[0] == self.n and A.stride(1) == 1
+        """SA = S @ A for an (n x m) CUDA tensor A (float64/float32/bfloat16), row-major
+        (stride(1) == 1) or column-major (stride(0) == 1, e.g. a transposed view)."""
+        assert A.is_cuda and A.dim() == 2 and A.shape[0] == self.n
         m = A.shape[1]
+        if A.stride(1) == 1 and (A.stride(0) >= m or m == 1):
+            layout, lda = SK_ROW_MAJOR, A.stride(0)
+        else:
+            assert A.stride(0) == 1, "A must be row-major or column-major"
+            layout, lda = SK_COL_MAJOR, A.stride(1)
         odt = out_dtype or (torch.float64 if A.dtype == torch.float64 else torch.float32)
         if out is None:
             out = torch.empty((self.d, m), dtype=odt, device=A.device)
         assert out.shape == (self.d, m) and out.stride(1) == 1 and out.dtype == odt
         wsp, wsb = (None, 0) if ws is None else (_ptr(ws), ws.numel() * ws.element_size())
-        check(load().sketch_apply(self.h, _DT[A.dtype], SK_ROW_MAJOR, m, _ptr(A), A.stride(0), _DT[odt], _ptr(out),
+        check(load().sketch_apply(self.h, _DT[A.dtype], layout, m, _ptr(A), lda, _DT[odt], _ptr(out),
                                   out.stride(0), wsp, wsb, _stream(stream)))
         return out
 

@@ -146,3 +146,28 @@ def test_full_size_sampled_columns(lib):
     Sb = S.apply(b[:, None].contiguous()).cpu().numpy()
     ref = sk.sparsestack_apply(b.cpu().numpy()[:, None], d, zeta, seed)
     _check(Sb, ref, _bound(b.cpu().numpy()[:, None], d, zeta, seed, 2.0 ** -53))
+
+
+@pytest.mark.parametrize("kind,dtype,n,m,d,zeta", [("sparsestack", torch.float64, 20000, 50, 200, 4),
+                                                   ("sparsestack", torch.float32, 7001, 130, 96, 8),
+                                                   ("sparsestack", torch.bfloat16, 3000, 34, 64, 4),
+                                                   ("sparsestack", torch.float64, 5000, 3, 40, 4),
+                                                   ("gaussian", torch.float64, 3000, 20, 64, 1),
+                                                   ("srtt", torch.float64, 4096, 17, 64, 1),
+                                                   ("sparsertt", torch.float64, 3000, 9, 48, 0)])
+def test_apply_column_major_equals_row_major(lib, kind, dtype, n, m, d, zeta):
+    """Column-major A (a transposed view, and one with lda > n) gives SA bitwise
+    equal to the same matrix in row-major order."""
+    g = torch.Generator().manual_seed(n + m)
+    A = torch.randn((n, m), generator=g, dtype=torch.float64).to(dtype).cuda()
+    S = lib.Sketch(kind, d, n, zeta, 5)
+    ref = S.apply(A.contiguous())
+    At = A.t().contiguous().t()  # column-major view: stride (1, n)
+    assert At.stride() == (1, n)
+    got = S.apply(At)
+    assert torch.equal(got, ref)
+    pad = torch.zeros((m, n + 7), dtype=dtype, device="cuda")
+    pad[:, :n] = A.t()
+    Ap = pad[:, :n].t()  # column-major with lda = n + 7
+    assert Ap.stride() == (1, n + 7)
+    assert torch.equal(S.apply(Ap), ref)
