@@ -63,8 +63,9 @@ enum {
 /*
  * Create a sketch S (d x n) on the current HIP device.
  *   kind  SK_SPARSESTACK: requires 1 <= zeta <= d and d % zeta == 0 and
- *         d / zeta < 2^31 (the row and column applies take at most 16384
- *         and 16383 buckets per block and refuse more with SK_E_NOTSUP).
+ *         d / zeta < 2^31 (sketch_apply takes at most 16384 buckets per
+ *         block; sketch_apply_T at most 800 for SK_F64 and 1024 for SK_F32
+ *         and SK_BF16; both refuse more with SK_E_NOTSUP).
  *         The bucket s_it in [0, d/zeta) and sign rho_it of column i,
  *         block t are drawn from Philox4x32-10 (Salmon et al., SC'11) with
  *         key = seed and counter (i mod 2^32, i >> 32, t / 4, 1), word t % 4:

@@ -12,7 +12,8 @@ struct RowsPlan {
   int R = 128;           // rows per LDS sub-tile
   int W = 16;            // waves per workgroup
   int bpg = 1;           // sketch blocks handled by one workgroup
-  int n_groups = 1;      // workgroups sharing one A tile (zeta / bpg, rounded up)
+  int n_groups = 1;      // workgroups sharing one A tile (zeta / bpg, rounded up, times ranges)
+  int ranges = 1;        // bucket-range groups per block (more buckets than 16 waves hold)
   int H = 1;             // bucket ranges per block (one wave each)
   int per_range = 1;     // buckets per range
   int n_chunks = 1;      // row chunks

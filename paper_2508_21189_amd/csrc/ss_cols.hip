@@ -326,6 +326,9 @@ __global__ void __launch_bounds__(512) ss_cols_vec_kernel(ColsArgs a) {
 // ---------------------------------------------------------------------------
 static size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
 
+// LDS of the plan kernel for tiles of R indices (defined with that kernel)
+size_t plan_kernel_lds(int R, int zeta, int64_t nb);
+
 // Plan of the column-mode apply; the plan kernel is the row-mode one over the
 // n columns (tile = TC columns, entries carry the plain column offset).
 struct ColsPlan {
@@ -363,7 +366,7 @@ static int cols_plan(const sk_sketch* S, int dtype_in, ColsPlan* p) {
     p->lst_off = (int)a16((size_t)(nb + 1) * 2);
     p->rec_bytes = (int)a16((size_t)p->lst_off + (size_t)(p->TC + 1) * 4);
     p->lds = a16((size_t)64 * (p->TC + 1) * accb) + (size_t)p->bpg * p->rec_bytes;
-    const size_t plan_lds = a16((size_t)2 * S->zeta * p->TC * 2 + 4) + (size_t)S->zeta * (nb + 1) * 4;
+    const size_t plan_lds = plan_kernel_lds(p->TC, S->zeta, nb);
     if ((p->lds <= 160 * 1024 && plan_lds <= 160 * 1024) || p->TC <= 32) break;
     p->TC /= 2;
   }

@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(1024) ss_plan_kernel(PlanArgs a) {
   const int rv = (int)min((int64_t)R, a.n - r0);
   uint16_t* codes = (uint16_t*)smem;                          // [zeta][R]
   uint16_t* rnk = codes + (size_t)zeta * R;                   // [zeta][R]
-  uint32_t* cnts = (uint32_t*)(rnk + (size_t)zeta * R + ((zeta * R) & 1));  // [zeta][nb + 1]
+  uint32_t* cnts = (uint32_t*)(rnk + (size_t)zeta * R + ((zeta * R) & 1));  // [waves][nb + 1]
 
   // Hash: one Philox call gives the words of blocks 4g .. 4g+3 of one row.
   const int ng = (zeta + 3) / 4;
@@ -116,10 +116,11 @@ __global__ void __launch_bounds__(1024) ss_plan_kernel(PlanArgs a) {
   }
   lds_barrier();
 
-  // Stable counting sort of block t's rows by bucket, one wave per block.
+  // Stable counting sort of block t's rows by bucket, one wave per block;
+  // a wave reuses its count array for its next block.
   const uint64_t below = (1ull << lane) - 1ull;
+  uint32_t* cnt = cnts + (size_t)wave * (nb + 1);
   for (int t = wave; t < zeta; t += nwaves) {
-    uint32_t* cnt = cnts + t * (nb + 1);
     const uint16_t* cd = codes + t * R;
     uint16_t* rk = rnk + t * R;
     for (int s = lane; s <= nb; s += 64) cnt[s] = 0;
@@ -182,6 +183,7 @@ struct RowsArgs {
   int64_t lda_bytes;
   int64_t n, m, d;
   int C, n_slabs, R, bpg, n_groups, H, per_range, n_chunks;
+  int ranges;  // bucket-range groups per block: group g takes blocks from g / ranges, range g % ranges
   int64_t rows_per_chunk;
   int zeta, nb;
   const unsigned char* plan;
@@ -267,7 +269,8 @@ __global__ void __launch_bounds__(1024) ss_rows_kernel(RowsArgs a) {
   const int chunk = (q8 / (a.n_groups * a.n_slabs)) * 8 + xcd;
   if (chunk >= a.n_chunks) return;
 
-  const int t0 = group * a.bpg;
+  const int rg = group % a.ranges;
+  const int t0 = (group / a.ranges) * a.bpg;
   const int bpg = min(a.bpg, a.zeta - t0);
   const int64_t col0 = (int64_t)slab * a.C;
   const int Cw = (int)min((int64_t)a.C, a.m - col0);
@@ -279,7 +282,7 @@ __global__ void __launch_bounds__(1024) ss_rows_kernel(RowsArgs a) {
 
   const int tl = wave / a.H, hr = wave - (wave / a.H) * a.H;
   const bool walker = tl < bpg;
-  const int s_begin = hr * a.per_range;
+  const int s_begin = (rg * a.H + hr) * a.per_range;
   const int s_cnt = walker ? max(0, min(a.per_range, nb - s_begin)) : 0;
 
   Tacc acc[JB];
@@ -620,9 +623,18 @@ static int jb_variant(int dtype_in, int per_range) {
 static size_t narrow_lds(int R, int accb, int zeta, int rec_bytes) {
   return align16((size_t)R * 4 * accb) + (size_t)zeta * rec_bytes;
 }
-static size_t plan_lds(int R, int zeta, int64_t nb) {
-  return align16((size_t)2 * zeta * R * 2 + 4) + (size_t)zeta * (nb + 1) * 4;
+// The plan kernel runs one wave per block (at most 16), fewer where the
+// waves' count arrays would not fit in LDS.
+static int plan_waves(int R, int zeta, int64_t nb) {
+  const size_t fixed = align16((size_t)2 * zeta * R * 2 + 4);
+  int nw = std::min(16, zeta);
+  while (nw > 1 && fixed + (size_t)nw * (nb + 1) * 4 > 160 * 1024) --nw;
+  return nw;
 }
+size_t plan_kernel_lds(int R, int zeta, int64_t nb) {
+  return align16((size_t)2 * zeta * R * 2 + 4) + (size_t)plan_waves(R, zeta, nb) * (nb + 1) * 4;
+}
+static size_t plan_lds(int R, int zeta, int64_t nb) { return plan_kernel_lds(R, zeta, nb); }
 
 static int plan_narrow(const sk_sketch* S, int dtype_in, int64_t m, RowsPlan* p) {
   const size_t cap = 160 * 1024;
@@ -664,11 +676,16 @@ int plan_rows(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_
   }
   const int jmax = jb_max(dtype_in);
   const int Hmin = (int)((nb + jmax - 1) / jmax);
+  p->ranges = 1;
   if (Hmin > 16) {
-    set_error("SparseStack row apply: d/zeta too large for the register-resident accumulators");
-    return SK_E_NOTSUP;
-  }
-  if ((int64_t)zeta * Hmin <= 16) {
+    // more buckets than one workgroup's 16 waves hold in registers: each
+    // block's buckets are split over `ranges` workgroups (each reads the
+    // tile; one block per workgroup)
+    p->ranges = (Hmin + 15) / 16;
+    p->bpg = 1;
+    p->H = 16;
+    p->n_groups = zeta * p->ranges;
+  } else if ((int64_t)zeta * Hmin <= 16) {
     p->bpg = zeta;
     p->n_groups = 1;
     p->H = std::max(Hmin, (int)std::min<int64_t>(nb, 16 / zeta));
@@ -678,7 +695,7 @@ int plan_rows(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_
     p->H = Hmin;
   }
   p->W = p->bpg * p->H;
-  p->per_range = (int)((nb + p->H - 1) / p->H);
+  p->per_range = (int)((nb + (int64_t)p->H * p->ranges - 1) / ((int64_t)p->H * p->ranges));
   p->jb = jb_variant(dtype_in, p->per_range);
 
   // direct global->LDS load width
@@ -701,17 +718,20 @@ int plan_rows(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_
   p->n_slabs = (int)((m + C - 1) / C);
   p->rowb = (int)align16((size_t)C * es);
 
-  // tile rows: about 64 KB per buffer, shrunk until the LDS plan fits
+  // tile rows: about 64 KB per buffer, shrunk until the LDS plan of the
+  // sketch kernel and that of the plan kernel fit
   int R = env_int("SKETCH_TILE_ROWS", 65536 / p->rowb);
   const size_t lds_cap = 160 * 1024;
   for (;;) {
     plan_record(R, nb, &p->rec_bytes, &p->lst_off);
-    if (rows_lds(es, R, p->rowb, p->bpg, p->rec_bytes, p->W).total <= lds_cap || R <= 16) break;
+    if ((rows_lds(es, R, p->rowb, p->bpg, p->rec_bytes, p->W).total <= lds_cap && plan_lds(R, zeta, nb) <= lds_cap) ||
+        R <= 16)
+      break;
     R = R * 7 / 8;
   }
   p->R = R;
   p->lds_bytes = rows_lds(es, R, p->rowb, p->bpg, p->rec_bytes, p->W).total;
-  if (p->lds_bytes > lds_cap) {
+  if (p->lds_bytes > lds_cap || plan_lds(R, zeta, nb) > lds_cap) {
     set_error("sketch_apply: LDS plan does not fit");
     return SK_E_NOTSUP;
   }
@@ -753,7 +773,7 @@ int launch_plan_generic(const sk_sketch* S, int R, int rec_bytes, int lst_off, i
   a.rec_bytes = rec_bytes;
   a.lst_off = lst_off;
   a.runit = runit;
-  const int threads = 64 * std::min(16, S->zeta);
+  const int threads = 64 * plan_waves(R, S->zeta, S->nb);
   const size_t lds = plan_lds(R, S->zeta, S->nb);
   SK_HIP(hipFuncSetAttribute((const void*)ss_plan_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(ss_plan_kernel, dim3((unsigned)n_tiles), dim3(threads), lds, st, a);
@@ -780,6 +800,7 @@ static int launch_rows_t(const sk_sketch* S, const RowsPlan& p, int64_t m, const
   a.R = p.R;
   a.bpg = p.bpg;
   a.n_groups = p.n_groups;
+  a.ranges = p.ranges;
   a.H = p.H;
   a.per_range = p.per_range;
   a.n_chunks = p.n_chunks;

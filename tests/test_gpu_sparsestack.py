@@ -6,7 +6,8 @@
     |SA_gpu - SA_ref| <= (c_j + 8) * u * (|S||A|)_jc, where c_j is the number
     of rows in bucket j and u the unit roundoff of the accumulation type
     (2^-53 for float64, 2^-24 for float32), on ragged shapes, several tiles,
-    zeta in {1, 4, 8}, one bucket per block (d = zeta), and float32 / bfloat16
+    zeta in {1, 2, 4, 8, 64}, one bucket per block (d = zeta), blocks of more
+    buckets than one workgroup holds (up to 16384), and float32 / bfloat16
     inputs (compared with the oracle applied to the same rounded values);
   * results are bitwise reproducible run to run;
   * S^T (adjoint) matches the oracle and satisfies <SA, Y> = <A, S^T Y>;
@@ -80,6 +81,10 @@ CASES = [
     (9000, 4, 4096, 4, 13),    # narrow input at its largest d (four buckets per lane)
     (1000003, 1, 800, 8, 15),  # narrow input, the right-hand side at scale (many tiles per chunk)
     (4000, 5, 64, 4, 14),      # the narrowest input of the wide kernel
+    (5003, 70, 1602, 2, 17),   # 801 buckets per block: one more than 16 waves hold, two bucket ranges
+    (30011, 40, 8000, 2, 16),  # 4000 buckets per block: five bucket ranges per block
+    (20000, 16, 16384, 1, 18), # the largest block of the row apply (16384 buckets, 21 ranges)
+    (4000, 5, 640, 64, 19),    # 64 blocks: the plan kernel's tile shrinks to fit its LDS
 ]
 
 
@@ -97,7 +102,8 @@ def test_apply_f64_parity(lib, n, m, d, zeta, seed):
 @pytest.mark.parametrize("n,m,d,zeta,seed", [(20000, 64, 200, 4, 1), (6007, 100, 2000, 8, 2),
                                              (3000, 16, 64, 8, 3), (1000, 500, 400, 8, 4),
                                              (100000, 64, 400, 8, 5), (30000, 1, 200, 4, 6),
-                                             (20011, 3, 96, 8, 7)])
+                                             (20011, 3, 96, 8, 7), (20000, 64, 2048, 1, 8),
+                                             (7001, 24, 6000, 2, 9)])
 def test_apply_lowprec_parity(lib, dtype, n, m, d, zeta, seed):
     rng = np.random.default_rng(seed)
     A = torch.from_numpy(rng.standard_normal((n, m))).cuda().to(torch.float32).to(dtype)
