@@ -129,8 +129,14 @@ int sketch_apply(sketch_t S, int dtype_in, int layout, int64_t m, const void* A,
                  int dtype_out, void* SA, int64_t ldsa, void* ws, size_t ws_bytes, void* stream);
 
 /*
- * Y = A S^T (the paper's A Omega): A is rows x n row-major (lda >= n) of
- * dtype_in, Y is rows x d row-major (ldy >= d) of dtype_out.
+ * Y = A S^T (the paper's A Omega): A is rows x n of dtype_in, layout
+ * SK_ROW_MAJOR (element (r,i) at A[r*lda + i], lda >= n) or SK_COL_MAJOR
+ * (element (r,i) at A[i*lda + r], lda >= rows); Y is rows x d row-major
+ * (ldy >= d) of dtype_out. Column-major A is the row-major n x rows matrix
+ * A^T: Y^T = S A^T is sketch_apply's row-mode apply of it (written d x rows
+ * into the workspace, with sketch_apply's input rules and limits), then a
+ * tiled transpose into Y; the result is bitwise the transpose of
+ * sketch_apply on A^T. The row-major path:
  *   SparseStack: any input type, F32 accumulation for F32/BF16, F64 for F64.
  *   Gaussian: F64 or F32 input; G (d x n) is generated into the workspace and
  *     Y = A G^T is one GEMM on the matrix cores (F32 GEMM for F32 input).
@@ -139,7 +145,7 @@ int sketch_apply(sketch_t S, int dtype_in, int layout, int64_t m, const void* A,
  * Deterministic for SparseStack, SRTT and SparseRTT; the Gaussian GEMM
  * follows rocBLAS.
  */
-int sketch_apply_T(sketch_t S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out,
+int sketch_apply_T(sketch_t S, int dtype_in, int layout, int64_t rows, const void* A, int64_t lda, int dtype_out,
                    void* Y, int64_t ldy, void* ws, size_t ws_bytes, void* stream);
 
 /* Result details of sketch_sv_extremes. */
@@ -170,7 +176,8 @@ int sketch_sv_extremes(sketch_t S, int steps, uint64_t start_seed, double* alpha
 
 /* Workspace bytes needed by sketch_apply (op 0: row-major A, m = columns of
  * A; op 2: column-major A, which adds the row-major copy, n * m elements) or
- * sketch_apply_T (op 1, m = rows of A). */
+ * sketch_apply_T (m = rows of A; op 1: row-major A; op 3: column-major A,
+ * op 0's bytes for A^T plus the d x rows result before its transpose). */
 int sketch_workspace_size(sketch_t S, int op, int dtype_in, int64_t m, size_t* bytes);
 
 /*

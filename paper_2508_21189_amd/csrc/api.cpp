@@ -247,7 +247,7 @@ int sketch_info(sketch_t S, int* kind, int64_t* d, int64_t* n, int* zeta, uint64
 }
 
 int sketch_workspace_size(sketch_t S, int op, int dtype_in, int64_t m, size_t* bytes) {
-  if (!S || !bytes || m < 1 || !valid_dtype(dtype_in) || op < 0 || op > 2) {
+  if (!S || !bytes || m < 1 || !valid_dtype(dtype_in) || op < 0 || op > 3) {
     set_error("sketch_workspace_size: invalid argument");
     return SK_E_INVAL;
   }
@@ -282,14 +282,25 @@ int sketch_apply(sketch_t S, int dtype_in, int layout, int64_t m, const void* A,
   return apply_dispatch(S, dtype_in, m, A, lda, dtype_out, SA, ldsa, ws, ws_bytes, (hipStream_t)stream);
 }
 
-int sketch_apply_T(sketch_t S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out, void* Y,
-                   int64_t ldy, void* ws, size_t ws_bytes, void* stream) {
+int sketch_apply_T(sketch_t S, int dtype_in, int layout, int64_t rows, const void* A, int64_t lda, int dtype_out,
+                   void* Y, int64_t ldy, void* ws, size_t ws_bytes, void* stream) {
   if (!S || !A || !Y) {
     set_error("sketch_apply_T: null handle or pointer");
     return SK_E_INVAL;
   }
   if (rows < 1 || !valid_dtype(dtype_in) || (dtype_out != SK_F64 && dtype_out != SK_F32)) {
     set_error("sketch_apply_T: need rows >= 1, dtype_in in {F64, F32, BF16}, dtype_out in {F64, F32}");
+    return SK_E_INVAL;
+  }
+  if (layout == SK_COL_MAJOR) {
+    if (lda < rows || ldy < S->d) {
+      set_error("sketch_apply_T: column-major A needs lda >= rows, and ldy >= d");
+      return SK_E_INVAL;
+    }
+    return apply_T_colmajor(S, dtype_in, rows, A, lda, dtype_out, Y, ldy, ws, ws_bytes, (hipStream_t)stream);
+  }
+  if (layout != SK_ROW_MAJOR) {
+    set_error("sketch_apply_T: layout must be SK_ROW_MAJOR or SK_COL_MAJOR");
     return SK_E_INVAL;
   }
   if (lda < S->n || ldy < S->d) {

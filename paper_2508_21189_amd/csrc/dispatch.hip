@@ -105,7 +105,20 @@ static size_t colmajor_copy_bytes(const sk_sketch* S, int dtype_in, int64_t m) {
   return ((size_t)S->n * colmajor_copy_ld(m) * dtype_size(dtype_in) + 255) & ~(size_t)255;
 }
 
+// The d x rows result S A^T of sketch_apply_T with column-major A, before
+// its transpose (F64 output is the worst case), 256-aligned.
+static size_t colmajor_T_result_bytes(const sk_sketch* S, int64_t rows) {
+  return ((size_t)S->d * rows * 8 + 255) & ~(size_t)255;
+}
+
 int apply_workspace(const sk_sketch* S, int op, int dtype_in, int64_t m, size_t* bytes) {
+  if (op == 3) {  // sketch_apply_T with column-major A: op 0 on A^T (m = rows), then the result
+    size_t rest = 0;
+    int rc = apply_workspace(S, 0, dtype_in, m, &rest);
+    if (rc != SK_OK) return rc;
+    *bytes = colmajor_T_result_bytes(S, m) + rest;
+    return SK_OK;
+  }
   if (op == 2) {  // sketch_apply with column-major A: the row-major copy, then op 0 on it
     size_t rest = 0;
     int rc = apply_workspace(S, 0, dtype_in, m, &rest);
@@ -172,6 +185,32 @@ int apply_colmajor(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t
   rc = launch_colmajor_to_rowmajor(dtype_in, A, lda, S->n, m, w, ldt, st);
   if (rc != SK_OK) return rc;
   return apply_dispatch(S, dtype_in, m, w, ldt, dtype_out, SA, ldsa, (char*)w + cb, need - cb, st);
+}
+
+// Y = A S^T for column-major A (rows x n): the n x rows row-major matrix A^T
+// is sketched by the row-mode apply into the workspace (d x rows), which is
+// then transposed into Y.
+int apply_T_colmajor(sk_sketch* S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out, void* Y,
+                     int64_t ldy, void* ws, size_t ws_bytes, hipStream_t st) {
+  size_t need = 0;
+  int rc = apply_workspace_for(S, dtype_in, rows, A, lda, &need);
+  if (rc != SK_OK) return rc;
+  const size_t rb = colmajor_T_result_bytes(S, rows);
+  need += rb;
+  void* w = ws;
+  if (w) {
+    if (ws_bytes < need) {
+      set_error("sketch_apply_T: workspace too small for column-major A (see sketch_workspace_size, op 3)");
+      return SK_E_INVAL;
+    }
+  } else {
+    rc = handle_workspace(S, need, &w);
+    if (rc != SK_OK) return rc;
+  }
+  rc = apply_dispatch(S, dtype_in, rows, A, lda, dtype_out, w, rows, (char*)w + rb, need - rb, st);
+  if (rc != SK_OK) return rc;
+  // S A^T is d x rows row-major, i.e. the column-major rows x d matrix Y
+  return launch_colmajor_to_rowmajor(dtype_out, w, rows, rows, S->d, Y, ldy, st);
 }
 
 int apply_dispatch(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t lda, int dtype_out, void* SA,

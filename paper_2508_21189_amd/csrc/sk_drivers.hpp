@@ -14,6 +14,8 @@ int apply_workspace_for(const sk_sketch* S, int dtype_in, int64_t m, const void*
 
 // SA = S A for a column-major A (n x m, lda >= n): a row-major copy in the
 // workspace (op 2 of apply_workspace), then the row-mode apply.
+int apply_T_colmajor(sk_sketch* S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out, void* Y,
+                     int64_t ldy, void* ws, size_t ws_bytes, hipStream_t st);
 int apply_colmajor(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t lda, int dtype_out, void* SA,
                    int64_t ldsa, void* ws, size_t ws_bytes, hipStream_t st);
 int apply_dispatch(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t lda, int dtype_out, void* SA,

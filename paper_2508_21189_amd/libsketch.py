@@ -52,7 +52,7 @@ def load():
                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_uint64)]
     lib.sketch_apply.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _i64, _vp, _i64, ctypes.c_int, _vp, _i64, _vp,
                                  ctypes.c_size_t, _vp]
-    lib.sketch_apply_T.argtypes = [_vp, ctypes.c_int, _i64, _vp, _i64, ctypes.c_int, _vp, _i64, _vp,
+    lib.sketch_apply_T.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _i64, _vp, _i64, ctypes.c_int, _vp, _i64, _vp,
                                    ctypes.c_size_t, _vp]
     lib.sketch_workspace_size.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _i64, ctypes.POINTER(ctypes.c_size_t)]
     lib.sketch_adjoint.argtypes = [_vp, _i64, _vp, _i64, _vp, _i64, _vp]
@@ -204,15 +204,23 @@ class Sketch:
                                   out.stride(0), wsp, wsb, _stream(stream)))
         return out
 
-    def apply_T(self, A, out_dtype=None, out=None, stream=None):
-        """Y = A @ S^T for a row-major (rows x n) CUDA tensor A."""
-        assert A.is_cuda and A.dim() == 2 and A.shape[1] == self.n and A.stride(1) == 1
+    def apply_T(self, A, out_dtype=None, out=None, ws=None, stream=None):
+        """Y = A @ S^T for a (rows x n) CUDA tensor A, row-major (stride(1) == 1)
+        or column-major (stride(0) == 1, e.g. a transposed view)."""
+        assert A.is_cuda and A.dim() == 2 and A.shape[1] == self.n
         rows = A.shape[0]
+        if A.stride(1) == 1 and (A.stride(0) >= self.n or rows == 1):
+            layout, lda = SK_ROW_MAJOR, A.stride(0)
+        else:
+            assert A.stride(0) == 1, "A must be row-major or column-major"
+            layout, lda = SK_COL_MAJOR, A.stride(1)
         odt = out_dtype or (torch.float64 if A.dtype == torch.float64 else torch.float32)
         if out is None:
             out = torch.empty((rows, self.d), dtype=odt, device=A.device)
-        check(load().sketch_apply_T(self.h, _DT[A.dtype], rows, _ptr(A), A.stride(0), _DT[odt], _ptr(out),
-                                    out.stride(0), None, 0, _stream(stream)))
+        assert out.shape == (rows, self.d) and out.stride(1) == 1 and out.dtype == odt
+        wsp, wsb = (None, 0) if ws is None else (_ptr(ws), ws.numel() * ws.element_size())
+        check(load().sketch_apply_T(self.h, _DT[A.dtype], layout, rows, _ptr(A), lda, _DT[odt], _ptr(out),
+                                    out.stride(0), wsp, wsb, _stream(stream)))
         return out
 
     def adjoint(self, Y, stream=None):

@@ -10,7 +10,9 @@
     both orthonormalize range(Y) and take the exact SVD of Q^T A), U and V
     have orthonormal columns, and ||A - U diag(s) V^T||_2 matches the
     oracle's spectral error (within 1%);
-  * float32 input: the spectral error matches the oracle's within 1%.
+  * float32 input: the spectral error matches the oracle's within 1%;
+  * column-major A (a transposed view) gives bitwise the transpose of the
+    row-mode apply of A^T, for every sketch kind.
 """
 import numpy as np
 import pytest
@@ -61,6 +63,32 @@ def test_apply_T_lowprec(lib, dtype, rows, n, d, zeta, seed):
         ref = sk.sparsestack_apply_T(A64, d, zeta, seed)
         bound = _bound_T(A64, d, zeta, seed, 2.0 ** -24) + 2.0 ** -24 * np.abs(ref)
         assert np.all(np.abs(got - ref) <= bound)
+
+
+@pytest.mark.parametrize("kind,dtype,rows,n,d,zeta", [("sparsestack", torch.float64, 130, 777, 40, 4),
+                                                     ("sparsestack", torch.float64, 70, 3001, 4000, 2),
+                                                     ("sparsestack", torch.float32, 200, 1000, 64, 8),
+                                                     ("sparsestack", torch.bfloat16, 100, 4097, 512, 8),
+                                                     ("gaussian", torch.float64, 64, 1000, 40, 1),
+                                                     ("srtt", torch.float64, 33, 777, 40, 1),
+                                                     ("sparsertt", torch.float64, 65, 1500, 48, 0)])
+def test_apply_T_column_major(lib, kind, dtype, rows, n, d, zeta):
+    """Column-major A (a transposed view): bitwise the transpose of the row-mode
+    apply of A^T; for SparseStack also the oracle within the summation bound
+    (including 2000 buckets per block, beyond what the row-major path takes)."""
+    rng = np.random.default_rng(rows + n)
+    At = torch.from_numpy(rng.standard_normal((n, rows))).to(torch.float32).to(dtype).cuda()
+    A = At.t()  # rows x n, stride(0) == 1
+    S = lib.Sketch(kind, d, n, zeta, 5)
+    odt = torch.float64
+    got = S.apply_T(A, out_dtype=odt)
+    want = S.apply(At, out_dtype=odt).t()
+    assert torch.equal(got, want)
+    if kind == "sparsestack":
+        A64 = A.to(torch.float64).cpu().numpy()
+        ref = sk.sparsestack_apply_T(A64, d, zeta, 5)
+        u = 2.0 ** -53 if dtype == torch.float64 else 2.0 ** -24
+        assert np.all(np.abs(got.cpu().numpy() - ref) <= _bound_T(A64, d, zeta, 5, u))
 
 
 def _decay(rows, cols, seed):
