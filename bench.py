@@ -343,8 +343,9 @@ def main():
     ap.add_argument("--inj-steps", type=int, default=400, help="Lanczos steps per estimate")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the row-sharded design is described in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (it would shard A by rows, "
+              "each GPU sketching its block and one all-reduce summing the d x m partials). Run with --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -1,7 +1,7 @@
 """Philox4x32-10 in NumPy (oracle side; test infrastructure only).
 
 The paper only asks for iid uniform bucket indices and Rademacher signs
-(Def. 1.5). This build draws them from Philox4x32-10, the counter-based
+(Def. 1.5). They are drawn here from Philox4x32-10, the counter-based
 generator of Salmon, Moraes, Dror and Shaw ("Parallel random numbers: as
 easy as 1, 2, 3", SC'11), so that entry (i, t) of the sketch is a pure
 function of (seed, i, t) and either side can produce any entry on demand.

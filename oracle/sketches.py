@@ -148,7 +148,7 @@ def srtt_sample(npad, d, seed):
     """d distinct row indices of [0, npad), sorted ascending.
 
     The paper's restriction selects coordinates uniformly at random (Sec. 1.4.2)
-    without saying whether repeats are allowed; this build samples without
+    without saying whether repeats are allowed; it is sampled here without
     replacement (as SparseCol does, Def. 4.1) using Floyd's algorithm: for
     j = npad-d .. npad-1 draw u uniform on {0..j}; insert u, or j if u is
     already chosen. u = (w * (j+1)) >> 32 with w the first Philox word of
