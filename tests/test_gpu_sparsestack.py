@@ -9,6 +9,8 @@
     zeta in {1, 2, 4, 8, 64}, one bucket per block (d = zeta), blocks of more
     buckets than one workgroup holds (up to 16384), and float32 / bfloat16
     inputs (compared with the oracle applied to the same rounded values);
+  * edge cases: one row of A, d = 1, zeta = 100 blocks of one bucket, 1000
+    columns, a tile exactly full and a one-row tail;
   * results are bitwise reproducible run to run;
   * S^T (adjoint) matches the oracle and satisfies <SA, Y> = <A, S^T Y>;
   * at the full 4,194,304 x 200 float64 shape, sampled columns match the
@@ -96,6 +98,34 @@ def test_apply_f64_parity(lib, n, m, d, zeta, seed):
     got = S.apply(torch.from_numpy(A).cuda()).cpu().numpy()
     ref = sk.sparsestack_apply(A, d, zeta, seed)
     _check(got, ref, _bound(A, d, zeta, seed, 2.0 ** -53))
+
+
+EDGE_CASES = [
+    (1, 5, 8, 8, 21),          # one row of A: one partial tile, every other chunk empty
+    (1, 1, 3, 3, 22),          # one row, one column (narrow kernel)
+    (7, 64, 1, 1, 23),         # d = 1: a single bucket, every row lands in it
+    (500, 130, 100, 100, 24),  # zeta = 100 > 16 blocks: several block groups, plan waves loop over blocks
+    (300, 3, 100, 100, 25),    # zeta = 100 on the narrow kernel
+    (2000, 1000, 40, 4, 26),   # 1000 columns: 16 column slabs
+    (163, 50, 800, 8, 27),     # exactly one full tile of the coherent layout
+    (164, 50, 800, 8, 28),     # one full tile and a one-row tail
+]
+
+
+@pytest.mark.parametrize("n,m,d,zeta,seed", EDGE_CASES)
+def test_apply_edge_cases(lib, n, m, d, zeta, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, m))
+    S = lib.Sketch("sparsestack", d, n, zeta, seed)
+    got = S.apply(torch.from_numpy(A).cuda()).cpu().numpy()
+    ref = sk.sparsestack_apply(A, d, zeta, seed)
+    _check(got, ref, _bound(A, d, zeta, seed, 2.0 ** -53))
+    # float32 with an odd column count takes the 4-byte load path
+    A32 = torch.from_numpy(A).to(torch.float32)
+    got32 = S.apply(A32.cuda(), out_dtype=torch.float64).cpu().numpy()
+    A64 = A32.double().numpy()
+    ref32 = sk.sparsestack_apply(A64, d, zeta, seed)
+    _check(got32, ref32, _bound(A64, d, zeta, seed, 2.0 ** -24))
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
