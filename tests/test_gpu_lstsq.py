@@ -11,8 +11,9 @@ solution x* of the oracle (Householder TSQR of [A b] in float64):
 ||A (x - x*)|| <= 1e-10 ||b|| and | ||r|| - ||r*|| | <= 1e-10 ||r*||, for the
 float64 sketch and for float32 and bfloat16 sketch copies of A, on Gaussian,
 coherent (Pareto rows, spikes, kappa = 1e8) and kappa = 1e10 column-scaled
-inputs; the run is bitwise reproducible; the iteration cap and the cold start
-behave as documented.
+inputs, including the benchmark's full 4,194,304 x 200 coherent solve at
+tol 1e-10; the run is bitwise reproducible; the iteration cap and the cold
+start behave as documented.
 """
 import numpy as np
 import pytest
@@ -137,6 +138,20 @@ def test_precond_coherent(lib, exponent):
     x, rc, info = S.lstsq_precond(_gpu(A), _gpu(b), tol=1e-12, maxit=300)
     assert rc == 0
     _check_vs_exact(A, b, x.cpu().numpy())
+
+
+def test_precond_full_size_coherent(lib):
+    """The solve the benchmark times, at its full size: coherent 4,194,304 x 200
+    (Pareto rows, spikes, kappa(D) = 1e8; the same generator and seeds),
+    SparseStack d = 800, zeta = 8, tol 1e-10, against the oracle's exact
+    solution (Householder TSQR of [A b] on the host, about half a minute)."""
+    from paper_2508_21189_amd import inputs
+    n, m, d, zeta = 1 << 22, 200, 800, 8
+    A, b, _, _ = inputs.coherent(n, m, exponent=8.0, seed=200)
+    S = lib.Sketch("sparsestack", d, n, zeta, 2000)
+    x, rc, info = S.lstsq_precond(A, b, tol=1e-10, maxit=300)
+    assert rc == 0 and info["converged"] == 1
+    _check_vs_exact(A.cpu().numpy(), b.cpu().numpy(), x.cpu().numpy())
 
 
 @pytest.mark.parametrize("dt", [torch.float32, torch.bfloat16])
