@@ -12,7 +12,10 @@
     oracle's spectral error (within 1%);
   * float32 input: the spectral error matches the oracle's within 1%;
   * column-major A (a transposed view) gives bitwise the transpose of the
-    row-mode apply of A^T, for every sketch kind.
+    row-mode apply of A^T, for every sketch kind;
+  * at the benchmark's full size (65536 x 16384 float32, k = 512) the
+    singular values satisfy interlacing and Weyl's bound against the known
+    spectrum i^-2.
 """
 import numpy as np
 import pytest
@@ -162,6 +165,31 @@ def test_apply_T_srtt(lib, rows, n, d, seed):
     ref32 = sk.srtt_apply(A32.double().numpy().T, d, seed).T
     got32 = S.apply_T(A32.cuda(), out_dtype=torch.float64).cpu().numpy()
     assert np.all(np.abs(got32 - ref32) <= (p + 2) * 2.0 ** -24 * l1)
+
+
+def test_rsvd_full_size_known_spectrum(lib):
+    """The benchmark's RSVD at its full size: A = U diag(i^-2) V^T (Haar U, V),
+    65536 x 16384 float32, SparseStack k = 512, zeta = 8 (the benchmark's
+    generator and seeds). Checks that hold at any size:
+      * s_i <= sigma_i(A): the singular values of Q^T A interlace those of A
+        (float32 storage moves sigma_i(A) off i^-2 by at most 2^-24 ||A||_F);
+      * sigma_i(A) - s_i <= ||A - U diag(s) V^T||_2 (Weyl), which is about
+        1.4e-5 here (sigma_513 = 3.8e-6 is the floor): the test allows 3e-5;
+      * U and V^T have orthonormal columns / rows."""
+    from paper_2508_21189_amd import inputs
+    rows, cols, k = 65536, 16384, 512
+    A, sig = inputs.lowrank_decay(rows, cols, seed=202, dtype=torch.float32)
+    S = lib.Sketch("sparsestack", k, cols, 8, 2002)
+    U, s, Vt, rc, info = S.rsvd(A)
+    assert rc == 0
+    exact = sig[:k].double()
+    fro = float(torch.sqrt((sig.double() ** 2).sum()))
+    slack = 2.0 ** -24 * fro
+    assert torch.all(s <= exact + slack)
+    assert torch.all(exact - s <= 3e-5)
+    eye = torch.eye(k, dtype=torch.float64, device="cuda")
+    assert float((U.T @ U - eye).abs().max()) <= 1e-12
+    assert float((Vt @ Vt.T - eye).abs().max()) <= 1e-12
 
 
 @pytest.mark.parametrize("kind", ["gaussian", "srtt"])
