@@ -63,9 +63,8 @@ enum {
 /*
  * Create a sketch S (d x n) on the current HIP device.
  *   kind  SK_SPARSESTACK: requires 1 <= zeta <= d and d % zeta == 0 and
- *         d / zeta < 2^31 (sketch_apply takes at most 16384 buckets per
- *         block; sketch_apply_T at most 800 for SK_F64 and 1024 for SK_F32
- *         and SK_BF16; both refuse more with SK_E_NOTSUP).
+ *         d / zeta < 2^31 (sketch_apply and sketch_apply_T take at most
+ *         16384 buckets per block and refuse more with SK_E_NOTSUP).
  *         The bucket s_it in [0, d/zeta) and sign rho_it of column i,
  *         block t are drawn from Philox4x32-10 (Salmon et al., SC'11) with
  *         key = seed and counter (i mod 2^32, i >> 32, t / 4, 1), word t % 4:
@@ -138,6 +137,10 @@ int sketch_apply(sketch_t S, int dtype_in, int layout, int64_t m, const void* A,
  * tiled transpose into Y; the result is bitwise the transpose of
  * sketch_apply on A^T. The row-major path:
  *   SparseStack: any input type, F32 accumulation for F32/BF16, F64 for F64.
+ *     Blocks of more than 800 (F64) or 1024 (F32, BF16) buckets, more than
+ *     the column kernel keeps in registers, take the column-major route on
+ *     the same memory (A is then the column-major n x rows matrix A^T): two
+ *     transposes through the workspace and the row-mode apply.
  *   Gaussian: F64 or F32 input; G (d x n) is generated into the workspace and
  *     Y = A G^T is one GEMM on the matrix cores (F32 GEMM for F32 input).
  *   SRTT and SparseRTT: one Walsh-Hadamard transform per row in LDS; needs

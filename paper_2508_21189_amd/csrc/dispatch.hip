@@ -145,6 +145,13 @@ int apply_workspace(const sk_sketch* S, int op, int dtype_in, int64_t m, size_t*
   } else if (op == 0 && trig_kind(S->kind)) {
     *bytes = srtt_workspace(S, (int)m);
   } else if (op == 1 && S->kind == SK_SPARSESTACK) {
+    if (!cols_kernel_fits(S, dtype_in)) {  // through the row-mode apply of A^T
+      size_t rest = 0;
+      int rc = apply_workspace(S, 2, dtype_in, m, &rest);
+      if (rc != SK_OK) return rc;
+      *bytes = colmajor_T_result_bytes(S, m) + rest;
+      return SK_OK;
+    }
     return cols_workspace(S, dtype_in, bytes);
   } else if (op == 1 && (S->kind == SK_GAUSSIAN || trig_kind(S->kind))) {
     // m is the number of rows of A in this orientation; F64 output is the worst case
@@ -291,9 +298,36 @@ int apply_dispatch(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t
   }
 }
 
+// Y = A S^T for row-major A with more buckets per block than the column
+// kernel holds: row-major A is the column-major n x rows matrix A^T, which
+// sketch_apply's column-major path (a tiled transpose into the workspace, then
+// the row-mode apply) turns into S A^T (d x rows), transposed into Y.
+static int apply_T_via_rows(sk_sketch* S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out,
+                            void* Y, int64_t ldy, void* ws, size_t ws_bytes, hipStream_t st) {
+  size_t rest = 0;
+  int rc = apply_workspace(S, 2, dtype_in, rows, &rest);
+  if (rc != SK_OK) return rc;
+  const size_t rb = colmajor_T_result_bytes(S, rows);
+  void* w = ws;
+  if (w) {
+    if (ws_bytes < rb + rest) {
+      set_error("sketch_apply_T: workspace too small (see sketch_workspace_size)");
+      return SK_E_INVAL;
+    }
+  } else {
+    rc = handle_workspace(S, rb + rest, &w);
+    if (rc != SK_OK) return rc;
+  }
+  rc = apply_colmajor(S, dtype_in, rows, A, lda, dtype_out, w, rows, (char*)w + rb, rest, st);
+  if (rc != SK_OK) return rc;
+  return launch_colmajor_to_rowmajor(dtype_out, w, rows, rows, S->d, Y, ldy, st);
+}
+
 int apply_T_dispatch(sk_sketch* S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out, void* Y,
                      int64_t ldy, void* ws, size_t ws_bytes, hipStream_t st) {
   if (S->kind == SK_IDENTITY_TEST) return launch_convert(dtype_in, A, lda, dtype_out, Y, ldy, rows, S->n, st);
+  if (S->kind == SK_SPARSESTACK && !cols_kernel_fits(S, dtype_in))
+    return apply_T_via_rows(S, dtype_in, rows, A, lda, dtype_out, Y, ldy, ws, ws_bytes, st);
   if (S->kind == SK_SPARSESTACK) {
     size_t need = 0;
     int rc = cols_workspace(S, dtype_in, &need);

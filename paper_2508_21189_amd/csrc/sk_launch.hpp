@@ -37,6 +37,7 @@ int launch_rows_apply(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64
                       int64_t lda, int dtype_out, void* SA, int64_t ldsa, void* ws, hipStream_t st);
 
 // Column mode (Y = A S^T, A rows x n row-major): workspace bytes and launch.
+bool cols_kernel_fits(const sk_sketch* S, int dtype_in);
 int cols_workspace(const sk_sketch* S, int dtype_in, size_t* bytes);
 int launch_cols_apply(const sk_sketch* S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out,
                       void* Y, int64_t ldy, void* ws, size_t ws_bytes, hipStream_t st);

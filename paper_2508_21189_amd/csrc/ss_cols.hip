@@ -338,12 +338,19 @@ struct ColsPlan {
   size_t lds, plan_bytes;
 };
 
+// The column kernel keeps a block's buckets in the registers of at most 16
+// waves: at most 16 * 50 (FP64) or 16 * 64 (FP32 / BF16) buckets per block.
+bool cols_kernel_fits(const sk_sketch* S, int dtype_in) {
+  const int jmax = dtype_in == SK_F64 ? 50 : 64;
+  return S->nb <= 16383 && (S->nb + jmax - 1) / jmax <= 16;
+}
+
 static int cols_plan(const sk_sketch* S, int dtype_in, ColsPlan* p) {
   const int accb = dtype_in == SK_F64 ? 8 : 4;
   const int jmax = dtype_in == SK_F64 ? 50 : 64;
   const int64_t nb = S->nb;
   const int Hmin = (int)((nb + jmax - 1) / jmax);
-  if (Hmin > 16 || nb > 16383) {
+  if (!cols_kernel_fits(S, dtype_in)) {
     set_error("sketch_apply_T: d/zeta too large for the register-resident accumulators");
     return SK_E_NOTSUP;
   }

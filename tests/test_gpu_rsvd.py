@@ -13,6 +13,9 @@
   * float32 input: the spectral error matches the oracle's within 1%;
   * column-major A (a transposed view) gives bitwise the transpose of the
     row-mode apply of A^T, for every sketch kind;
+  * blocks of more buckets than the column kernel holds go through the
+    row-mode apply of A^T: within the oracle's bound, bitwise equal to the
+    column-major route, and an RSVD on such a sketch matches the oracle;
   * at the benchmark's full size (65536 x 16384 float32, k = 512) the
     singular values satisfy interlacing and Weyl's bound against the known
     spectrum i^-2.
@@ -92,6 +95,36 @@ def test_apply_T_column_major(lib, kind, dtype, rows, n, d, zeta):
         ref = sk.sparsestack_apply_T(A64, d, zeta, 5)
         u = 2.0 ** -53 if dtype == torch.float64 else 2.0 ** -24
         assert np.all(np.abs(got.cpu().numpy() - ref) <= _bound_T(A64, d, zeta, 5, u))
+
+
+@pytest.mark.parametrize("dtype,rows,n,d,zeta", [(torch.float64, 70, 3001, 4000, 2), (torch.float32, 64, 2000, 2100, 1),
+                                                 (torch.bfloat16, 36, 1500, 1700, 1)])
+def test_apply_T_large_blocks(lib, dtype, rows, n, d, zeta):
+    """More buckets per block than the column kernel holds (800 FP64, 1024 FP32/BF16): row-major A goes through the
+    row-mode apply of A^T; within the summation bound of the oracle and bitwise equal to the column-major route."""
+    rng = np.random.default_rng(d)
+    A = torch.from_numpy(rng.standard_normal((rows, n))).to(torch.float32).to(dtype).cuda()
+    S = lib.Sketch("sparsestack", d, n, zeta, 8)
+    got = S.apply_T(A, out_dtype=torch.float64)
+    assert torch.equal(got, S.apply_T(A.t().contiguous().t(), out_dtype=torch.float64))
+    A64 = A.to(torch.float64).cpu().numpy()
+    ref = sk.sparsestack_apply_T(A64, d, zeta, 8)
+    u = 2.0 ** -53 if dtype == torch.float64 else 2.0 ** -24
+    assert np.all(np.abs(got.cpu().numpy() - ref) <= _bound_T(A64, d, zeta, 8, u))
+
+
+def test_rsvd_large_blocks(lib):
+    """k = 900 with zeta = 1 (900 buckets, past the column kernel): the singular values of the oracle's rsvd on the
+    same sketch Y, to 1e-12 absolute (||A||_2 = 1). cols >> k, so that no bucket is empty (an empty bucket is a zero
+    column of Y, which rsvd reports as rank deficient)."""
+    rows, cols, k = 1400, 12000, 900
+    A, _ = _decay(rows, cols, seed=k)
+    S = lib.Sketch("sparsestack", k, cols, 1, 100 + k)
+    U, s, Vt, rc, info = S.rsvd(torch.from_numpy(A).cuda())
+    assert rc == 0
+    Y = sk.sparsestack_apply_T(A, k, 1, 100 + k)
+    Ur, sr, Vtr, Q = lr.rsvd_from_sketch(A, Y)
+    assert np.max(np.abs(s.cpu().numpy() - sr)) <= 1e-12
 
 
 def _decay(rows, cols, seed):
