@@ -12,7 +12,9 @@ solution x* of the oracle (Householder TSQR of [A b] in float64):
 float64 sketch and for float32 and bfloat16 sketch copies of A, on Gaussian,
 coherent (Pareto rows, spikes, kappa = 1e8) and kappa = 1e10 column-scaled
 inputs, including the benchmark's full 4,194,304 x 200 coherent solve at
-tol 1e-10; the run is bitwise reproducible; the iteration cap and the cold
+tol 1e-10; at the full 8,388,608 x 500 mixed-precision size the float32 and
+bfloat16 sketch variants reach the float64 variant's solution; the run is
+bitwise reproducible; the iteration cap and the cold
 start behave as documented.
 """
 import numpy as np
@@ -152,6 +154,30 @@ def test_precond_full_size_coherent(lib):
     x, rc, info = S.lstsq_precond(A, b, tol=1e-10, maxit=300)
     assert rc == 0 and info["converged"] == 1
     _check_vs_exact(A.cpu().numpy(), b.cpu().numpy(), x.cpu().numpy())
+
+
+def test_precond_full_size_mixed_precision(lib):
+    """The benchmark's mixed-precision system at its full size: 8,388,608 x 500,
+    kappa(D) = 1e10 (same generator and seeds), SparseStack d = 2000, zeta = 8,
+    tol 1e-10, with the sketch reading A itself, its float32 copy and its
+    bfloat16 copy. A property that holds at any size: all three converge to the
+    same least-squares solution, so ||A (x_lo - x_64)|| <= 2e-10 ||b|| and the
+    residual norms agree to 2e-10 (A x is formed by torch in float64)."""
+    from paper_2508_21189_amd import inputs
+    n, m, d = 1 << 23, 500, 2000
+    A, b, _ = inputs.scaled_gaussian(n, m, exponent=10.0, seed=201)
+    S = lib.Sketch("sparsestack", d, n, 8, 2001)
+    x64, rc, info = S.lstsq_precond(A, b, tol=1e-10, maxit=300)
+    assert rc == 0 and info["converged"] == 1
+    nb = float(b.norm())
+    r64 = float((A @ x64 - b).norm())
+    for dt in (torch.float32, torch.bfloat16):
+        As = A.to(dt)
+        x, rc, info = S.lstsq_precond(A, b, tol=1e-10, maxit=300, A_sketch=As)
+        del As
+        assert rc == 0 and info["converged"] == 1
+        assert float((A @ (x - x64)).norm()) <= 2e-10 * nb
+        assert abs(float((A @ x - b).norm()) - r64) <= 2e-10 * r64
 
 
 @pytest.mark.parametrize("dt", [torch.float32, torch.bfloat16])
