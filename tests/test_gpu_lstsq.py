@@ -83,6 +83,23 @@ def test_sketch_and_solve_matches_oracle(lib, n, m, d, zeta, seed):
     assert q_gpu >= 1.0 - 1e-12 and abs(q_gpu - q_ref) <= 1e-10 * q_ref
 
 
+def test_sketch_and_solve_config_distortion(lib):
+    """The 20000 x 50 sketch-and-solve configuration (d = 200, zeta = 4): the
+    distortion of S on range(A) (Prop. 1.9: alpha = sigma_min(SQ)^2,
+    beta = sigma_max(SQ)^2 for an orthonormal basis Q) from the GPU sketch of Q
+    equals the oracle's to 1e-12, and it is an embedding (0 < alpha <= 1 <= beta)."""
+    from oracle import metrics
+    from paper_2508_21189_amd import inputs
+    n, m, d, zeta, seed = 20000, 50, 200, 4, 11
+    A, _, _ = inputs.small_gaussian(n, m, seed=seed)
+    Q = np.linalg.qr(A)[0]
+    S = lib.Sketch("sparsestack", d, n, zeta, seed)
+    ag, bg, eg = metrics.distortion(S.apply(_gpu(Q)).cpu().numpy())
+    ar, br, er = metrics.distortion(sk.sparsestack_apply(Q, d, zeta, seed))
+    assert abs(ag - ar) <= 1e-12 and abs(bg - br) <= 1e-12
+    assert 0.0 < ag <= 1.0 <= bg
+
+
 def test_sketch_and_solve_rank_deficient(lib):
     from paper_2508_21189_amd import inputs
     n, m, d, zeta, seed = 6000, 24, 96, 4, 8
