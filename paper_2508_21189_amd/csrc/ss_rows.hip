@@ -15,13 +15,15 @@
 //    with direct global->LDS loads, so the prefetch of tile k+1 costs no VGPRs
 //    and overlaps the work on tile k.
 //  * Each wave owns one block and a contiguous range of its buckets and keeps
-//    one accumulator per bucket per lane in registers. The first row of every
+//    one accumulator per bucket per lane in registers. A block with more
+//    buckets than one workgroup's 16 waves hold is split into bucket ranges
+//    over several workgroups, each reading the tile. The first row of every
 //    bucket is added by fully unrolled, branch-free code (an empty bucket reads
-//    a zero row), so the LDS reads are independent and pipeline; the further
-//    rows of a bucket (a third of all rows when a tile holds one or two rows
-//    per bucket) are compacted into a short per-wave list and added behind one
-//    uniform test per bucket. All 64 lanes read one row at consecutive
-//    columns: LDS reads are conflict-free.
+//    a zero row), so the LDS reads are independent and pipeline; the second
+//    and third rows of every bucket are preloaded one per lane and added
+//    behind scalar bit tests (one readlane each), and only buckets with four
+//    or more rows walk the rest of their list. All lanes read one row at
+//    consecutive columns: LDS reads are conflict-free.
 //  * At the end of the chunk the accumulators go to a partial buffer
 //    [chunk][d][m]; a second kernel sums the partials in chunk order and scales
 //    by 1/sqrt(zeta). Summation order is fixed, so results are bitwise
