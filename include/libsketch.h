@@ -264,6 +264,38 @@ int lstsq_sketch_precond(sketch_t S, int64_t m, const double* A, int64_t lda, in
                          const void* A_sketch, int64_t lda_sketch, const double* b, double* x, double tol,
                          int maxit, int warm_start, sk_lsqr_info* info, void* stream);
 
+/* One problem of lstsq_sketch_solve_batched. */
+typedef struct {
+  int64_t n;       /* rows of A */
+  int64_t k;       /* columns of A, 1 <= k <= 1024 */
+  int dtype;       /* element type of A and b: SK_F64, SK_F32 or SK_BF16 */
+  const void* A;   /* device, n x k row-major, lda >= k */
+  int64_t lda;
+  const void* b;   /* device, n elements */
+  double* x;       /* device, k doubles (output) */
+  uint64_t seed;   /* seed of this problem's SparseStack sketch */
+  int status;      /* output: SK_OK, SK_W_RANKDEF, or SK_E_INVAL for an invalid problem */
+  int rank;        /* output: the numerical rank r of S A */
+  double t_ms;     /* output: device time of this problem (its first to its last kernel) */
+} sk_ls_problem;
+
+/*
+ * Many independent sketch-and-solve problems (Alg. 3, as lstsq_sketch_solve)
+ * in one call: problem p is solved with its own SparseStack sketch of
+ * d = d_per_k * k rows in zeta blocks (zeta must divide d) under key p.seed,
+ * reading A and b in their own precision (F32 and BF16 accumulate the sketch
+ * in F32; QR, SVD and the solve are F64). The problems are queued back to
+ * back on `stream`, sharing one workspace (ws, ws_bytes >=
+ * lstsq_batched_workspace_size; NULL to allocate and free one inside the
+ * call); the call synchronizes once at the end. Every problem is validated
+ * before any work is queued: if one is invalid, its status is SK_E_INVAL,
+ * nothing runs, and SK_E_INVAL is returned. Otherwise returns SK_OK, or
+ * SK_W_RANKDEF if some problem was rank deficient (see its status).
+ */
+int lstsq_batched_workspace_size(const sk_ls_problem* probs, int nprob, int d_per_k, int zeta, size_t* bytes);
+int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int zeta, void* ws, size_t ws_bytes,
+                               void* stream);
+
 /*
  * *resnorm (host) = ||b - A x||_2 in F64, with A (n x m) as above and the
  * handle supplying n and the workspace. Needs m <= 512. Synchronizes.

@@ -7,6 +7,8 @@
 // All device memory comes from one handle-owned buffer carved per call.
 #include <algorithm>
 #include <cmath>
+#include <string>
+#include <vector>
 
 #include "sk_dense.hpp"
 #include "sk_drivers.hpp"
@@ -103,11 +105,12 @@ struct SketchBufs {
   double* c;
 };
 
-int sketch_bufs(Carver& cv, const sk_sketch* S, int k, int dts, const void* As, int64_t ldas, const double* b,
-                SketchBufs* B) {
+// b is of type dtb (F64 unless a batched problem brings F32 or BF16).
+int sketch_bufs(Carver& cv, const sk_sketch* S, int k, int dts, const void* As, int64_t ldas, const void* b,
+                SketchBufs* B, int dtb = SK_F64) {
   size_t wa = 0, wb = 0;
   if (S->kind == SK_GAUSSIAN || trig_kind(S->kind)) {
-    if (dts != SK_F64) {
+    if (dts != SK_F64 || dtb != SK_F64) {
       set_error("the Gaussian, SRTT and SparseRTT sketches read F64 only");
       return SK_E_NOTSUP;
     }
@@ -115,7 +118,7 @@ int sketch_bufs(Carver& cv, const sk_sketch* S, int k, int dts, const void* As, 
     wa = S->kind == SK_GAUSSIAN ? gauss_workspace(S, k + 1) : srtt_workspace(S, k + 1);
   } else {
     SK_TRY(apply_workspace_for(S, dts, k, As, ldas, &wa));
-    SK_TRY(apply_workspace_for(S, SK_F64, 1, b, 1, &wb));
+    SK_TRY(apply_workspace_for(S, dtb, 1, b, 1, &wb));
   }
   const int64_t d = S->d;
   B->SA = cv.take<double>((size_t)d * k);
@@ -132,16 +135,16 @@ int sketch_bufs(Carver& cv, const sk_sketch* S, int k, int dts, const void* As, 
 
 // S A (any input precision, F64 result), S b, and the Householder QR of
 // [S A | S b]: R (k x k) and c = (Q^T S b)[0:k].
-int sketch_and_factor(sk_sketch* S, int k, int dts, const void* As, int64_t ldas, const double* b, const SketchBufs& B,
-                      Phases& ph, hipStream_t st) {
+int sketch_and_factor(sk_sketch* S, int k, int dts, const void* As, int64_t ldas, const void* b, const SketchBufs& B,
+                      Phases& ph, hipStream_t st, int dtb = SK_F64) {
   const int64_t d = S->d;
   if (S->kind == SK_GAUSSIAN) {
-    SK_TRY(launch_gauss_rows(S, k, (const double*)As, ldas, b, B.SA, k, B.Sb, B.aws, B.aws_bytes, st));
+    SK_TRY(launch_gauss_rows(S, k, (const double*)As, ldas, (const double*)b, B.SA, k, B.Sb, B.aws, B.aws_bytes, st));
   } else if (trig_kind(S->kind)) {
-    SK_TRY(launch_srtt_rows(S, k, (const double*)As, ldas, b, B.SA, k, B.Sb, B.aws, B.aws_bytes, st));
+    SK_TRY(launch_srtt_rows(S, k, (const double*)As, ldas, (const double*)b, B.SA, k, B.Sb, B.aws, B.aws_bytes, st));
   } else {
     SK_TRY(apply_dispatch(S, dts, k, As, ldas, SK_F64, B.SA, k, B.aws, B.aws_bytes, st));
-    SK_TRY(apply_dispatch(S, SK_F64, 1, b, 1, SK_F64, B.Sb, 1, B.aws, B.aws_bytes, st));
+    SK_TRY(apply_dispatch(S, dtb, 1, b, 1, SK_F64, B.Sb, 1, B.aws, B.aws_bytes, st));
   }
   SK_TRY(ph.mark());
   SK_TRY(launch_to_columns(B.SA, k, B.Sb, d, k, B.W, d, st));
@@ -151,6 +154,75 @@ int sketch_and_factor(sk_sketch* S, int k, int dts, const void* As, int64_t ldas
 }
 
 bool dtype_ok(int dt) { return dt == SK_F64 || dt == SK_F32 || dt == SK_BF16; }
+
+// ---- batched sketch-and-solve
+bool batched_problem_valid(const sk_ls_problem& p, int d_per_k, int zeta) {
+  if (p.n < 1 || p.k < 1 || p.k > 1024 || p.lda < p.k || !p.A || !p.b || !p.x || !dtype_ok(p.dtype)) return false;
+  const int64_t d = (int64_t)d_per_k * p.k;
+  return d >= p.k && d % zeta == 0;
+}
+
+// Problem p's SparseStack as a description that owns no memory: every buffer
+// its kernels use is carved from the batch workspace.
+void batched_sketch(const sk_ls_problem& p, int d_per_k, int zeta, int device, sk_sketch* W) {
+  W->kind = SK_SPARSESTACK;
+  W->d = (int64_t)d_per_k * p.k;
+  W->n = p.n;
+  W->zeta = zeta;
+  W->nb = W->d / zeta;
+  W->seed = p.seed;
+  W->k0 = (uint32_t)p.seed;
+  W->k1 = (uint32_t)(p.seed >> 32);
+  W->device = device;
+}
+
+struct SolveBufs {
+  SketchBufs B;
+  double *U, *V, *sv, *work, *z;
+};
+
+int batched_bufs(Carver& cv, const sk_sketch* W, const sk_ls_problem& p, SolveBufs* X) {
+  const int k = (int)p.k;
+  SK_TRY(sketch_bufs(cv, W, k, p.dtype, p.A, p.lda, p.b, &X->B, p.dtype));
+  X->U = cv.take<double>((size_t)k * k);
+  X->V = cv.take<double>((size_t)k * k);
+  X->sv = cv.take<double>((size_t)k);
+  X->work = cv.take<double>((size_t)2 * k * k);
+  X->z = cv.take<double>((size_t)k);
+  return SK_OK;
+}
+
+// Workspace layout: the rank of every problem (nprob ints), then the buffers
+// of one problem, reused by each in turn (the problems run in stream order).
+int batched_bytes(const sk_ls_problem* probs, int nprob, int d_per_k, int zeta, int device, size_t* bytes) {
+  size_t mx = 0;
+  for (int i = 0; i < nprob; ++i) {
+    sk_sketch W;
+    batched_sketch(probs[i], d_per_k, zeta, device, &W);
+    Carver cv;
+    cv.take<int>((size_t)nprob);
+    SolveBufs X;
+    SK_TRY(batched_bufs(cv, &W, probs[i], &X));
+    mx = std::max(mx, cv.off);
+  }
+  *bytes = mx;
+  return SK_OK;
+}
+
+int batched_check(const sk_ls_problem* probs, int nprob, int d_per_k, int zeta, const char* who) {
+  if (!probs || nprob < 1 || d_per_k < 1 || zeta < 1) {
+    set_error(std::string(who) + ": need problems, nprob >= 1, d_per_k >= 1 and zeta >= 1");
+    return SK_E_INVAL;
+  }
+  for (int i = 0; i < nprob; ++i) {
+    if (!batched_problem_valid(probs[i], d_per_k, zeta)) {
+      set_error(std::string(who) + ": problem " + std::to_string(i) +
+                " is invalid (need n >= 1, 1 <= k <= 1024, lda >= k, pointers, a dtype, zeta | d_per_k * k)");
+      return SK_E_INVAL;
+    }
+  }
+  return SK_OK;
+}
 
 }  // namespace
 
@@ -224,6 +296,102 @@ int lstsq_sketch_solve(sketch_t S, int64_t m, const double* A, int64_t lda, cons
     info->t_total_ms = ph.ms(0, 2);
   }
   return r < k ? SK_W_RANKDEF : SK_OK;
+}
+
+int lstsq_batched_workspace_size(const sk_ls_problem* probs, int nprob, int d_per_k, int zeta, size_t* bytes) {
+  if (!bytes) {
+    set_error("lstsq_batched_workspace_size: null output");
+    return SK_E_INVAL;
+  }
+  SK_TRY(batched_check(probs, nprob, d_per_k, zeta, "lstsq_batched_workspace_size"));
+  int device = 0;
+  SK_HIP(hipGetDevice(&device));
+  return batched_bytes(probs, nprob, d_per_k, zeta, device, bytes);
+}
+
+int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int zeta, void* ws, size_t ws_bytes,
+                               void* stream) {
+  if (probs && nprob > 0) {
+    for (int i = 0; i < nprob; ++i) {
+      probs[i].status = batched_problem_valid(probs[i], d_per_k, zeta) ? SK_OK : SK_E_INVAL;
+      probs[i].rank = 0;
+      probs[i].t_ms = 0.0;
+    }
+  }
+  SK_TRY(batched_check(probs, nprob, d_per_k, zeta, "lstsq_sketch_solve_batched"));
+  int device = 0;
+  SK_HIP(hipGetDevice(&device));
+  size_t need = 0;
+  SK_TRY(batched_bytes(probs, nprob, d_per_k, zeta, device, &need));
+  if (ws && ws_bytes < need) {
+    set_error("lstsq_sketch_solve_batched: workspace too small (see lstsq_batched_workspace_size)");
+    return SK_E_INVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  void* own = nullptr;
+  if (!ws) SK_HIP(hipMalloc(&own, need));
+  char* base = static_cast<char*>(ws ? ws : own);
+  std::vector<hipEvent_t> ev((size_t)2 * nprob, nullptr);
+  int rc = SK_OK;
+  for (auto& e : ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      set_error("lstsq_sketch_solve_batched: hipEventCreate failed");
+      rc = SK_E_HIP;
+      break;
+    }
+  }
+  Carver cv0{base, 0};
+  int* ranks = cv0.take<int>((size_t)nprob);
+  const size_t first = cv0.off;
+  for (int i = 0; i < nprob && rc == SK_OK; ++i) {
+    const sk_ls_problem& p = probs[i];
+    const int k = (int)p.k;
+    sk_sketch W;
+    batched_sketch(p, d_per_k, zeta, device, &W);
+    Carver cv{base, first};
+    SolveBufs X;
+    Phases ph(st);
+    if ((rc = batched_bufs(cv, &W, p, &X)) < 0) break;
+    if (hipEventRecord(ev[2 * i], st) != hipSuccess) {
+      rc = SK_E_HIP;
+      break;
+    }
+    if ((rc = sketch_and_factor(&W, k, p.dtype, p.A, p.lda, p.b, X.B, ph, st, p.dtype)) < 0) break;
+    if ((rc = launch_jacobi_svd(X.B.R, k, X.U, X.sv, X.V, X.work, st)) < 0) break;
+    if ((rc = launch_svd_solve(X.U, X.sv, X.V, X.B.c, k, std::ldexp(1.0, -52), p.x, X.z, ranks + i, st)) < 0)
+      break;
+    if (hipEventRecord(ev[2 * i + 1], st) != hipSuccess) {
+      rc = SK_E_HIP;
+      break;
+    }
+  }
+  // everything queued has finished before the events and the workspace go
+  if (hipStreamSynchronize(st) != hipSuccess && rc == SK_OK) {
+    set_error("lstsq_sketch_solve_batched: stream synchronization failed");
+    rc = SK_E_HIP;
+  }
+  bool rankdef = false;
+  if (rc == SK_OK) {
+    std::vector<int> h((size_t)nprob);
+    if (hipMemcpy(h.data(), ranks, sizeof(int) * nprob, hipMemcpyDeviceToHost) != hipSuccess) {
+      set_error("lstsq_sketch_solve_batched: reading the ranks failed");
+      rc = SK_E_HIP;
+    } else {
+      for (int i = 0; i < nprob; ++i) {
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
+        probs[i].rank = h[i];
+        probs[i].t_ms = t;
+        probs[i].status = h[i] < probs[i].k ? SK_W_RANKDEF : SK_OK;
+        rankdef = rankdef || h[i] < probs[i].k;
+      }
+    }
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (own) (void)hipFree(own);
+  if (rc < 0) return rc;
+  return rankdef ? SK_W_RANKDEF : SK_OK;
 }
 
 int lstsq_sketch_precond(sketch_t S, int64_t m, const double* A, int64_t lda, int sketch_dtype, const void* A_sketch,

@@ -113,6 +113,13 @@ def _as_dict(st):
     return {name: getattr(st, name) for name, _ in st._fields_}
 
 
+class LsProblem(ctypes.Structure):
+    """sk_ls_problem (one problem of lstsq_sketch_solve_batched)."""
+    _fields_ = [("n", _i64), ("k", _i64), ("dtype", ctypes.c_int), ("A", _vp), ("lda", _i64), ("b", _vp),
+                ("x", _vp), ("seed", ctypes.c_uint64), ("status", ctypes.c_int), ("rank", ctypes.c_int),
+                ("t_ms", ctypes.c_double)]
+
+
 _DRIVER_SIGS = {
     "lstsq_sketch_solve": [_vp, _i64, _vp, _i64, _vp, _vp, ctypes.POINTER(SolveInfo), _vp],
     "lstsq_sketch_precond": [_vp, _i64, _vp, _i64, ctypes.c_int, _vp, _i64, _vp, _vp, ctypes.c_double, ctypes.c_int,
@@ -125,6 +132,10 @@ _DRIVER_SIGS = {
     "nystrom_psd": [_vp, ctypes.c_int, _vp, _i64, _vp, _i64, _vp, ctypes.POINTER(NystromInfo), _vp],
     "sketch_sv_extremes": [_vp, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ExtremesInfo), _vp],
+    "lstsq_batched_workspace_size": [ctypes.POINTER(LsProblem), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_size_t)],
+    "lstsq_sketch_solve_batched": [ctypes.POINTER(LsProblem), ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
+                                   ctypes.c_size_t, _vp],
 }
 
 
@@ -355,3 +366,33 @@ def nystrom_psd(S, A, stream=None):
     rc = check(load().nystrom_psd(S.h, _DT[A.dtype], _ptr(A), A.stride(0), _ptr(U), k, _ptr(lam), ctypes.byref(info),
                                   _stream(stream)))
     return U, lam, rc, _as_dict(info)
+
+
+def _batched_array(problems):
+    """sk_ls_problem array for [(A, b, seed), ...] (A n x k row-major, b n elements of A's dtype, CUDA)."""
+    arr = (LsProblem * len(problems))()
+    xs = []
+    for i, (A, b, seed) in enumerate(problems):
+        assert A.is_cuda and A.dim() == 2 and A.stride(1) == 1 and A.dtype in _DT
+        assert b.is_cuda and b.dtype == A.dtype and b.numel() == A.shape[0] and b.is_contiguous()
+        x = torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
+        xs.append(x)
+        arr[i] = LsProblem(A.shape[0], A.shape[1], _DT[A.dtype], _ptr(A), A.stride(0), _ptr(b), _ptr(x),
+                           int(seed) & 0xFFFFFFFFFFFFFFFF, 0, 0, 0.0)
+    return arr, xs
+
+
+def batched_workspace_size(problems, d_per_k=4, zeta=4):
+    arr, _ = _batched_array(problems)
+    nbytes = ctypes.c_size_t(0)
+    check(load().lstsq_batched_workspace_size(arr, len(problems), d_per_k, zeta, ctypes.byref(nbytes)))
+    return nbytes.value
+
+
+def solve_batched(problems, d_per_k=4, zeta=4, ws=None, stream=None):
+    """lstsq_sketch_solve_batched over [(A, b, seed), ...]: problem p is sketched by its own SparseStack
+    (d = d_per_k * k, zeta blocks, key seed). Returns (xs, statuses, ranks, t_ms, status of the call)."""
+    arr, xs = _batched_array(problems)
+    wsp, wsb = (None, 0) if ws is None else (_ptr(ws), ws.numel() * ws.element_size())
+    rc = check(load().lstsq_sketch_solve_batched(arr, len(problems), d_per_k, zeta, wsp, wsb, _stream(stream)))
+    return xs, [p.status for p in arr], [p.rank for p in arr], [p.t_ms for p in arr], rc

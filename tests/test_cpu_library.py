@@ -89,3 +89,37 @@ def test_driver_null_handle_fails_cleanly():
     assert lib.nystrom_psd(None, 1, None, 4, None, 4, None, None, None) == libsketch.SK_E_INVAL
     a, b = ctypes.c_double(0), ctypes.c_double(0)
     assert lib.sketch_sv_extremes(None, 10, 0, ctypes.byref(a), ctypes.byref(b), None, None) == libsketch.SK_E_INVAL
+
+
+def test_ls_problem_layout_matches_header(tmp_path):
+    """The binding's sk_ls_problem has the C compiler's field offsets and size."""
+    import shutil
+    import subprocess
+    from paper_2508_21189_amd import libsketch
+    if not shutil.which("gcc"):
+        pytest.skip("no C compiler")
+    fields = [f for f, _ in libsketch.LsProblem._fields_]
+    body = "".join('printf("%%zu ", offsetof(sk_ls_problem, %s));' % f for f in fields)
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "libsketch.h"\n'
+                   'int main(void) { %s printf("%%zu\\n", sizeof(sk_ls_problem)); return 0; }\n' % body)
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [getattr(libsketch.LsProblem, f).offset for f in fields] + [ctypes.sizeof(libsketch.LsProblem)]
+    assert got == want
+
+
+def test_batched_rejects_invalid_problems_before_any_work():
+    from paper_2508_21189_amd import libsketch
+    lib = libsketch.load()
+    assert lib.lstsq_sketch_solve_batched(None, 0, 4, 4, None, 0, None) == libsketch.SK_E_INVAL
+    arr = (libsketch.LsProblem * 2)()
+    for p in arr:  # k = 0 and null pointers: invalid
+        p.n, p.k, p.dtype = 100, 0, 1
+        p.status = 7
+    assert lib.lstsq_sketch_solve_batched(arr, 2, 4, 4, None, 0, None) == libsketch.SK_E_INVAL
+    assert [p.status for p in arr] == [libsketch.SK_E_INVAL] * 2
+    assert "problem 0" in libsketch.last_error()
+    size = ctypes.c_size_t(0)
+    assert lib.lstsq_batched_workspace_size(arr, 2, 4, 4, ctypes.byref(size)) == libsketch.SK_E_INVAL

@@ -1,0 +1,108 @@
+"""GPU parity of the batched sketch-and-solve (lstsq_sketch_solve_batched).
+
+Every problem is solved with its own SparseStack (d = 4k, zeta = 4, its own
+seed) and compared with the oracle's sketch-and-solve (Alg. 3) on the
+oracle's own S A and S b for the same sketch:
+  * float64 problems to 1e-11 relative, as the single-problem driver;
+  * float32 and bfloat16 problems (the sketch accumulates in float32) within
+    the first-order perturbation bound of the small least-squares problem,
+    (||E|| ||x|| + ||e||) / s_min + ||E|| ||r|| / s_min^2 (doubled), where
+    |E| <= (c_j + 8) 2^-24 (|S||A|) and |e| <= (c_j + 8) 2^-24 (|S||b|)
+    bound the sketch's rounding entrywise (the oracle reads the same rounded
+    values);
+  * a rank-deficient problem is reported as such while the others succeed;
+  * a batch is bitwise reproducible, and a caller workspace gives the same
+    results as the internal one.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lstsq as ol
+from oracle import sketches as sk
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2508_21189_amd import libsketch
+    libsketch.load()
+    return libsketch
+
+
+def _problem(n, k, dtype, seed, dependent=False):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, k))
+    if dependent:
+        A[:, k - 1] = 2.0 * A[:, 0]
+    b = A @ rng.standard_normal(k) + 1e-4 * rng.standard_normal(n)
+    At = torch.from_numpy(A).to(dtype).cuda()
+    bt = torch.from_numpy(b).to(dtype).cuda()
+    return At, bt
+
+
+def _oracle(A64, b64, k, seed, u):
+    d = 4 * k
+    SA = sk.sparsestack_apply(A64, d, 4, seed)
+    Sb = sk.sparsestack_apply(b64[:, None], d, 4, seed)[:, 0]
+    x, r, s = ol.sketch_and_solve(SA, Sb)
+    Sabs = abs(sk.sparsestack_csr(A64.shape[0], d, 4, seed))
+    cnt = np.asarray((Sabs != 0).sum(axis=1)).ravel()[:, None]
+    E = np.linalg.norm((cnt + 8.0) * u * (Sabs @ np.abs(A64)))
+    e = np.linalg.norm((cnt[:, 0] + 8.0) * u * (Sabs @ np.abs(b64)))
+    res = np.linalg.norm(SA @ x - Sb)
+    smin = s[r - 1]
+    tol = 2.0 * ((E * np.linalg.norm(x) + e) / smin + E * res / smin ** 2)
+    return x, r, tol
+
+
+CASES = [(3000, 16, torch.float64), (12000, 33, torch.float32), (40001, 64, torch.float32),
+         (5000, 100, torch.bfloat16), (20000, 48, torch.float64), (7000, 20, torch.float32)]
+
+
+def test_batched_matches_oracle(lib):
+    problems = []
+    for i, (n, k, dt) in enumerate(CASES):
+        A, b = _problem(n, k, dt, 10 + i)
+        problems.append((A, b, 1000 + i))
+    xs, status, ranks, t_ms, rc = lib.solve_batched(problems)
+    assert rc == 0 and status == [0] * len(CASES)
+    for (A, b, seed), x, rank, t, (n, k, dt) in zip(problems, xs, ranks, t_ms, CASES):
+        A64 = A.to(torch.float64).cpu().numpy()
+        b64 = b.to(torch.float64).cpu().numpy()
+        xg = x.cpu().numpy()
+        if dt == torch.float64:
+            xr, r, _ = _oracle(A64, b64, k, seed, 2.0 ** -53)
+            assert np.linalg.norm(xg - xr) <= 1e-11 * np.linalg.norm(xr)
+        else:
+            xr, r, tol = _oracle(A64, b64, k, seed, 2.0 ** -24)
+            assert np.linalg.norm(xg - xr) <= tol
+        assert rank == r == k and t > 0.0
+
+
+def test_batched_rank_deficient_problem(lib):
+    problems = [(*_problem(4000, 12, torch.float64, 1), 5), (*_problem(4000, 12, torch.float64, 2, True), 6)]
+    xs, status, ranks, t_ms, rc = lib.solve_batched(problems)
+    assert rc == lib.SK_W_RANKDEF
+    assert status == [0, lib.SK_W_RANKDEF] and ranks == [12, 11]
+    A64 = problems[1][0].cpu().numpy()
+    b64 = problems[1][1].cpu().numpy()
+    xr, r, _ = _oracle(A64, b64, 12, 6, 2.0 ** -53)
+    assert r == 11 and np.linalg.norm(xs[1].cpu().numpy() - xr) <= 1e-9 * np.linalg.norm(xr)
+
+
+def test_batched_reproducible_and_caller_workspace(lib):
+    problems = []
+    for i, (n, k, dt) in enumerate(CASES[:4]):
+        A, b = _problem(n, k, dt, 40 + i)
+        problems.append((A, b, 77 + i))
+    x1 = lib.solve_batched(problems)[0]
+    x2 = lib.solve_batched(problems)[0]
+    ws = torch.empty(lib.batched_workspace_size(problems), dtype=torch.uint8, device="cuda")
+    x3 = lib.solve_batched(problems, ws=ws)[0]
+    for a, b, c in zip(x1, x2, x3):
+        assert torch.equal(a, b) and torch.equal(a, c)
+    with pytest.raises(lib.SketchError):
+        lib.solve_batched(problems, ws=ws[:16])
