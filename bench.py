@@ -20,7 +20,14 @@ The JSON line also carries
   lsqr_mixed    the same on the 8388608 x 500, kappa = 1e10 system, where the
                 float32 / bfloat16 sketch copies pay off;
   rsvd          Alg. 1 on a 65536 x 16384 float32 matrix with known spectrum
-                (k = 512) for the three sketch kinds, with the spectral error;
+                (k = 512) for the four sketch kinds, with the spectral error;
+  gen_nystrom,  generalized Nystrom (outer and SVD forms) and psd Nystrom,
+  nystrom       SparseStack against Gaussian;
+  batched       512 independent float32 least-squares problems solved by
+                lstsq_sketch_solve_batched: problems per second and the
+                p50 / p99 per-problem device time;
+  injectivity   the injectivity / dilation sweep of Fig. 2;
+  stream_read_ref  a plain streaming read of A in the same run;
   cpu_baseline  the plain CPU oracle timed on a bounded row sample of the
                 same matrix on this host.
 """
@@ -291,6 +298,57 @@ def nystrom_variants(libsketch, inputs, torch, reps):
     return out
 
 
+def batched_solves(libsketch, torch, reps, nprob=512):
+    """Many independent least-squares problems (lstsq_sketch_solve_batched):
+    n log-uniform in [1e4, 1e6], k uniform in [16, 256], float32 N(0,1)
+    entries, b = A x_planted + 1e-4 noise, each problem with its own
+    SparseStack (d = 4k, zeta = 4, its own seed). Reports problems per second
+    over the whole batch (wall clock, one call, caller workspace) and the
+    p50 / p99 of the per-problem device times."""
+    import numpy as np
+    import statistics
+    rng = np.random.default_rng(DATA_SEED + 5)
+    ns = np.exp(rng.uniform(np.log(1e4), np.log(1e6), nprob)).astype(np.int64)
+    ks = rng.integers(16, 257, nprob)
+    print("bench: generating %d least-squares problems (%.1f GB float32)" % (nprob, float((ns * ks).sum()) * 4e-9),
+          file=sys.stderr, flush=True)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(DATA_SEED + 5)
+    problems, planted = [], []
+    for i in range(nprob):
+        n, k = int(ns[i]), int(ks[i])
+        A = torch.randn((n, k), generator=g, dtype=torch.float32, device="cuda")
+        x = torch.randn(k, generator=g, dtype=torch.float32, device="cuda")
+        b = A @ x + 1e-4 * torch.randn(n, generator=g, dtype=torch.float32, device="cuda")
+        problems.append((A, b, SKETCH_SEED + 1000 + i))
+        planted.append(x.double())
+    ws = torch.empty(libsketch.batched_workspace_size(problems), dtype=torch.uint8, device="cuda")
+    libsketch.solve_batched(problems[:8], ws=ws)  # warm-up (code objects)
+    walls, lat = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs, status, ranks, t_ms, rc = libsketch.solve_batched(problems, ws=ws)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        lat = t_ms
+    err = [float((x - xp).norm() / xp.norm()) for x, xp in zip(xs, planted)]
+    lat_sorted = sorted(lat)
+    wall = statistics.median(walls)
+    out = {"workload": "%d problems, n log-uniform [1e4, 1e6], k uniform [16, 256], f32 N(0,1), d=4k, zeta=4"
+           % nprob, "total_gb": round(float((ns * ks).sum()) * 4e-9, 2), "wall_s": round(wall, 4),
+           "problems_per_s": round(nprob / wall, 1),
+           "p50_ms": round(lat_sorted[len(lat) // 2], 4), "p99_ms": round(lat_sorted[min(len(lat) - 1,
+                                                                                          int(0.99 * len(lat)))], 4),
+           "status": rc, "all_full_rank": all(r == int(k) for r, k in zip(ranks, ks)),
+           "median_rel_err_vs_planted": statistics.median(err)}
+    print("bench: batched %d problems %.3f s (%.0f problems/s), p50 %.3f ms, p99 %.3f ms" %
+          (nprob, wall, out["problems_per_s"], out["p50_ms"], out["p99_ms"]), file=sys.stderr, flush=True)
+    del problems, planted, ws, xs
+    torch.cuda.empty_cache()
+    return out
+
+
 def injectivity_sweep(libsketch, torch, trials, trials_1e7, steps):
     """Fig. 2: injectivity alpha and dilation beta of SparseStack on the
     coordinate basis Q = [e_1 ... e_r], k = 2r, r = 10^2 .. 10^7, zeta in
@@ -337,6 +395,8 @@ def main():
     ap.add_argument("--gn-reps", type=int, default=1,
                     help="timed generalized Nystrom calls per sketch kind and form (0 = skip)")
     ap.add_argument("--nystrom-reps", type=int, default=1, help="timed Nystrom calls per sketch kind (0 = skip)")
+    ap.add_argument("--batched-reps", type=int, default=2,
+                    help="timed runs of the 512-problem batched least-squares leg (0 = skip)")
     ap.add_argument("--inj-trials", type=int, default=10,
                     help="trials per point of the injectivity sweep for r <= 1e6 (0 = skip the sweep)")
     ap.add_argument("--inj-trials-1e7", type=int, default=3, help="trials per point at r = 1e7")
@@ -433,6 +493,8 @@ def main():
         rec["gen_nystrom"] = gn_variants(libsketch, inputs, torch, args.gn_reps)
     if args.nystrom_reps > 0:
         rec["nystrom"] = nystrom_variants(libsketch, inputs, torch, args.nystrom_reps)
+    if args.batched_reps > 0:
+        rec["batched"] = batched_solves(libsketch, torch, args.batched_reps)
     if args.inj_trials > 0:
         rec["injectivity"] = injectivity_sweep(libsketch, torch, args.inj_trials, max(1, args.inj_trials_1e7),
                                                args.inj_steps)

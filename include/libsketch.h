@@ -284,10 +284,15 @@ typedef struct {
  * in one call: problem p is solved with its own SparseStack sketch of
  * d = d_per_k * k rows in zeta blocks (zeta must divide d) under key p.seed,
  * reading A and b in their own precision (F32 and BF16 accumulate the sketch
- * in F32; QR, SVD and the solve are F64). The problems are queued back to
+ * in F32; QR, SVD and the solve are F64). After the Householder QR
+ * S [A b] = Q [R c; 0 *], a problem whose ||R||_F ||R^-1||_F < 1e-3 / (5 eps)
+ * certainly passes the rank test of Alg. 3 (s_k > 5 eps s_1), and its
+ * truncated-SVD solution is x = R^-1 c, computed directly; the others are
+ * redone with the SVD of R in a second pass, exactly as lstsq_sketch_solve
+ * does. The problems are queued back to
  * back on `stream`, sharing one workspace (ws, ws_bytes >=
  * lstsq_batched_workspace_size; NULL to allocate and free one inside the
- * call); the call synchronizes once at the end. Every problem is validated
+ * call); the call synchronizes once per pass. Every problem is validated
  * before any work is queued: if one is invalid, its status is SK_E_INVAL,
  * nothing runs, and SK_E_INVAL is returned. Otherwise returns SK_OK, or
  * SK_W_RANKDEF if some problem was rank deficient (see its status).

@@ -343,48 +343,72 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
   Carver cv0{base, 0};
   int* ranks = cv0.take<int>((size_t)nprob);
   const size_t first = cv0.off;
-  for (int i = 0; i < nprob && rc == SK_OK; ++i) {
-    const sk_ls_problem& p = probs[i];
-    const int k = (int)p.k;
-    sk_sketch W;
-    batched_sketch(p, d_per_k, zeta, device, &W);
-    Carver cv{base, first};
-    SolveBufs X;
-    Phases ph(st);
-    if ((rc = batched_bufs(cv, &W, p, &X)) < 0) break;
-    if (hipEventRecord(ev[2 * i], st) != hipSuccess) {
-      rc = SK_E_HIP;
-      break;
+  const double eps = std::ldexp(1.0, -52);
+  // Pass 1: sketch, Householder QR and, where the rank test of Alg. 3 is
+  // certain to pass, x = R^-1 c. Pass 2 redoes the problems it could not
+  // certify with the SVD of R (the same steps as lstsq_sketch_solve).
+  std::vector<int> h((size_t)nprob, 0);
+  std::vector<char> redo((size_t)nprob, 0);
+  std::vector<double> t_ms((size_t)nprob, 0.0);
+  for (int pass = 0; pass < 2 && rc == SK_OK; ++pass) {
+    bool queued = false;
+    for (int i = 0; i < nprob && rc == SK_OK; ++i) {
+      if (pass == 1 && !redo[i]) continue;
+      const sk_ls_problem& p = probs[i];
+      const int k = (int)p.k;
+      sk_sketch W;
+      batched_sketch(p, d_per_k, zeta, device, &W);
+      Carver cv{base, first};
+      SolveBufs X;
+      Phases ph(st);
+      if ((rc = batched_bufs(cv, &W, p, &X)) < 0) break;
+      if (hipEventRecord(ev[2 * i], st) != hipSuccess) {
+        rc = SK_E_HIP;
+        break;
+      }
+      if ((rc = sketch_and_factor(&W, k, p.dtype, p.A, p.lda, p.b, X.B, ph, st, p.dtype)) < 0) break;
+      if (pass == 0) {
+        // U and V hold R^-1 and its transpose here
+        if ((rc = launch_trinv(X.B.R, k, X.U, X.V, st)) < 0) break;
+        if ((rc = launch_certified_tri_solve(X.B.R, X.U, X.B.c, k, eps, p.x, ranks + i, st)) < 0) break;
+      } else {
+        if ((rc = launch_jacobi_svd(X.B.R, k, X.U, X.sv, X.V, X.work, st)) < 0) break;
+        if ((rc = launch_svd_solve(X.U, X.sv, X.V, X.B.c, k, eps, p.x, X.z, ranks + i, st)) < 0) break;
+      }
+      if (hipEventRecord(ev[2 * i + 1], st) != hipSuccess) {
+        rc = SK_E_HIP;
+        break;
+      }
+      queued = true;
     }
-    if ((rc = sketch_and_factor(&W, k, p.dtype, p.A, p.lda, p.b, X.B, ph, st, p.dtype)) < 0) break;
-    if ((rc = launch_jacobi_svd(X.B.R, k, X.U, X.sv, X.V, X.work, st)) < 0) break;
-    if ((rc = launch_svd_solve(X.U, X.sv, X.V, X.B.c, k, std::ldexp(1.0, -52), p.x, X.z, ranks + i, st)) < 0)
-      break;
-    if (hipEventRecord(ev[2 * i + 1], st) != hipSuccess) {
+    // everything queued has finished before the ranks are read and before the
+    // events and the workspace go
+    if (hipStreamSynchronize(st) != hipSuccess && rc == SK_OK) {
+      set_error("lstsq_sketch_solve_batched: stream synchronization failed");
       rc = SK_E_HIP;
-      break;
     }
-  }
-  // everything queued has finished before the events and the workspace go
-  if (hipStreamSynchronize(st) != hipSuccess && rc == SK_OK) {
-    set_error("lstsq_sketch_solve_batched: stream synchronization failed");
-    rc = SK_E_HIP;
-  }
-  bool rankdef = false;
-  if (rc == SK_OK) {
-    std::vector<int> h((size_t)nprob);
+    if (rc != SK_OK || !queued) break;
     if (hipMemcpy(h.data(), ranks, sizeof(int) * nprob, hipMemcpyDeviceToHost) != hipSuccess) {
       set_error("lstsq_sketch_solve_batched: reading the ranks failed");
       rc = SK_E_HIP;
-    } else {
-      for (int i = 0; i < nprob; ++i) {
+      break;
+    }
+    for (int i = 0; i < nprob; ++i) {
+      if (pass == 0 || redo[i]) {
         float t = 0.f;
         (void)hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
-        probs[i].rank = h[i];
-        probs[i].t_ms = t;
-        probs[i].status = h[i] < probs[i].k ? SK_W_RANKDEF : SK_OK;
-        rankdef = rankdef || h[i] < probs[i].k;
+        t_ms[i] += t;
       }
+      redo[i] = h[i] < 0;
+      probs[i].rank = h[i];
+    }
+  }
+  bool rankdef = false;
+  if (rc == SK_OK) {
+    for (int i = 0; i < nprob; ++i) {
+      probs[i].t_ms = t_ms[i];
+      probs[i].status = h[i] < probs[i].k ? SK_W_RANKDEF : SK_OK;
+      rankdef = rankdef || h[i] < probs[i].k;
     }
   }
   for (auto& e : ev)

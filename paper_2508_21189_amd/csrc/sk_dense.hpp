@@ -21,6 +21,11 @@ int launch_trinv(const double* R, int k, double* X, double* XT, hipStream_t st);
 int launch_jacobi_svd(const double* R, int k, double* U, double* s, double* V, double* work, hipStream_t st);
 // x = V_r diag(s_r)^{-1} U_r^T c with r = #{s_i > 5 eps s_1} (written to
 // *rank_out, device). z: k doubles of scratch.
+// Alg. 3's solve when its rank test certainly passes: *rank_out = k and
+// x = X c if ||R||_F ||X||_F < 1e-3 / (5 eps) (R upper triangular, X = R^-1,
+// both k x k row-major), else *rank_out = -1 and x untouched.
+int launch_certified_tri_solve(const double* R, const double* X, const double* c, int k, double eps, double* x,
+                               int* rank_out, hipStream_t st);
 int launch_svd_solve(const double* U, const double* s, const double* V, const double* c, int k, double eps, double* x,
                      double* z, int* rank_out, hipStream_t st);
 // x[0:n) = value

@@ -10,7 +10,9 @@ oracle's own S A and S b for the same sketch:
     |E| <= (c_j + 8) 2^-24 (|S||A|) and |e| <= (c_j + 8) 2^-24 (|S||b|)
     bound the sketch's rounding entrywise (the oracle reads the same rounded
     values);
-  * a rank-deficient problem is reported as such while the others succeed;
+  * a rank-deficient problem (which the full-rank certificate cannot pass, so
+    it is redone with the SVD of R) is reported as such, with the oracle's
+    truncated solution, while the others succeed;
   * a batch is bitwise reproducible, and a caller workspace gives the same
     results as the internal one.
 """
