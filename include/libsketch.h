@@ -289,10 +289,12 @@ typedef struct {
  * certainly passes the rank test of Alg. 3 (s_k > 5 eps s_1), and its
  * truncated-SVD solution is x = R^-1 c, computed directly; the others are
  * redone with the SVD of R in a second pass, exactly as lstsq_sketch_solve
- * does. The problems are queued back to
- * back on `stream`, sharing one workspace (ws, ws_bytes >=
- * lstsq_batched_workspace_size; NULL to allocate and free one inside the
- * call); the call synchronizes once per pass. Every problem is validated
+ * does. The problems are spread round-robin over up to four streams that
+ * the call creates (default priority) and that start after the work already
+ * queued on `stream`; each stream runs its problems back to back in its own
+ * slot of one workspace (ws, ws_bytes >= lstsq_batched_workspace_size; NULL
+ * to allocate and free one inside the call). The call waits for all of them
+ * once per pass and returns with every x written. Every problem is validated
  * before any work is queued: if one is invalid, its status is SK_E_INVAL,
  * nothing runs, and SK_E_INVAL is returned. Otherwise returns SK_OK, or
  * SK_W_RANKDEF if some problem was rank deficient (see its status).

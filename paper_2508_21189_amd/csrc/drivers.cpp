@@ -192,20 +192,31 @@ int batched_bufs(Carver& cv, const sk_sketch* W, const sk_ls_problem& p, SolveBu
   return SK_OK;
 }
 
-// Workspace layout: the rank of every problem (nprob ints), then the buffers
-// of one problem, reused by each in turn (the problems run in stream order).
-int batched_bytes(const sk_ls_problem* probs, int nprob, int d_per_k, int zeta, int device, size_t* bytes) {
+// Problems run on up to this many streams of their own, so that the
+// one-workgroup kernels of different problems (QR panels, small solves)
+// overlap; four matches the hardware queues HIP gives a process by default.
+constexpr int kBatchStreams = 4;
+int batch_streams(int nprob) { return std::min(nprob, kBatchStreams); }
+
+// Workspace layout: the rank of every problem (nprob ints), then one slot per
+// stream holding the buffers of one problem, reused by the problems of that
+// stream in turn (they run in stream order).
+struct BatchLayout {
+  size_t ranks_bytes, slot_bytes, total;
+};
+int batched_layout(const sk_ls_problem* probs, int nprob, int d_per_k, int zeta, int device, BatchLayout* L) {
   size_t mx = 0;
   for (int i = 0; i < nprob; ++i) {
     sk_sketch W;
     batched_sketch(probs[i], d_per_k, zeta, device, &W);
     Carver cv;
-    cv.take<int>((size_t)nprob);
     SolveBufs X;
     SK_TRY(batched_bufs(cv, &W, probs[i], &X));
     mx = std::max(mx, cv.off);
   }
-  *bytes = mx;
+  L->ranks_bytes = ((size_t)nprob * sizeof(int) + 255) & ~(size_t)255;
+  L->slot_bytes = (mx + 255) & ~(size_t)255;
+  L->total = L->ranks_bytes + (size_t)batch_streams(nprob) * L->slot_bytes;
   return SK_OK;
 }
 
@@ -306,7 +317,10 @@ int lstsq_batched_workspace_size(const sk_ls_problem* probs, int nprob, int d_pe
   SK_TRY(batched_check(probs, nprob, d_per_k, zeta, "lstsq_batched_workspace_size"));
   int device = 0;
   SK_HIP(hipGetDevice(&device));
-  return batched_bytes(probs, nprob, d_per_k, zeta, device, bytes);
+  BatchLayout L;
+  SK_TRY(batched_layout(probs, nprob, d_per_k, zeta, device, &L));
+  *bytes = L.total;
+  return SK_OK;
 }
 
 int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int zeta, void* ws, size_t ws_bytes,
@@ -321,8 +335,9 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
   SK_TRY(batched_check(probs, nprob, d_per_k, zeta, "lstsq_sketch_solve_batched"));
   int device = 0;
   SK_HIP(hipGetDevice(&device));
-  size_t need = 0;
-  SK_TRY(batched_bytes(probs, nprob, d_per_k, zeta, device, &need));
+  BatchLayout L;
+  SK_TRY(batched_layout(probs, nprob, d_per_k, zeta, device, &L));
+  const size_t need = L.total;
   if (ws && ws_bytes < need) {
     set_error("lstsq_sketch_solve_batched: workspace too small (see lstsq_batched_workspace_size)");
     return SK_E_INVAL;
@@ -332,6 +347,9 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
   if (!ws) SK_HIP(hipMalloc(&own, need));
   char* base = static_cast<char*>(ws ? ws : own);
   std::vector<hipEvent_t> ev((size_t)2 * nprob, nullptr);
+  const int NS = batch_streams(nprob);
+  std::vector<hipStream_t> ss((size_t)NS, nullptr);
+  hipEvent_t ready = nullptr;
   int rc = SK_OK;
   for (auto& e : ev) {
     if (hipEventCreate(&e) != hipSuccess) {
@@ -340,9 +358,20 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
       break;
     }
   }
-  Carver cv0{base, 0};
-  int* ranks = cv0.take<int>((size_t)nprob);
-  const size_t first = cv0.off;
+  // the problems' streams start after the work already queued on `stream`
+  if (rc == SK_OK && (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
+                      hipEventRecord(ready, st) != hipSuccess)) {
+    set_error("lstsq_sketch_solve_batched: event on the caller's stream failed");
+    rc = SK_E_HIP;
+  }
+  for (int j = 0; j < NS && rc == SK_OK; ++j) {
+    if (hipStreamCreateWithFlags(&ss[j], hipStreamNonBlocking) != hipSuccess ||
+        hipStreamWaitEvent(ss[j], ready, 0) != hipSuccess) {
+      set_error("lstsq_sketch_solve_batched: stream creation failed");
+      rc = SK_E_HIP;
+    }
+  }
+  int* ranks = reinterpret_cast<int*>(base);
   const double eps = std::ldexp(1.0, -52);
   // Pass 1: sketch, Householder QR and, where the rank test of Alg. 3 is
   // certain to pass, x = R^-1 c. Pass 2 redoes the problems it could not
@@ -356,36 +385,40 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
       if (pass == 1 && !redo[i]) continue;
       const sk_ls_problem& p = probs[i];
       const int k = (int)p.k;
+      const int slot = i % NS;
+      hipStream_t ps = ss[slot];
       sk_sketch W;
       batched_sketch(p, d_per_k, zeta, device, &W);
-      Carver cv{base, first};
+      Carver cv{base, L.ranks_bytes + (size_t)slot * L.slot_bytes};
       SolveBufs X;
-      Phases ph(st);
+      Phases ph(ps);
       if ((rc = batched_bufs(cv, &W, p, &X)) < 0) break;
-      if (hipEventRecord(ev[2 * i], st) != hipSuccess) {
+      if (hipEventRecord(ev[2 * i], ps) != hipSuccess) {
         rc = SK_E_HIP;
         break;
       }
-      if ((rc = sketch_and_factor(&W, k, p.dtype, p.A, p.lda, p.b, X.B, ph, st, p.dtype)) < 0) break;
+      if ((rc = sketch_and_factor(&W, k, p.dtype, p.A, p.lda, p.b, X.B, ph, ps, p.dtype)) < 0) break;
       if (pass == 0) {
         // U and V hold R^-1 and its transpose here
-        if ((rc = launch_trinv(X.B.R, k, X.U, X.V, st)) < 0) break;
-        if ((rc = launch_certified_tri_solve(X.B.R, X.U, X.B.c, k, eps, p.x, ranks + i, st)) < 0) break;
+        if ((rc = launch_trinv(X.B.R, k, X.U, X.V, ps)) < 0) break;
+        if ((rc = launch_certified_tri_solve(X.B.R, X.U, X.B.c, k, eps, p.x, ranks + i, ps)) < 0) break;
       } else {
-        if ((rc = launch_jacobi_svd(X.B.R, k, X.U, X.sv, X.V, X.work, st)) < 0) break;
-        if ((rc = launch_svd_solve(X.U, X.sv, X.V, X.B.c, k, eps, p.x, X.z, ranks + i, st)) < 0) break;
+        if ((rc = launch_jacobi_svd(X.B.R, k, X.U, X.sv, X.V, X.work, ps)) < 0) break;
+        if ((rc = launch_svd_solve(X.U, X.sv, X.V, X.B.c, k, eps, p.x, X.z, ranks + i, ps)) < 0) break;
       }
-      if (hipEventRecord(ev[2 * i + 1], st) != hipSuccess) {
+      if (hipEventRecord(ev[2 * i + 1], ps) != hipSuccess) {
         rc = SK_E_HIP;
         break;
       }
       queued = true;
     }
     // everything queued has finished before the ranks are read and before the
-    // events and the workspace go
-    if (hipStreamSynchronize(st) != hipSuccess && rc == SK_OK) {
-      set_error("lstsq_sketch_solve_batched: stream synchronization failed");
-      rc = SK_E_HIP;
+    // events, the streams and the workspace go
+    for (int j = 0; j < NS; ++j) {
+      if (ss[j] && hipStreamSynchronize(ss[j]) != hipSuccess && rc == SK_OK) {
+        set_error("lstsq_sketch_solve_batched: stream synchronization failed");
+        rc = SK_E_HIP;
+      }
     }
     if (rc != SK_OK || !queued) break;
     if (hipMemcpy(h.data(), ranks, sizeof(int) * nprob, hipMemcpyDeviceToHost) != hipSuccess) {
@@ -411,8 +444,13 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
       rankdef = rankdef || h[i] < probs[i].k;
     }
   }
+  for (int j = 0; j < NS; ++j)
+    if (ss[j]) (void)hipStreamSynchronize(ss[j]);
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
+  if (ready) (void)hipEventDestroy(ready);
+  for (auto& s2 : ss)
+    if (s2) (void)hipStreamDestroy(s2);
   if (own) (void)hipFree(own);
   if (rc < 0) return rc;
   return rankdef ? SK_W_RANKDEF : SK_OK;
