@@ -90,6 +90,9 @@ def test_apply_T_column_major(lib, kind, dtype, rows, n, d, zeta):
     got = S.apply_T(A, out_dtype=odt)
     want = S.apply(At, out_dtype=odt).t()
     assert torch.equal(got, want)
+    # a caller workspace of exactly the queried size (op 3) gives the same result
+    ws = torch.empty(S.workspace_size(3, dtype, rows), dtype=torch.uint8, device="cuda")
+    assert torch.equal(S.apply_T(A, out_dtype=odt, ws=ws), got)
     if kind == "sparsestack":
         A64 = A.to(torch.float64).cpu().numpy()
         ref = sk.sparsestack_apply_T(A64, d, zeta, 5)
@@ -107,6 +110,8 @@ def test_apply_T_large_blocks(lib, dtype, rows, n, d, zeta):
     S = lib.Sketch("sparsestack", d, n, zeta, 8)
     got = S.apply_T(A, out_dtype=torch.float64)
     assert torch.equal(got, S.apply_T(A.t().contiguous().t(), out_dtype=torch.float64))
+    ws = torch.empty(S.workspace_size(1, dtype, rows), dtype=torch.uint8, device="cuda")
+    assert torch.equal(S.apply_T(A, out_dtype=torch.float64, ws=ws), got)
     A64 = A.to(torch.float64).cpu().numpy()
     ref = sk.sparsestack_apply_T(A64, d, zeta, 8)
     u = 2.0 ** -53 if dtype == torch.float64 else 2.0 ** -24
