@@ -86,8 +86,9 @@ def cpu_baseline(A_dev, rows):
                       "median of 3 runs, %.2f s each" % (rows, N, t)}
 
 
-def _solve_stats(libsketch, torch, S, A, b, reps, tol, As=None):
-    """Median wall time (and its split) of reps sketch-and-precondition solves."""
+def _solve_stats(libsketch, torch, S, A, b, reps, tol, As=None, keep_x=None):
+    """Median wall time (and its split) of reps sketch-and-precondition solves
+    (the last solution goes to keep_x[0] when a list is given)."""
     import statistics
     S.lstsq_precond(A, b, tol=tol, maxit=300, A_sketch=As)  # warm-up (workspace, code objects)
     walls, infos = [], []
@@ -101,6 +102,8 @@ def _solve_stats(libsketch, torch, S, A, b, reps, tol, As=None):
     res = S.residual(A, b, x)
     it = infos[-1]
     med = lambda key: round(statistics.median(i[key] for i in infos), 3)
+    if keep_x is not None:
+        keep_x.append(x)
     return {"solve_ms": round(statistics.median(walls), 3), "status": rc, "iters": it["iters"],
             "converged": it["converged"], "t_sketch_ms": med("t_sketch_ms"), "t_qr_ms": med("t_qr_ms"),
             "t_lsqr_ms": med("t_lsqr_ms"),
@@ -148,15 +151,30 @@ def lsqr_mixed(libsketch, inputs, torch, reps, tol=1e-10):
     A, b, _ = inputs.scaled_gaussian(n3, m3, exponent=10.0, seed=DATA_SEED + 1)
     out = {"workload": "A %dx%d f64 iid N(0,1), kappa(D)=1e10; SparseStack d=%d zeta=8" % (n3, m3, d3)}
     S = libsketch.Sketch("sparsestack", d3, n3, 8, SKETCH_SEED + 1)
+    SA64 = S.apply(A)
+    nb = float(b.norm())
+    x64 = None
     for name, dt in (("f64", None), ("f32", torch.float32), ("bf16", torch.bfloat16)):
         As = A.to(dt) if dt is not None else None
-        out[name] = _solve_stats(libsketch, torch, S, A, b, reps, tol, As)
+        xs = []
+        out[name] = _solve_stats(libsketch, torch, S, A, b, reps, tol, As, keep_x=xs)
+        if dt is None:
+            x64 = xs[0]
+        else:
+            # reported, not gated: how far the low-precision sketch (rounded
+            # input and float32 accumulation) is from the float64 sketch, and
+            # how far the solution lands from the float64-sketch solution
+            SAlo = S.apply(As, out_dtype=torch.float64)
+            out[name]["sketch_rel_diff_vs_f64"] = float((SAlo - SA64).norm() / SA64.norm())
+            out[name]["A_x_diff_vs_f64_sketch_rel_b"] = float((A @ (xs[0] - x64)).norm()) / nb
+            out[name]["x_diff_vs_f64_sketch_rel"] = float((xs[0] - x64).norm() / x64.norm())
+            del SAlo
         print("bench: mixed %s %.2f ms, %d iterations" % (name, out[name]["solve_ms"], out[name]["iters"]),
               file=sys.stderr, flush=True)
         del As
         torch.cuda.empty_cache()
     out["speedup_vs_f64"] = {k: round(out["f64"]["solve_ms"] / out[k]["solve_ms"], 3) for k in ("f32", "bf16")}
-    del A, b, S
+    del A, b, S, SA64, x64
     torch.cuda.empty_cache()
     return out
 
