@@ -289,7 +289,7 @@ typedef struct {
  * certainly passes the rank test of Alg. 3 (s_k > 5 eps s_1), and its
  * truncated-SVD solution is x = R^-1 c, computed directly; the others are
  * redone with the SVD of R in a second pass, exactly as lstsq_sketch_solve
- * does. The problems are spread round-robin over up to eight streams that
+ * does. The problems are spread round-robin over up to 32 streams that
  * the call creates (default priority) and that start after the work already
  * queued on `stream`; each stream runs its problems back to back in its own
  * slot of one workspace (ws, ws_bytes >= lstsq_batched_workspace_size; NULL

@@ -195,14 +195,15 @@ int batched_bufs(Carver& cv, const sk_sketch* W, const sk_ls_problem& p, SolveBu
 
 // Problems run on up to this many streams of their own, so that the
 // one-workgroup kernels of different problems (QR panels, small solves)
-// overlap. Eight measured best for 512 problems of k = 16..256 (two and four
-// streams gave the same rate, 0.77 times that of eight).
-// SKETCH_BATCH_STREAMS (1 .. 16) overrides.
+// overlap. For 512 problems of k = 16..256 the rate rises with the stream
+// count up to the 32 streams taken here (relative to 32: 16 streams 0.92,
+// 8 streams 0.79, two or four 0.61).
+// SKETCH_BATCH_STREAMS (1 .. 32) overrides.
 int batch_streams(int nprob) {
   static const int ns = [] {
     const char* v = std::getenv("SKETCH_BATCH_STREAMS");
-    const int n = v ? std::atoi(v) : 8;
-    return std::max(1, std::min(16, n));
+    const int n = v ? std::atoi(v) : 32;
+    return std::max(1, std::min(32, n));
   }();
   return std::min(nprob, ns);
 }
