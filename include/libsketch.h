@@ -274,7 +274,8 @@ typedef struct {
   const void* b;   /* device, n elements */
   double* x;       /* device, k doubles (output) */
   uint64_t seed;   /* seed of this problem's SparseStack sketch */
-  int status;      /* output: SK_OK, SK_W_RANKDEF, or SK_E_INVAL for an invalid problem */
+  int status;      /* output: SK_OK, SK_W_RANKDEF, SK_E_INVAL for an invalid problem, or
+                      SK_E_NOTSUP for data the apply does not take (sketch_apply's rules) */
   int rank;        /* output: the numerical rank r of S A */
   double t_ms;     /* output: device time of this problem (its first to its last kernel) */
 } sk_ls_problem;
@@ -296,7 +297,9 @@ typedef struct {
  * to allocate and free one inside the call). The call waits for all of them
  * once per pass and returns with every x written. Every problem is validated
  * before any work is queued: if one is invalid, its status is SK_E_INVAL,
- * nothing runs, and SK_E_INVAL is returned. Otherwise returns SK_OK, or
+ * nothing runs, and SK_E_INVAL is returned; if the apply refuses one's data
+ * layout (more than 4 columns whose rows are not 4-byte multiples, as BF16
+ * with odd k), its status and the result are SK_E_NOTSUP and nothing runs. Otherwise returns SK_OK, or
  * SK_W_RANKDEF if some problem was rank deficient (see its status).
  */
 int lstsq_batched_workspace_size(const sk_ls_problem* probs, int nprob, int d_per_k, int zeta, size_t* bytes);

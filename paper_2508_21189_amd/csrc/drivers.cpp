@@ -214,14 +214,20 @@ int batch_streams(int nprob) {
 struct BatchLayout {
   size_t ranks_bytes, slot_bytes, total;
 };
-int batched_layout(const sk_ls_problem* probs, int nprob, int d_per_k, int zeta, int device, BatchLayout* L) {
+// On failure *bad is the problem the apply refused (its data layout).
+int batched_layout(const sk_ls_problem* probs, int nprob, int d_per_k, int zeta, int device, BatchLayout* L,
+                   int* bad = nullptr) {
   size_t mx = 0;
   for (int i = 0; i < nprob; ++i) {
     sk_sketch W;
     batched_sketch(probs[i], d_per_k, zeta, device, &W);
     Carver cv;
     SolveBufs X;
-    SK_TRY(batched_bufs(cv, &W, probs[i], &X));
+    const int rc = batched_bufs(cv, &W, probs[i], &X);
+    if (rc < 0) {
+      if (bad) *bad = i;
+      return rc;
+    }
     mx = std::max(mx, cv.off);
   }
   L->ranks_bytes = ((size_t)nprob * sizeof(int) + 255) & ~(size_t)255;
@@ -346,7 +352,12 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
   int device = 0;
   SK_HIP(hipGetDevice(&device));
   BatchLayout L;
-  SK_TRY(batched_layout(probs, nprob, d_per_k, zeta, device, &L));
+  int bad = -1;
+  const int lrc = batched_layout(probs, nprob, d_per_k, zeta, device, &L, &bad);
+  if (lrc < 0) {
+    if (bad >= 0) probs[bad].status = lrc;
+    return lrc;
+  }
   const size_t need = L.total;
   if (ws && ws_bytes < need) {
     set_error("lstsq_sketch_solve_batched: workspace too small (see lstsq_batched_workspace_size)");

@@ -108,3 +108,19 @@ def test_batched_reproducible_and_caller_workspace(lib):
         assert torch.equal(a, b) and torch.equal(a, c)
     with pytest.raises(lib.SketchError):
         lib.solve_batched(problems, ws=ws[:16])
+
+
+def test_batched_refuses_unsupported_layout_before_any_work(lib):
+    """BF16 data with an odd number of columns (> 4) has rows that are not 4-byte
+    multiples, which the apply does not take: that problem's status and the
+    call's result are SK_E_NOTSUP, and no solution is written."""
+    good = _problem(3000, 16, torch.float32, 1)
+    odd = _problem(3000, 17, torch.bfloat16, 2)
+    arr, xs = lib._batched_array([(*good, 1), (*odd, 2)])
+    for x in xs:
+        x.fill_(7.0)
+    rc = lib.load().lstsq_sketch_solve_batched(arr, 2, 4, 4, None, 0, None)
+    assert rc == lib.SK_E_NOTSUP
+    assert [p.status for p in arr] == [0, lib.SK_E_NOTSUP]
+    torch.cuda.synchronize()
+    assert all(bool((x == 7.0).all()) for x in xs)
