@@ -207,3 +207,6 @@ def test_apply_column_major_equals_row_major(lib, kind, dtype, n, m, d, zeta):
     Ap = pad[:, :n].t()  # column-major with lda = n + 7
     assert Ap.stride() == (1, n + 7)
     assert torch.equal(S.apply(Ap), ref)
+    # a caller workspace of exactly the queried size (op 2) gives the same result
+    ws = torch.empty(S.workspace_size(2, dtype, m), dtype=torch.uint8, device="cuda")
+    assert torch.equal(S.apply(At, ws=ws), ref)
