@@ -124,3 +124,31 @@ def test_batched_refuses_unsupported_layout_before_any_work(lib):
     assert [p.status for p in arr] == [0, lib.SK_E_NOTSUP]
     torch.cuda.synchronize()
     assert all(bool((x == 7.0).all()) for x in xs)
+
+
+WIDE = [(30011, 128, torch.float32), (50000, 200, torch.float32), (70001, 256, torch.float32),
+        (20000, 256, torch.float64), (40000, 160, torch.bfloat16)]
+
+
+def test_batched_wide_problems_match_oracle(lib):
+    """The benchmark batch draws k up to 256 (d = 4k = 1024): problems at
+    k = 128, 200 and 256 (float32, the benchmark's type), one at k = 256 in
+    float64 and one at k = 160 in bfloat16, each against the oracle's
+    sketch-and-solve on the same S."""
+    problems = []
+    for i, (n, k, dt) in enumerate(WIDE):
+        A, b = _problem(n, k, dt, 60 + i)
+        problems.append((A, b, 2000 + i))
+    xs, status, ranks, t_ms, rc = lib.solve_batched(problems)
+    assert rc == 0 and status == [0] * len(WIDE)
+    for (A, b, seed), x, rank, (n, k, dt) in zip(problems, xs, ranks, WIDE):
+        A64 = A.to(torch.float64).cpu().numpy()
+        b64 = b.to(torch.float64).cpu().numpy()
+        xg = x.cpu().numpy()
+        if dt == torch.float64:
+            xr, r, _ = _oracle(A64, b64, k, seed, 2.0 ** -53)
+            assert np.linalg.norm(xg - xr) <= 1e-11 * np.linalg.norm(xr)
+        else:
+            xr, r, tol = _oracle(A64, b64, k, seed, 2.0 ** -24)
+            assert np.linalg.norm(xg - xr) <= tol
+        assert rank == r == k
