@@ -28,10 +28,21 @@ struct RowsPlan {
   // narrow inputs (m <= 4): lanes over buckets instead of columns
   bool narrow = false;
   int64_t tiles_per_chunk = 0;
+  // bucket-indexed register accumulators (ss_idx.hip): jb is the register
+  // file size, rec_bytes the LDS buffer stride; plan_bytes holds the row
+  // codes
+  bool idx = false;
 };
 
 // Chooses the plan; returns SK_OK or SK_E_NOTSUP (and sets the error).
 int plan_rows(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t lda, RowsPlan* plan);
+
+// The bucket-indexed apply (ss_idx.hip): whether it takes this input, its
+// plan, and the sketch kernel writing the partials P.
+bool idx_apply_fits(const sk_sketch* S, int dtype_in, int64_t m);
+int plan_idx(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t lda, RowsPlan* plan);
+int launch_idx_sketch(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64_t m, const void* A, int64_t lda,
+                      void* ws, hipStream_t st);
 
 int launch_rows_apply(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64_t m, const void* A,
                       int64_t lda, int dtype_out, void* SA, int64_t ldsa, void* ws, hipStream_t st);

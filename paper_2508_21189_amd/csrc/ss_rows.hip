@@ -672,6 +672,7 @@ int plan_rows(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_
   const int zeta = S->zeta;
   const int64_t nb = S->nb;
   if (m <= 4 && S->d <= 4096 && nb <= 16383) return plan_narrow(S, dtype_in, m, p);
+  if (idx_apply_fits(S, dtype_in, m)) return plan_idx(S, dtype_in, m, A, lda, p);
   if (nb > 16384) {
     set_error("SparseStack row apply supports at most 16384 buckets per block");
     return SK_E_NOTSUP;
@@ -906,6 +907,16 @@ int launch_rows_apply(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64
                       int dtype_out, void* SA, int64_t ldsa, void* ws, hipStream_t st) {
   void* P = ws;
   void* plan = (unsigned char*)ws + p.partial_bytes;
+  if (p.idx) {
+    int rc = launch_idx_sketch(S, p, dtype_in, m, A, lda, ws, st);
+    if (rc != SK_OK) return rc;
+    if (dtype_in == SK_F64) {
+      if (dtype_out == SK_F64) return launch_reduce<double, double>(p, S, m, P, SA, ldsa, st);
+      return launch_reduce<double, float>(p, S, m, P, SA, ldsa, st);
+    }
+    if (dtype_out == SK_F64) return launch_reduce<float, double>(p, S, m, P, SA, ldsa, st);
+    return launch_reduce<float, float>(p, S, m, P, SA, ldsa, st);
+  }
   // wide kernel: entry << 3 is the row's byte offset in the tile (rows of 64 elements)
   const int runit = p.narrow ? 1 : p.rowb / 8;
   int rc = launch_plan(S, p, plan, runit, st);
