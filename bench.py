@@ -18,7 +18,10 @@ The JSON line also carries
                 (median), iterations, the sketch / QR / LSQR split, and the
                 LSQR iteration's HBM roofline;
   lsqr_mixed    the same on the 8388608 x 500, kappa = 1e10 system, where the
-                float32 / bfloat16 sketch copies pay off;
+                float32 / bfloat16 sketch copies pay off, with the Gaussian
+                sketch beside them, each sketch kernel's HBM roofline, and
+                every solution's errors against the oracle's exact solution
+                (Householder TSQR of [A b] on the host);
   rsvd          Alg. 1 on a 65536 x 16384 float32 matrix with known spectrum
                 (k = 512) for the four sketch kinds, with the spectral error;
   gen_nystrom,  generalized Nystrom (outer and SVD forms) and psd Nystrom,
@@ -28,8 +31,9 @@ The JSON line also carries
                 p50 / p99 per-problem device time;
   injectivity   the injectivity / dilation sweep of Fig. 2;
   stream_read_ref  a plain streaming read of A in the same run;
-  cpu_baseline  the plain CPU oracle timed on a bounded row sample of the
-                same matrix on this host.
+  cpu_baseline  the plain CPU oracle timed per step (sketch, QR, LSQR,
+                exact TSQR) on a bounded row sample of the same system on this
+                host, with the host's core count and BLAS thread count.
 """
 import argparse
 import hashlib
@@ -47,8 +51,11 @@ N, M, D, ZETA = 1 << 22, 200, 800, 8
 DATA_SEED, SKETCH_SEED = 200, 2000
 
 
+APPLY_KERNEL = "ss_idx_kernel<double,200,16>"
+
+
 def kernel_source_digest():
-    p = os.path.join(HERE, "paper_2508_21189_amd", "csrc", "ss_rows.hip")
+    p = os.path.join(HERE, "paper_2508_21189_amd", "csrc", "ss_idx.hip")
     with open(p, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
@@ -56,7 +63,7 @@ def kernel_source_digest():
 def measured_traffic():
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
-    p = os.path.join(HERE, "profiles", "ss_rows_coherent_f64_traffic.json")
+    p = os.path.join(HERE, "profiles", "ss_idx_coherent_f64_traffic.json")
     try:
         with open(p) as f:
             t = json.load(f)
@@ -67,23 +74,74 @@ def measured_traffic():
     return t.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(A_dev, rows):
-    """Oracle SA on the first `rows` rows (the pattern of those rows is the
-    pattern of the full sketch); single-threaded scipy sparse product."""
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([int(i.get("num_threads", 1)) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:
+        return None
+
+
+def cpu_baseline(A_cpu, b_cpu, rows):
+    """The oracle, as it stands, timed per step on the first `rows` rows of the
+    coherent system (the pattern of those rows is the full sketch's): the
+    sketch S A (scipy.sparse product, single-threaded, Philox pattern
+    included), the Householder QR of S A, sketch-and-precondition LSQR to
+    tol 1e-10 on the sample system, and the exact least-squares solve by TSQR
+    (LAPACK, all BLAS threads). The reported value is the sketch's rate."""
     import numpy as np
 
+    from oracle import lstsq as ol
     from oracle import sketches as sk
-    A = A_dev[:rows].cpu().numpy()
+    A = A_cpu[:rows].numpy()
+    b = b_cpu[:rows].numpy()
     times = []
     for _ in range(3):
         t0 = time.perf_counter()
-        sk.sparsestack_apply(A, D, ZETA, SKETCH_SEED)
+        SA = sk.sparsestack_apply(A, D, ZETA, SKETCH_SEED)
         times.append(time.perf_counter() - t0)
-    t = float(np.median(times))
-    gbs = (rows * M * 8 + D * M * 8) / t / 1e9
-    return {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of %d rows, SA via scipy.sparse (single-threaded) incl. Philox pattern; "
-                      "median of 3 runs, %.2f s each" % (rows, N, t)}
+    t_sa = float(np.median(times))
+    Sb = sk.sparsestack_apply(b[:, None], D, ZETA, SKETCH_SEED)[:, 0]
+    t0 = time.perf_counter()
+    ol.householder_qr(np.column_stack([SA, Sb]))
+    t_qr = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    x, info = ol.sketch_and_precondition(A, b, SA, Sb, tol=1e-10, maxit=300)
+    t_lsqr = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    xs, rs, _ = ol.exact_lstsq_tsqr(A, b)
+    t_tsqr = time.perf_counter() - t0
+    gbs = (rows * M * 8 + D * M * 8) / t_sa / 1e9
+    return {"value": round(gbs, 4), "unit": "GB/s", "cores": len(os.sched_getaffinity(0)),
+            "blas_threads": _blas_threads(), "kind": "oracle",
+            "sample": "first %d of %d rows of the coherent system; SA via scipy.sparse (single-threaded, Philox "
+                      "pattern included), median of 3 runs" % (rows, N),
+            "steps_s": {"sketch_SA": round(t_sa, 3), "qr_of_SA": round(t_qr, 4),
+                        "sketch_precond_lsqr_tol1e-10": round(t_lsqr, 3), "lsqr_iters": int(info["iters"]),
+                        "exact_tsqr": round(t_tsqr, 3)},
+            "sample_lsqr_vs_tsqr": {"A_x_minus_xstar_rel_b": float(np.linalg.norm(A @ (x - xs)) /
+                                                                    np.linalg.norm(b))}}
+
+
+def apply_roofline(S, A, torch, transpose=False, reps=5, kernel=None):
+    """Average device time of the dominant kernel of S A (or A S^T) over reps
+    calls (HIP events on the call's stream) and its rate against the 8 TB/s
+    HBM peak, counting A read once and the result written once."""
+    dt_out = torch.float64 if A.dtype == torch.float64 else torch.float32
+    fn = (lambda: S.apply_T(A, out_dtype=dt_out)) if transpose else (lambda: S.apply(A, out_dtype=dt_out))
+    fn()
+    torch.cuda.synchronize()
+    S.timing(1)
+    for _ in range(reps):
+        y = fn()
+    torch.cuda.synchronize()
+    ms, cnt = S.timing(2)
+    S.timing(0)
+    kms = ms / max(1, cnt)
+    alg = A.numel() * A.element_size() + y.numel() * y.element_size()
+    gbs = alg / (kms * 1e-3) / 1e9
+    return {"kernel_ms": round(kms, 4), "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "alg_bytes": int(alg), "kernel": kernel}
 
 
 def _solve_stats(libsketch, torch, S, A, b, reps, tol, As=None, keep_x=None):
@@ -142,10 +200,13 @@ def lsqr_variants(libsketch, torch, A, b, reps, tol=1e-10):
     return out
 
 
-def lsqr_mixed(libsketch, inputs, torch, reps, tol=1e-10):
+def lsqr_mixed(libsketch, inputs, torch, reps, tol=1e-10, exact=True):
     """The mixed-precision system: A 8388608 x 500 iid N(0,1) with column
     scaling kappa(D) = 1e10, SparseStack d = 2000, zeta = 8, the sketch reading
-    A itself (float64) or its float32 / bfloat16 copy; QR and LSQR in float64."""
+    A itself (float64) or its float32 / bfloat16 copy; QR and LSQR in float64.
+    Also: the Gaussian (matrix-core) sketch of the same system, each sketch
+    kernel's HBM roofline, and (exact=True) every solution's error against
+    the oracle's exact least-squares solution computed on the host."""
     n3, m3, d3 = 1 << 23, 500, 2000
     print("bench: generating %d x %d float64 input" % (n3, m3), file=sys.stderr, flush=True)
     A, b, _ = inputs.scaled_gaussian(n3, m3, exponent=10.0, seed=DATA_SEED + 1)
@@ -154,10 +215,14 @@ def lsqr_mixed(libsketch, inputs, torch, reps, tol=1e-10):
     SA64 = S.apply(A)
     nb = float(b.norm())
     x64 = None
+    sols = {}
+    out["apply_roofline"] = {}
     for name, dt in (("f64", None), ("f32", torch.float32), ("bf16", torch.bfloat16)):
         As = A.to(dt) if dt is not None else None
+        out["apply_roofline"][name] = apply_roofline(S, As if As is not None else A, torch)
         xs = []
         out[name] = _solve_stats(libsketch, torch, S, A, b, reps, tol, As, keep_x=xs)
+        sols[name] = xs[0]
         if dt is None:
             x64 = xs[0]
         else:
@@ -173,8 +238,40 @@ def lsqr_mixed(libsketch, inputs, torch, reps, tol=1e-10):
               file=sys.stderr, flush=True)
         del As
         torch.cuda.empty_cache()
-    out["speedup_vs_f64"] = {k: round(out["f64"]["solve_ms"] / out[k]["solve_ms"], 3) for k in ("f32", "bf16")}
-    del A, b, S, SA64, x64
+    # the Gaussian sketch (matrix-core GEMM, d = 2000) of the same system
+    Sg = libsketch.Sketch("gaussian", d3, n3, 1, SKETCH_SEED + 1)
+    xs = []
+    out["gaussian_f64"] = _solve_stats(libsketch, torch, Sg, A, b, 1, tol, None, keep_x=xs)
+    sols["gaussian_f64"] = xs[0]
+    print("bench: mixed gaussian %.2f ms, %d iterations" % (out["gaussian_f64"]["solve_ms"],
+                                                           out["gaussian_f64"]["iters"]), file=sys.stderr, flush=True)
+    del Sg
+    out["speedup_vs_f64"] = {k: round(out["f64"]["solve_ms"] / out[k]["solve_ms"], 3)
+                             for k in ("f32", "bf16", "gaussian_f64")}
+    if exact:
+        # the oracle's exact solution x* (Householder TSQR of [A b] on the
+        # host, from the same bytes) and each solution's errors against it
+        import numpy as np
+
+        from oracle import lstsq as ol
+        t0 = time.perf_counter()
+        Ah, bh = A.cpu(), b.cpu()
+        xstar, rstar, _ = ol.exact_lstsq_tsqr(Ah.numpy(), bh.numpy())
+        t_tsqr = time.perf_counter() - t0
+        del Ah, bh
+        xs_d = torch.from_numpy(np.ascontiguousarray(xstar)).cuda()
+        cn = torch.sqrt(torch.stack([torch.sum(A[:, j] ** 2) for j in range(m3)]))  # column norms
+        out["vs_oracle_exact"] = {"how": "oracle exact_lstsq_tsqr of [A b] on %d host cores, %.1f s"
+                                         % (len(os.sched_getaffinity(0)), t_tsqr)}
+        for name, x in sols.items():
+            r = float((A @ x - b).norm())
+            out["vs_oracle_exact"][name] = {
+                "A_x_minus_xstar_rel_b": float((A @ (x - xs_d)).norm()) / nb,
+                "resnorm_rel_diff": abs(r - rstar) / rstar,
+                "col_scaled_forward_err": float((cn * (x - xs_d)).norm() / (cn * xs_d).norm())}
+        print("bench: mixed errors against the oracle's exact solution done (TSQR %.1f s)" % t_tsqr,
+              file=sys.stderr, flush=True)
+    del A, b, S, SA64, x64, sols
     torch.cuda.empty_cache()
     return out
 
@@ -191,6 +288,9 @@ def rsvd_variants(libsketch, inputs, torch, reps):
     out = {"workload": "A %dx%d f32 = U diag(i^-2) V^T, k=%d" % (rows, cols, k), "floor_sigma_k+1": float(sig[k])}
     for kind, zeta in (("sparsestack", 8), ("srtt", 1), ("sparsertt", 0), ("gaussian", 1)):
         S = libsketch.Sketch(kind, k, cols, zeta, SKETCH_SEED + 2)
+        if kind == "sparsestack":
+            # the column-mode apply Y = A S^T that the RSVD's sketch step runs
+            out["apply_roofline_colmode"] = apply_roofline(S, A, torch, transpose=True)
         S.rsvd(A)
         walls, infos = [], []
         for _ in range(reps):
@@ -404,6 +504,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-rows", type=int, default=1 << 20)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed-exact", action="store_true",
+                    help="skip the host TSQR of the mixed-precision system (errors against the oracle's x*)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain device copy of A (a kernel of known traffic, for counter calibration)")
     ap.add_argument("--lsqr-reps", type=int, default=3, help="timed solves per sketch variant (0 = skip)")
@@ -473,7 +575,7 @@ def main():
         "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": "ss_rows_kernel<double>", "kernel_avg_ms": round(kern_avg_ms, 4),
+                     "kernel": APPLY_KERNEL, "kernel_avg_ms": round(kern_avg_ms, 4),
                      "alg_bytes_per_launch": alg_bytes},
     }
     # context: a plain streaming read of the same bytes in the same run (a
@@ -500,11 +602,11 @@ def main():
         del Acopy
     if args.lsqr_reps > 0:
         rec["lsqr"] = lsqr_variants(libsketch, torch, A, b, args.lsqr_reps)
-    cpu_sample = A[:args.cpu_rows].cpu() if not args.no_cpu else None
+    cpu_sample = (A[:args.cpu_rows].cpu(), b[:args.cpu_rows].cpu()) if not args.no_cpu else None
     del A, b, out, ws, S
     torch.cuda.empty_cache()
     if args.mixed_reps > 0:
-        rec["lsqr_mixed"] = lsqr_mixed(libsketch, inputs, torch, args.mixed_reps)
+        rec["lsqr_mixed"] = lsqr_mixed(libsketch, inputs, torch, args.mixed_reps, exact=not args.no_mixed_exact)
     if args.rsvd_reps > 0:
         rec["rsvd"] = rsvd_variants(libsketch, inputs, torch, args.rsvd_reps)
     if args.gn_reps > 0:
@@ -518,7 +620,7 @@ def main():
                                                args.inj_steps)
     if not args.no_cpu:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
-        rec["cpu_baseline"] = cpu_baseline(cpu_sample, args.cpu_rows)
+        rec["cpu_baseline"] = cpu_baseline(cpu_sample[0], cpu_sample[1], args.cpu_rows)
     print(json.dumps(rec), flush=True)
 
 

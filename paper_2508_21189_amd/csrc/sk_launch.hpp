@@ -32,6 +32,7 @@ struct RowsPlan {
   // file size, rec_bytes the LDS buffer stride; plan_bytes holds the row
   // codes
   bool idx = false;
+  int nbuf = 2;  // its tile buffers (loads run nbuf - 1 tiles ahead)
 };
 
 // Chooses the plan; returns SK_OK or SK_E_NOTSUP (and sets the error).

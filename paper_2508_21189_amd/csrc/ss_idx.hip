@@ -41,7 +41,24 @@ namespace sk {
 namespace {
 
 __device__ inline void idx_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-__device__ inline void idx_wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// Wait until at most n of this wave's memory loads are outstanding (n is
+// capped at 15; a smaller count only waits longer).
+__device__ inline void idx_wait_vm(int n) {
+  switch (n) {
+#define SK_VMW(K) \
+  case K:         \
+    asm volatile("s_waitcnt vmcnt(" #K ")" ::: "memory"); \
+    break;
+    SK_VMW(1) SK_VMW(2) SK_VMW(3) SK_VMW(4) SK_VMW(5) SK_VMW(6) SK_VMW(7) SK_VMW(8)
+    SK_VMW(9) SK_VMW(10) SK_VMW(11) SK_VMW(12) SK_VMW(13) SK_VMW(14) SK_VMW(15)
+#undef SK_VMW
+    default:
+      if (n >= 16)
+        asm volatile("s_waitcnt vmcnt(15)" ::: "memory");
+      else
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  }
+}
 
 // Direct global->LDS loads (16 or 4 bytes a lane at LDS address M0 + lane *
 // width), issued from inline assembly so that the compiler's counters do not
@@ -211,6 +228,7 @@ template <>
 struct IdxT<uint16_t> {  // bf16 input, f32 accumulation
   using acc = float;
   using pm = uint32_t;
+  static constexpr uint32_t one_hi = 0x3F800000u;
   static constexpr int rpa = 1;
 };
 
@@ -245,6 +263,7 @@ struct IdxArgs {
   uint32_t k0, k1;
   void* P;
   int buf_stride;  // LDS bytes of one tile buffer
+  int nbuf;        // tile buffers: loads run nbuf - 1 tiles ahead
   int off_touch;   // LDS scratch (1 KB per wave) that the code prefetch lands in
   const unsigned char* codes_touch;  // the row codes, for that prefetch only
 };
@@ -361,12 +380,24 @@ __global__ void __launch_bounds__(NREG > 64 ? 512 : 1024)
         if (o + lane * 16 < cbytes) idx_dma16(csrc + o + lane * 16, la);
     }
   };
-  if (nsub > 0) issue_loads(0, 0);
+  // Loads this wave issues for one full tile: its share of the tile's loads
+  // that have an active lane (a load of 64 chunks starting at a row's first
+  // chunk always has one; with 128 chunks a row, one starting mid-row has
+  // one iff the slab reaches that far), and the code prefetch.
+  const int nbuf = a.nbuf;
+  int per_tile = walker ? (8 * R + 1023) / 1024 : 0;
+  for (int k = wave; k < n_instr; k += nwaves)
+    if (((k * 64) % CPR) * LB < slab_bytes) ++per_tile;
+  for (int p = 0; p < nbuf - 1 && p < nsub; ++p) issue_loads(p, p);
   for (int st = 0; st < nsub; ++st) {
-    const int buf = st & 1;
-    idx_wait_dma();
+    const int buf = st % nbuf;
+    // tile st is complete once only the loads of the later tiles in flight
+    // remain; a partial (last) tile among those: wait for everything
+    const int later = min(st + nbuf - 2, nsub - 1) - st;
+    const bool later_full = later <= 0 || r_begin + (int64_t)(st + later + 1) * R <= r_end;
+    idx_wait_vm(later > 0 && later_full ? later * per_tile : 0);
     idx_barrier();  // tile st is in LDS; everyone finished tile st-1
-    if (st + 1 < nsub) issue_loads(st + 1, buf ^ 1);
+    if (st + nbuf - 1 < nsub) issue_loads(st + nbuf - 1, (st + nbuf - 1) % nbuf);
     if (walker) {
       const int64_t r0 = r_begin + (int64_t)st * R;
       const int rv = (int)min((int64_t)R, r_end - r0);
@@ -494,7 +525,11 @@ static int plan_idx_lb(const sk_sketch* S, int dtype_in, int64_t m, int load_byt
   const int wg_per_cu = std::max(1, std::min(2, (4 * wps) / p->W));
   const size_t cap = std::min<size_t>(160 * 1024, (size_t)(160 * 1024 / wg_per_cu));
   const size_t touch = (size_t)1024 * p->W;
-  int R = (int)((cap - touch - 64) / 2 / (size_t)p->rowb);
+  // two buffers: loading three or four tiles ahead measured slower (F64
+  // coherent 2.06 ms with two, 2.40 with three, 2.62 with four)
+  const int nbuf = std::max(2, std::min(4, env_i("SKETCH_IDX_NBUF", 2)));
+  p->nbuf = nbuf;
+  int R = (int)((cap - touch - 64) / nbuf / (size_t)p->rowb);
   // at most 128 rows: larger tiles measured slower (F32 m = 200: 128 rows
   // 1.34 ms, 288 rows 1.90 ms), and 128 is the most that fits for F64
   R = std::min(R, env_i("SKETCH_IDX_ROWS", 128));
@@ -507,7 +542,7 @@ static int plan_idx_lb(const sk_sketch* S, int dtype_in, int64_t m, int load_byt
   }
   p->R = R;
   const size_t buf = a16((size_t)R * p->rowb);
-  p->lds_bytes = 2 * buf + touch;
+  p->lds_bytes = nbuf * buf + touch;
   p->rec_bytes = (int)buf;  // buffer stride
   p->lst_off = 0;
 
@@ -571,7 +606,8 @@ static int launch_idx_t(const sk_sketch* S, const RowsPlan& p, int64_t m, const 
   a.nb = (int)S->nb;
   a.P = P;
   a.buf_stride = p.rec_bytes;
-  a.off_touch = 2 * p.rec_bytes;
+  a.nbuf = p.nbuf;
+  a.off_touch = p.nbuf * p.rec_bytes;
   a.codes_touch = (const unsigned char*)codes;
   const int64_t grid = ((int64_t)(p.n_chunks + 7) / 8) * 8 * p.n_slabs * p.n_groups;
   auto kern = ss_idx_kernel<Tin, NREG, LB>;
