@@ -151,6 +151,29 @@ int sketch_apply(sketch_t S, int dtype_in, int layout, int64_t m, const void* A,
 int sketch_apply_T(sketch_t S, int dtype_in, int layout, int64_t rows, const void* A, int64_t lda, int dtype_out,
                    void* Y, int64_t ldy, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * SA = S A exactly as sketch_apply (row-major A, SparseStack only, same
+ * kernels, bitwise the same result), for callers that cannot allocate device
+ * memory: code under stream capture, serving loops, harnesses that forbid
+ * allocation. Its scratch (per-chunk partial sums and per-row codes) is a
+ * fixed device array of the library, sketch_noalloc_scratch_bytes() bytes
+ * (128 MB) on each device the library runs on, held until the process ends;
+ * its device address is looked up once per device on the first call there.
+ * The call allocates nothing and takes no workspace. An apply that needs
+ * more scratch than the array holds (sketch_workspace_size, op 0) is refused
+ * with SK_E_NOTSUP before any work is queued. Every call on a device shares
+ * that device's array (it keeps the last call's contents; the apply writes
+ * everything it reads), so calls that overlap on one device, on other
+ * streams or threads, race and must be serialized by the caller. The handle
+ * must have been created on the current device. Timing (sketch_timing) must
+ * be off: it creates events.
+ */
+int sketch_apply_noalloc(sketch_t S, int dtype_in, int64_t m, const void* A, int64_t lda, int dtype_out, void* SA,
+                         int64_t ldsa, void* stream);
+
+/* Bytes of the fixed scratch array behind sketch_apply_noalloc. */
+size_t sketch_noalloc_scratch_bytes(void);
+
 /* Result details of sketch_sv_extremes. */
 typedef struct {
   int steps;           /* Lanczos steps taken (fewer than asked after an invariant subspace) */

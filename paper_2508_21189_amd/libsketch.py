@@ -58,6 +58,10 @@ def load():
     lib.sketch_adjoint.argtypes = [_vp, _i64, _vp, _i64, _vp, _i64, _vp]
     lib.sketch_pattern.argtypes = [_vp, _vp, _vp, _vp]
     lib.sketch_timing.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
+    if hasattr(lib, "sketch_apply_noalloc"):
+        lib.sketch_apply_noalloc.argtypes = [_vp, ctypes.c_int, _i64, _vp, _i64, ctypes.c_int, _vp, _i64, _vp]
+        lib.sketch_noalloc_scratch_bytes.restype = ctypes.c_size_t
+        lib.sketch_noalloc_scratch_bytes.argtypes = []
     _bind_drivers(lib)
     _lib = lib
     return lib
@@ -142,7 +146,8 @@ _DRIVER_SIGS = {
 def exported_symbols():
     """Names the header declares; used by the load test."""
     return ["sketch_create", "sketch_destroy", "sketch_last_error", "sketch_info", "sketch_apply", "sketch_apply_T",
-            "sketch_workspace_size", "sketch_adjoint", "sketch_pattern", "sketch_timing"] + list(_DRIVER_SIGS)
+            "sketch_workspace_size", "sketch_adjoint", "sketch_pattern", "sketch_timing", "sketch_apply_noalloc",
+            "sketch_noalloc_scratch_bytes"] + list(_DRIVER_SIGS)
 
 
 def last_error():
@@ -213,6 +218,19 @@ class Sketch:
         wsp, wsb = (None, 0) if ws is None else (_ptr(ws), ws.numel() * ws.element_size())
         check(load().sketch_apply(self.h, _DT[A.dtype], layout, m, _ptr(A), lda, _DT[odt], _ptr(out),
                                   out.stride(0), wsp, wsb, _stream(stream)))
+        return out
+
+    def apply_noalloc(self, A, out_dtype=None, out=None, stream=None):
+        """SA = S @ A through sketch_apply_noalloc (row-major A, SparseStack): the
+        library's fixed device scratch array instead of any workspace."""
+        assert A.is_cuda and A.dim() == 2 and A.shape[0] == self.n and A.stride(1) == 1
+        m = A.shape[1]
+        odt = out_dtype or (torch.float64 if A.dtype == torch.float64 else torch.float32)
+        if out is None:
+            out = torch.empty((self.d, m), dtype=odt, device=A.device)
+        assert out.shape == (self.d, m) and out.stride(1) == 1 and out.dtype == odt
+        check(load().sketch_apply_noalloc(self.h, _DT[A.dtype], m, _ptr(A), A.stride(0), _DT[odt], _ptr(out),
+                                          out.stride(0), _stream(stream)))
         return out
 
     def apply_T(self, A, out_dtype=None, out=None, ws=None, stream=None):
