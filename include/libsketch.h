@@ -271,7 +271,7 @@ typedef struct {
 
 /*
  * Sketch-and-precondition, the high-accuracy least-squares solver named in
- * Sec. 1.3 (remark after Thm. 1.4): QR of the sketch S A = Q R (Householder,
+ * Sec. 1.4 (remark after Thm. 1.4): QR of the sketch S A = Q R (Householder,
  * F64), the warm start x0 = R^-1 Q^T S b, then LSQR (Paige & Saunders 1982)
  * on min ||A R^-1 y - (b - A x0)|| in F64, and x = x0 + R^-1 y.
  * Stopping test (checked every iteration): ||r|| <= tol ||r0|| or

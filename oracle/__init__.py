@@ -20,7 +20,7 @@ Modules
              Gaussian test matrix (Def. 1.4): dense construction and
              application S @ A, A @ S^T, S^T @ Y.
   lstsq      sketch-and-solve (Alg. 3), exact least squares by Householder
-             TSQR, sketch-and-precondition with LSQR (Sec. 1.3 remark).
+             TSQR, sketch-and-precondition with LSQR (Sec. 1.4 remark).
   lowrank    randomized SVD (Alg. 1) and the spectral-error estimate.
   metrics    subspace-embedding distortion (Prop. 1.9, Defs. 1.1-1.2),
              coherence, isotropy statistics.

@@ -6,7 +6,7 @@
   lsqr                    Paige & Saunders, ACM TOMS 8 (1982), the Krylov
                           solver used by sketch-and-precondition
   sketch_and_precondition the method the paper names as the standard
-                          high-accuracy least-squares solver (Sec. 1.3,
+                          high-accuracy least-squares solver (Sec. 1.4,
                           remark after Thm. 1.4), in the form of its
                           references: QR of the sketch, then LSQR on A R^-1.
 
