@@ -600,6 +600,16 @@ def main():
         Acopy = A.clone()  # reads and writes n*m*8 bytes
         torch.cuda.synchronize()
         del Acopy
+    # the Gaussian comparison sketch (Def. 1.4) of the same A: G generated in
+    # the kernel, FP64 matrix cores; its roofline is the FP64 MFMA peak
+    Sg = libsketch.Sketch("gaussian", D, N, 1, SKETCH_SEED)
+    rg = apply_roofline(Sg, A, torch, reps=3)
+    flops = 2.0 * D * N * M
+    tfs = flops / (rg["kernel_ms"] * 1e-3) / 1e12
+    rec["gaussian_roofline"] = {"bound": "mfma", "achieved": round(tfs, 2), "peak": 78.6, "unit": "TFLOP/s",
+                                "frac": round(tfs / 78.6, 4), "kernel": "gauss_rows_kernel (FP64 MFMA, G generated "
+                                "in-kernel)", "kernel_avg_ms": rg["kernel_ms"], "flops_per_launch": flops}
+    del Sg
     if args.lsqr_reps > 0:
         rec["lsqr"] = lsqr_variants(libsketch, torch, A, b, args.lsqr_reps)
     cpu_sample = (A[:args.cpu_rows].cpu(), b[:args.cpu_rows].cpu()) if not args.no_cpu else None
