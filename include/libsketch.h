@@ -257,6 +257,32 @@ typedef struct {
 int lstsq_sketch_solve(sketch_t S, int64_t m, const double* A, int64_t lda, const double* b, double* x,
                        sk_solve_info* info, void* stream);
 
+/* Result of lstsq_sketch_solve_async, written by the device. */
+typedef struct {
+  int rank;              /* numerical rank r of S A (the rank test of Alg. 3); r < m: truncated solution */
+  int pad_;
+  double sigma_max;      /* largest singular value of S A */
+  double sigma_min_kept; /* r-th singular value of S A */
+} sk_solve_result;
+
+/*
+ * Sketch-and-solve (Alg. 3), exactly as lstsq_sketch_solve (the same kernels
+ * in the same order: bitwise the same x), but fully asynchronous and
+ * allocation-free, so that it can be recorded into a HIP graph by stream
+ * capture: everything is enqueued on `stream`, nothing is allocated (ws,
+ * ws_bytes >= lstsq_solve_workspace_size, is required) and the host waits for
+ * nothing. The rank and singular values go to `result`, a DEVICE struct (may
+ * be NULL), when the stream reaches them; rank deficiency is reported there,
+ * not as a return code. Returns 0 once enqueued, or a negative error before
+ * enqueuing anything. Calls sharing a workspace must be serialized.
+ */
+int lstsq_sketch_solve_async(sketch_t S, int64_t m, const double* A, int64_t lda, const double* b, double* x,
+                             sk_solve_result* result, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes of lstsq_sketch_solve_async for m columns (a bound over the
+ * alignments and leading dimensions A may have). */
+int lstsq_solve_workspace_size(sketch_t S, int64_t m, size_t* bytes);
+
 typedef struct {
   int iters;            /* LSQR iterations taken */
   int converged;        /* 1 if the stopping test held */

@@ -65,24 +65,32 @@ static void sparsecol_host(int64_t npad, int64_t d, int xi, uint32_t k0, uint32_
   }
 }
 
-// Grows the handle-owned workspace (used when the caller passes ws = NULL).
-int handle_workspace(sk_sketch* S, size_t bytes, void** out) {
+// Grows a handle-owned buffer to at least `bytes`, ordered on the call's
+// stream: the old buffer is released and the new one taken with the
+// stream-ordered allocator, so no device-wide synchronization is needed (calls
+// that share a handle's buffers are serialized by the caller, per the header).
+int grow_buffer(void** buf, size_t* cur, size_t bytes, hipStream_t st) {
+  if (*cur >= bytes) return SK_OK;
+  if (*buf) {
+    SK_HIP(hipFreeAsync(*buf, st));
+    *buf = nullptr;
+    *cur = 0;
+  }
+  void* p = nullptr;
+  SK_HIP(hipMallocAsync(&p, bytes, st));
+  *buf = p;
+  *cur = bytes;
+  return SK_OK;
+}
+
+// The handle-owned workspace (used when the caller passes ws = NULL).
+int handle_workspace(sk_sketch* S, size_t bytes, void** out, hipStream_t st) {
   if (bytes == 0) {
     *out = nullptr;
     return SK_OK;
   }
-  if (S->ws_bytes < bytes) {
-    if (S->ws) {
-      SK_HIP(hipDeviceSynchronize());
-      SK_HIP(hipFree(S->ws));
-      S->ws = nullptr;
-      S->ws_bytes = 0;
-    }
-    void* p = nullptr;
-    SK_HIP(hipMalloc(&p, bytes));
-    S->ws = p;
-    S->ws_bytes = bytes;
-  }
+  int rc = grow_buffer(&S->ws, &S->ws_bytes, bytes, st);
+  if (rc != SK_OK) return rc;
   *out = S->ws;
   return SK_OK;
 }
@@ -225,10 +233,12 @@ int sketch_destroy(sketch_t S) {
   if (!S) return SK_OK;
   (void)hipDeviceSynchronize();
   drop_events(S);
-  if (S->ws) (void)hipFree(S->ws);
+  // (the handle's workspaces come from the stream-ordered allocator)
+  if (S->ws) (void)hipFreeAsync(S->ws, nullptr);
   if (S->d_sample) (void)hipFree(S->d_sample);
   if (S->d_sgn) (void)hipFree(S->d_sgn);
   drivers_release(S);
+  (void)hipStreamSynchronize(nullptr);  // the stream-ordered frees
   delete S;
   return SK_OK;
 }

@@ -184,7 +184,7 @@ int apply_colmajor(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t
       return SK_E_INVAL;
     }
   } else {
-    rc = handle_workspace(S, need, &w);
+    rc = handle_workspace(S, need, &w, st);
     if (rc != SK_OK) return rc;
   }
   const size_t cb = colmajor_copy_bytes(S, dtype_in, m);
@@ -211,7 +211,7 @@ int apply_T_colmajor(sk_sketch* S, int dtype_in, int64_t rows, const void* A, in
       return SK_E_INVAL;
     }
   } else {
-    rc = handle_workspace(S, need, &w);
+    rc = handle_workspace(S, need, &w, st);
     if (rc != SK_OK) return rc;
   }
   rc = apply_dispatch(S, dtype_in, rows, A, lda, dtype_out, w, rows, (char*)w + rb, need - rb, st);
@@ -236,7 +236,7 @@ int apply_dispatch(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t
           return SK_E_INVAL;
         }
       } else {
-        rc = handle_workspace(S, p.partial_bytes + p.plan_bytes, &w);
+        rc = handle_workspace(S, p.partial_bytes + p.plan_bytes, &w, st);
         if (rc != SK_OK) return rc;
       }
       return launch_rows_apply(S, p, dtype_in, m, A, lda, dtype_out, SA, ldsa, w, st);
@@ -251,7 +251,7 @@ int apply_dispatch(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t
             return SK_E_INVAL;
           }
         } else {
-          int rc = handle_workspace(S, need, &w);
+          int rc = handle_workspace(S, need, &w, st);
           if (rc != SK_OK) return rc;
         }
         return launch_gauss_rows_f32(S, m, (const float*)A, lda, dtype_out, SA, ldsa, w, need, st);
@@ -268,7 +268,7 @@ int apply_dispatch(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t
           return SK_E_INVAL;
         }
       } else {
-        int rc = handle_workspace(S, need, &w);
+        int rc = handle_workspace(S, need, &w, st);
         if (rc != SK_OK) return rc;
       }
       return launch_gauss_rows(S, m, (const double*)A, lda, nullptr, (double*)SA, ldsa, nullptr, w, need, st);
@@ -287,7 +287,7 @@ int apply_dispatch(sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t
           return SK_E_INVAL;
         }
       } else {
-        int rc = handle_workspace(S, need, &w);
+        int rc = handle_workspace(S, need, &w, st);
         if (rc != SK_OK) return rc;
       }
       return launch_srtt_rows(S, m, (const double*)A, lda, nullptr, (double*)SA, ldsa, nullptr, w, need, st);
@@ -315,7 +315,7 @@ static int apply_T_via_rows(sk_sketch* S, int dtype_in, int64_t rows, const void
       return SK_E_INVAL;
     }
   } else {
-    rc = handle_workspace(S, rb + rest, &w);
+    rc = handle_workspace(S, rb + rest, &w, st);
     if (rc != SK_OK) return rc;
   }
   rc = apply_colmajor(S, dtype_in, rows, A, lda, dtype_out, w, rows, (char*)w + rb, rest, st);
@@ -339,7 +339,7 @@ int apply_T_dispatch(sk_sketch* S, int dtype_in, int64_t rows, const void* A, in
         return SK_E_INVAL;
       }
     } else {
-      rc = handle_workspace(S, need, &w);
+      rc = handle_workspace(S, need, &w, st);
       if (rc != SK_OK) return rc;
     }
     return launch_cols_apply(S, dtype_in, rows, A, lda, dtype_out, Y, ldy, w, need, st);
@@ -356,7 +356,7 @@ int apply_T_dispatch(sk_sketch* S, int dtype_in, int64_t rows, const void* A, in
           return SK_E_INVAL;
         }
       } else {
-        rc = handle_workspace(S, need, &w);
+        rc = handle_workspace(S, need, &w, st);
         if (rc != SK_OK) return rc;
       }
     }

@@ -34,19 +34,9 @@ struct Carver {
   }
 };
 
-int driver_workspace(sk_sketch* S, size_t bytes, char** out) {
-  if (S->dws_bytes < bytes) {
-    if (S->dws) {
-      SK_HIP(hipDeviceSynchronize());
-      SK_HIP(hipFree(S->dws));
-      S->dws = nullptr;
-      S->dws_bytes = 0;
-    }
-    void* p = nullptr;
-    SK_HIP(hipMalloc(&p, bytes));
-    S->dws = p;
-    S->dws_bytes = bytes;
-  }
+int driver_workspace(sk_sketch* S, size_t bytes, char** out, hipStream_t st) {
+  const int rc = grow_buffer(&S->dws, &S->dws_bytes, bytes, st);
+  if (rc != SK_OK) return rc;
   if (!S->h_pinned) SK_HIP(hipHostMalloc(&S->h_pinned, 4096, hipHostMallocDefault));
   *out = static_cast<char*>(S->dws);
   return SK_OK;
@@ -57,7 +47,9 @@ struct Phases {
   hipEvent_t ev[6] = {};
   int n = 0;
   hipStream_t st;
-  explicit Phases(hipStream_t s) : st(s) {}
+  explicit Phases(hipStream_t s, bool enabled = true) : st(s) {
+    if (!enabled) n = 6;  // no events (stream capture, no host involvement)
+  }
   int mark() {
     if (n >= 6) return SK_OK;
     SK_HIP(hipEventCreate(&ev[n]));
@@ -71,7 +63,8 @@ struct Phases {
     return 0.0;
   }
   ~Phases() {
-    for (int i = 0; i < n; ++i) (void)hipEventDestroy(ev[i]);
+    for (int i = 0; i < n; ++i)
+      if (ev[i]) (void)hipEventDestroy(ev[i]);
   }
 };
 
@@ -255,7 +248,7 @@ int batched_check(const sk_ls_problem* probs, int nprob, int d_per_k, int zeta, 
 
 void drivers_release(sk_sketch* S) {
   blas_release(S);
-  if (S->dws) (void)hipFree(S->dws);
+  if (S->dws) (void)hipFreeAsync(S->dws, nullptr);
   if (S->h_pinned) (void)hipHostFree(S->h_pinned);
   S->dws = nullptr;
   S->h_pinned = nullptr;
@@ -290,7 +283,7 @@ int lstsq_sketch_solve(sketch_t S, int64_t m, const double* A, int64_t lda, cons
   double* z = cv.take<double>((size_t)k);
   int* rank = cv.take<int>(1);
   char* base = nullptr;
-  SK_TRY(driver_workspace(S, cv.off, &base));
+  SK_TRY(driver_workspace(S, cv.off, &base, st));
   Carver cv2{base, 0};
   SK_TRY(sketch_bufs(cv2, S, k, SK_F64, A, lda, b, &B));
   U = cv2.take<double>((size_t)k * k);
@@ -323,6 +316,87 @@ int lstsq_sketch_solve(sketch_t S, int64_t m, const double* A, int64_t lda, cons
     info->t_total_ms = ph.ms(0, 2);
   }
   return r < k ? SK_W_RANKDEF : SK_OK;
+}
+
+// rank, sigma_1 and sigma_r of a solve into the caller's device struct
+__global__ void solve_result_kernel(const int* rank, const double* sv, sk_solve_result* out) {
+  const int r = *rank;
+  out->rank = r;
+  out->sigma_max = sv[0];
+  out->sigma_min_kept = r > 0 ? sv[r - 1] : 0.0;
+}
+
+// Workspace of one sketch-and-solve (Alg. 3) for an A at this address and
+// leading dimension (the apply's plan depends on the alignment).
+static size_t solve_ws_bytes(sk_sketch* S, int k, const void* A, int64_t lda, const void* b, int* rc) {
+  Carver cv;
+  SketchBufs B;
+  *rc = sketch_bufs(cv, S, k, SK_F64, A, lda, b, &B);
+  cv.take<double>((size_t)k * k);
+  cv.take<double>((size_t)k * k);
+  cv.take<double>((size_t)k);
+  cv.take<double>((size_t)2 * k * k);
+  cv.take<double>((size_t)k);
+  cv.take<int>(1);
+  return cv.off + 256;  // (+256: the caller's buffer is carved from a 256-byte aligned start)
+}
+
+int lstsq_solve_workspace_size(sketch_t S, int64_t m, size_t* bytes) {
+  if (!S || !bytes || m < 1 || S->d < m || m > 1024) {
+    set_error("lstsq_solve_workspace_size: invalid argument (need m <= d, m <= 1024)");
+    return SK_E_INVAL;
+  }
+  // the bound over the alignments and leading dimensions an A may have
+  size_t best = 0;
+  const uintptr_t addrs[2] = {256, 8};
+  for (uintptr_t ad : addrs)
+    for (int64_t ld : {m, m + 1}) {
+      int rc = SK_OK;
+      const size_t need = solve_ws_bytes(S, (int)m, (const void*)ad, ld, (const void*)ad, &rc);
+      if (rc < 0) return rc;
+      best = std::max(best, need);
+    }
+  *bytes = best;
+  return SK_OK;
+}
+
+int lstsq_sketch_solve_async(sketch_t S, int64_t m, const double* A, int64_t lda, const double* b, double* x,
+                             sk_solve_result* result, void* ws, size_t ws_bytes, void* stream) {
+  if (!S || !A || !b || !x || !ws || m < 1 || lda < m) {
+    set_error("lstsq_sketch_solve_async: invalid argument (a workspace is required)");
+    return SK_E_INVAL;
+  }
+  if (S->d < m || m > 1024) {
+    set_error("lstsq_sketch_solve_async: need m <= d and m <= 1024");
+    return SK_E_INVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int k = (int)m;
+  int rc = SK_OK;
+  const size_t need = solve_ws_bytes(S, k, A, lda, b, &rc);
+  if (rc < 0) return rc;
+  if (ws_bytes < need) {
+    set_error("lstsq_sketch_solve_async: workspace too small (see lstsq_solve_workspace_size)");
+    return SK_E_INVAL;
+  }
+  Carver cv{(char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255), 0};
+  SketchBufs B;
+  SK_TRY(sketch_bufs(cv, S, k, SK_F64, A, lda, b, &B));
+  double* U = cv.take<double>((size_t)k * k);
+  double* V = cv.take<double>((size_t)k * k);
+  double* sv = cv.take<double>((size_t)k);
+  double* work = cv.take<double>((size_t)2 * k * k);
+  double* z = cv.take<double>((size_t)k);
+  int* rank = cv.take<int>(1);
+  Phases ph(st, false);
+  SK_TRY(sketch_and_factor(S, k, SK_F64, A, lda, b, B, ph, st));
+  SK_TRY(launch_jacobi_svd(B.R, k, U, sv, V, work, st));
+  SK_TRY(launch_svd_solve(U, sv, V, B.c, k, std::ldexp(1.0, -52), x, z, rank, st));
+  if (result) {
+    hipLaunchKernelGGL(solve_result_kernel, dim3(1), dim3(1), 0, st, rank, sv, result);
+    SK_HIP(hipGetLastError());
+  }
+  return SK_OK;
 }
 
 int lstsq_batched_workspace_size(const sk_ls_problem* probs, int nprob, int d_per_k, int zeta, size_t* bytes) {
@@ -520,7 +594,7 @@ int lstsq_sketch_precond(sketch_t S, int64_t m, const double* A, int64_t lda, in
   Carver cv;
   SK_TRY(carve(cv));
   char* base = nullptr;
-  SK_TRY(driver_workspace(S, cv.off, &base));
+  SK_TRY(driver_workspace(S, cv.off, &base, st));
   Carver cv2{base, 0};
   SK_TRY(carve(cv2));
   double* qv = part + (size_t)groups * (k + 1);
@@ -622,7 +696,7 @@ int lstsq_residual(sketch_t S, int64_t m, const double* A, int64_t lda, const do
   Carver cv;
   carve(cv);
   char* base = nullptr;
-  SK_TRY(driver_workspace(S, cv.off, &base));
+  SK_TRY(driver_workspace(S, cv.off, &base, st));
   Carver cv2{base, 0};
   carve(cv2);
   SK_HIP(hipMemcpyAsync(u, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));

@@ -39,19 +39,8 @@ struct Carve {
     if (_rc < 0) return _rc;  \
   } while (0)
 
-int lowrank_workspace(sk_sketch* S, size_t bytes, char** out) {
-  if (S->dws_bytes < bytes) {
-    if (S->dws) {
-      SK_HIP(hipDeviceSynchronize());
-      SK_HIP(hipFree(S->dws));
-      S->dws = nullptr;
-      S->dws_bytes = 0;
-    }
-    void* p = nullptr;
-    SK_HIP(hipMalloc(&p, bytes));
-    S->dws = p;
-    S->dws_bytes = bytes;
-  }
+int lowrank_workspace(sk_sketch* S, size_t bytes, char** out, hipStream_t st) {
+  SK_TRY2(grow_buffer(&S->dws, &S->dws_bytes, bytes, st));
   if (!S->h_pinned) SK_HIP(hipHostMalloc(&S->h_pinned, 4096, hipHostMallocDefault));
   *out = static_cast<char*>(S->dws);
   return SK_OK;
@@ -177,7 +166,7 @@ extern "C" int rsvd(sketch_t S, int dtype, int64_t rows, const void* A, int64_t 
   Carve c0;
   carve(c0);
   char* base = nullptr;
-  SK_TRY2(lowrank_workspace(S, c0.off, &base));
+  SK_TRY2(lowrank_workspace(S, c0.off, &base, st));
   Carve c1{base, 0};
   carve(c1);
   int* h = static_cast<int*>(S->h_pinned);
@@ -296,7 +285,7 @@ extern "C" int gen_nystrom(sketch_t So, sketch_t Sp, int dtype, int64_t rows, co
   Carve c0;
   carve(c0);
   char* base = nullptr;
-  SK_TRY2(lowrank_workspace(So, c0.off, &base));
+  SK_TRY2(lowrank_workspace(So, c0.off, &base, st));
   Carve c1{base, 0};
   carve(c1);
   int* h = static_cast<int*>(So->h_pinned);
@@ -386,7 +375,7 @@ extern "C" int gen_nystrom_svd(sketch_t So, sketch_t Sp, int dtype, int64_t rows
   Carve c0;
   carve(c0);
   char* base = nullptr;
-  SK_TRY2(lowrank_workspace(So, c0.off, &base));
+  SK_TRY2(lowrank_workspace(So, c0.off, &base, st));
   Carve c1{base, 0};
   carve(c1);
   int* h = static_cast<int*>(So->h_pinned);
@@ -491,7 +480,7 @@ extern "C" int nystrom_psd(sketch_t S, int dtype, const void* A, int64_t lda, do
   Carve c0;
   carve(c0);
   char* base = nullptr;
-  SK_TRY2(lowrank_workspace(S, c0.off, &base));
+  SK_TRY2(lowrank_workspace(S, c0.off, &base, st));
   Carve c1{base, 0};
   carve(c1);
   int* h = static_cast<int*>(S->h_pinned);

@@ -26,7 +26,7 @@
 #include <cmath>
 #include <vector>
 
-#include "sk_launch.hpp"
+#include "sk_drivers.hpp"
 
 namespace sk {
 
@@ -236,19 +236,9 @@ struct ExtCarve {
   }
 };
 
-int ext_workspace(sk_sketch* S, size_t bytes, char** out) {
-  if (S->dws_bytes < bytes) {
-    if (S->dws) {
-      SK_HIP(hipDeviceSynchronize());
-      SK_HIP(hipFree(S->dws));
-      S->dws = nullptr;
-      S->dws_bytes = 0;
-    }
-    void* p = nullptr;
-    SK_HIP(hipMalloc(&p, bytes));
-    S->dws = p;
-    S->dws_bytes = bytes;
-  }
+int ext_workspace(sk_sketch* S, size_t bytes, char** out, hipStream_t st) {
+  const int rc = grow_buffer(&S->dws, &S->dws_bytes, bytes, st);
+  if (rc != SK_OK) return rc;
   *out = static_cast<char*>(S->dws);
   return SK_OK;
 }
@@ -322,7 +312,7 @@ extern "C" int sketch_sv_extremes(sketch_t S, int steps, uint64_t start_seed, do
   carve(cv, &keys, &keys2, &vals, &vals2, &tmp, &rowptr, &v, &vp, &w, &y, &part, &part2, &al, &be, &kstop);
   char* base = nullptr;
   {
-    int rc = ext_workspace(S, cv.off, &base);
+    int rc = ext_workspace(S, cv.off, &base, st);
     if (rc != SK_OK) return rc;
   }
   ExtCarve c2;

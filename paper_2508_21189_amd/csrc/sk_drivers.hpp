@@ -4,7 +4,9 @@
 
 namespace sk {
 
-int handle_workspace(sk_sketch* S, size_t bytes, void** out);
+int handle_workspace(sk_sketch* S, size_t bytes, void** out, hipStream_t st);
+// Stream-ordered growth of a handle-owned buffer (no device-wide sync).
+int grow_buffer(void** buf, size_t* cur, size_t bytes, hipStream_t st);
 
 // Bytes of workspace needed by sketch_apply (op 0) or sketch_apply_T (op 1).
 int apply_workspace(const sk_sketch* S, int op, int dtype_in, int64_t m, size_t* bytes);

@@ -129,6 +129,8 @@ _DRIVER_SIGS = {
     "lstsq_sketch_precond": [_vp, _i64, _vp, _i64, ctypes.c_int, _vp, _i64, _vp, _vp, ctypes.c_double, ctypes.c_int,
                              ctypes.c_int, ctypes.POINTER(LsqrInfo), _vp],
     "lstsq_residual": [_vp, _i64, _vp, _i64, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp],
+    "lstsq_sketch_solve_async": [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp],
+    "lstsq_solve_workspace_size": [_vp, _i64, ctypes.POINTER(ctypes.c_size_t)],
     "rsvd": [_vp, ctypes.c_int, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, ctypes.POINTER(RsvdInfo), _vp],
     "gen_nystrom": [_vp, _vp, ctypes.c_int, _i64, _vp, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(GnInfo), _vp],
     "gen_nystrom_svd": [_vp, _vp, ctypes.c_int, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, ctypes.POINTER(GnInfo),
@@ -141,6 +143,17 @@ _DRIVER_SIGS = {
     "lstsq_sketch_solve_batched": [ctypes.POINTER(LsProblem), ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
                                    ctypes.c_size_t, _vp],
 }
+
+
+SOLVE_RESULT_BYTES = 24  # sk_solve_result: int rank, int pad, double sigma_max, double sigma_min_kept
+
+
+def read_solve_result(buf):
+    """(rank, sigma_max, sigma_min_kept) from a device sk_solve_result."""
+    h = buf.cpu().numpy().tobytes()
+    import struct
+    r, _, smax, smin = struct.unpack("iidd", h[:24])
+    return r, smax, smin
 
 
 def exported_symbols():
@@ -287,6 +300,22 @@ class Sketch:
         rc = check(load().lstsq_sketch_solve(self.h, m, _ptr(A), A.stride(0), _ptr(b), _ptr(x), ctypes.byref(info),
                                              _stream(stream)))
         return x, rc, _as_dict(info)
+
+    def solve_workspace_size(self, m):
+        """Bytes of workspace lstsq_sketch_solve_async needs for m columns."""
+        out = ctypes.c_size_t(0)
+        check(load().lstsq_solve_workspace_size(self.h, int(m), ctypes.byref(out)))
+        return out.value
+
+    def lstsq_solve_async(self, A, b, x, ws, result=None, stream=None):
+        """Sketch-and-solve enqueued on `stream` with no host synchronization and
+        no allocation (x, ws and the optional device result buffer of 24 bytes
+        (SOLVE_RESULT_BYTES) are caller tensors); capturable into a HIP graph."""
+        self._check_system(A, b)
+        assert x.is_cuda and x.dtype == torch.float64 and x.shape == (A.shape[1],)
+        res = _ptr(result) if result is not None else None
+        return check(load().lstsq_sketch_solve_async(self.h, A.shape[1], _ptr(A), A.stride(0), _ptr(b), _ptr(x), res,
+                                                     _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
 
     def lstsq_precond(self, A, b, tol=1e-10, maxit=100, warm_start=True, A_sketch=None, stream=None):
         """Sketch-and-precondition LSQR: returns (x, status, info dict).
