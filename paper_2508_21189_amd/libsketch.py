@@ -142,7 +142,26 @@ _DRIVER_SIGS = {
                                      ctypes.POINTER(ctypes.c_size_t)],
     "lstsq_sketch_solve_batched": [ctypes.POINTER(LsProblem), ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
                                    ctypes.c_size_t, _vp],
+    "lstsq_batched_create": [ctypes.POINTER(LsProblem), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                             ctypes.POINTER(_vp)],
+    "lstsq_batched_workspace": [_vp, ctypes.POINTER(ctypes.c_size_t)],
+    "lstsq_batched_bind": [_vp, _vp, ctypes.c_size_t, _vp],
+    "lstsq_batched_launch": [_vp, _vp],
+    "lstsq_batched_enqueue": [_vp, _vp],
+    "lstsq_batched_results": [_vp, ctypes.POINTER(LsProblem), _vp],
+    "lstsq_batched_info": [_vp, _vp],
+    "lstsq_batched_destroy": [_vp],
 }
+
+SK_BATCH_AUTOTUNE = 1
+SK_BATCH_NOTUNE = 2
+
+
+class BatchInfo(ctypes.Structure):
+    """sk_batch_info."""
+    _fields_ = [("graph_launches", _i64), ("kernel_nodes", ctypes.c_int), ("sketch_workgroups", ctypes.c_int),
+                ("solve_workgroups", ctypes.c_int), ("sketch_items", ctypes.c_int), ("reduce_items", ctypes.c_int),
+                ("tuned", ctypes.c_int), ("pad_", ctypes.c_int), ("workspace_bytes", ctypes.c_size_t)]
 
 
 SOLVE_RESULT_BYTES = 24  # sk_solve_result: int rank, int pad, double sigma_max, double sigma_min_kept
@@ -434,6 +453,61 @@ def batched_workspace_size(problems, d_per_k=4, zeta=4):
     nbytes = ctypes.c_size_t(0)
     check(load().lstsq_batched_workspace_size(arr, len(problems), d_per_k, zeta, ctypes.byref(nbytes)))
     return nbytes.value
+
+
+class BatchPlan:
+    """A batch plan (lstsq_batched_create ... destroy) over [(A, b, seed), ...]: bind() a workspace once,
+    then launch() runs the whole batch as one graph launch; results() waits and returns
+    (statuses, ranks, t_ms, status of the call). xs holds the solution vectors."""
+
+    def __init__(self, problems, d_per_k=4, zeta=4, flags=0):
+        self.arr, self.xs = _batched_array(problems)
+        self.n = len(problems)
+        self.keep = problems  # the tensors must outlive the plan
+        h = _vp()
+        check(load().lstsq_batched_create(self.arr, self.n, d_per_k, zeta, flags, ctypes.byref(h)))
+        self.h = h
+        self.ws = None
+
+    def workspace_bytes(self):
+        nbytes = ctypes.c_size_t(0)
+        check(load().lstsq_batched_workspace(self.h, ctypes.byref(nbytes)))
+        return nbytes.value
+
+    def bind(self, ws=None, stream=None):
+        if ws is None:
+            ws = torch.empty(self.workspace_bytes() + 256, dtype=torch.uint8, device="cuda")
+            off = (-ws.data_ptr()) % 256
+            ws = ws[off:]
+        self.ws = ws
+        check(load().lstsq_batched_bind(self.h, _ptr(ws), ws.numel(), _stream(stream)))
+        return ws
+
+    def launch(self, stream=None):
+        check(load().lstsq_batched_launch(self.h, _stream(stream)))
+
+    def enqueue(self, stream=None):
+        check(load().lstsq_batched_enqueue(self.h, _stream(stream)))
+
+    def results(self, stream=None):
+        rc = check(load().lstsq_batched_results(self.h, self.arr, _stream(stream)))
+        return [p.status for p in self.arr], [p.rank for p in self.arr], [p.t_ms for p in self.arr], rc
+
+    def info(self):
+        inf = BatchInfo()
+        check(load().lstsq_batched_info(self.h, ctypes.byref(inf)))
+        return inf
+
+    def close(self):
+        if self.h is not None:
+            load().lstsq_batched_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def solve_batched(problems, d_per_k=4, zeta=4, ws=None, stream=None):
