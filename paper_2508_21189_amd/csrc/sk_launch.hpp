@@ -33,6 +33,7 @@ struct RowsPlan {
   // codes
   bool idx = false;
   int nbuf = 2;  // its tile buffers (loads run nbuf - 1 tiles ahead)
+  int nparts = 1, ps = 0;  // bucket parts of a block (one wave each) and buckets per part
 };
 
 // Chooses the plan; returns SK_OK or SK_E_NOTSUP (and sets the error).

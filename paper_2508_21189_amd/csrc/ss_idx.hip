@@ -31,6 +31,12 @@
 //  * Partials go to [chunk][d][m]; reduce_partials_kernel sums them in chunk
 //    order and scales by 1/sqrt(zeta). No atomics and a fixed order of
 //    every sum: bitwise reproducible.
+//  * FP64 blocks of more buckets than one register file holds (100) are split
+//    into bucket parts, one wave each: every part's wave walks every row,
+//    adding rows of its part into their buckets and the others into dump
+//    registers that are never stored (rotating over four, so that dumped
+//    rows do not queue on one register). Each bucket still receives its rows
+//    in row order, so the sums are those of a single register file.
 #include "sk_idx.hpp"
 #include "sk_launch.hpp"
 
@@ -54,6 +60,9 @@ struct IdxArgs {
   int nbuf;        // tile buffers: loads run nbuf - 1 tiles ahead
   int off_touch;   // LDS scratch (1 KB per wave) that the code prefetch lands in
   const unsigned char* codes_touch;  // the row codes, for that prefetch only
+  // bucket parts (more buckets than one register file): parts per block
+  // and buckets per part
+  int nparts, ps;
 };
 
 // Row codes of row i = tile * R + r and block t, at base = (tile * zeta + t)
@@ -87,7 +96,46 @@ __global__ void ss_idx_plan_kernel(int64_t n, int64_t n_tiles, int R, int zeta, 
   }
 }
 
-template <typename Tin, int NREG, int LB>
+// Bucket parts: a block whose nb buckets exceed one register file is split
+// into nparts parts of ps buckets, one wave each, every wave walking all the
+// tile's rows in order. For list (tile, block t, part h), at base =
+// ((tile * zeta + t) * nparts + h) * 2R, row r's entry [base + r] is the
+// bucket's register index within part h, or, when the bucket lies in another
+// part, one of ndump dump slots (registers that are never stored; rotating
+// with the row so that consecutive dumped rows do not wait on one register);
+// [base + R + r] is the high word of the +-1.0 multiplier. Same Philox
+// reading as above.
+__global__ void ss_idx_plan_parts_kernel(int64_t n, int64_t n_tiles, int R, int zeta, uint32_t nb, int nparts,
+                                         int ps, uint32_t dump0, uint32_t ndump, uint32_t one_hi, uint32_t rpa,
+                                         uint32_t k0, uint32_t k1, uint32_t* __restrict__ codes) {
+  const int ng = (zeta + 3) / 4;
+  const int64_t total = n_tiles * R * ng;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t tr = idx / ng;  // tile * R + r = the row index i
+    const int g = (int)(idx - tr * ng);
+    const int64_t tile = tr / R;
+    const int r = (int)(tr - tile * R);
+    const uint64_t i = (uint64_t)tr;
+    U4 w = U4{0u, 0u, 0u, 0u};
+    if ((int64_t)i < n) w = philox4x32_10(U4{(uint32_t)i, (uint32_t)(i >> 32), (uint32_t)g, kTagSparseStack}, k0, k1);
+    for (int j = 0; j < 4; ++j) {
+      const int t = 4 * g + j;
+      if (t >= zeta) break;
+      const uint32_t word = word_of(w, j);
+      const int b = (int)ss_bucket(word, nb);
+      const uint32_t sw = (ss_negative(word) << 31) | one_hi;
+      for (int h = 0; h < nparts; ++h) {
+        const int rel = b - h * ps;
+        uint32_t* c = codes + ((tile * zeta + t) * nparts + h) * (int64_t)(2 * R);
+        c[r] = (rel >= 0 && rel < ps ? (uint32_t)rel : dump0 + (uint32_t)r % ndump) * rpa;
+        c[R + r] = sw;
+      }
+    }
+  }
+}
+
+template <typename Tin, int NREG, int LB, bool PARTS = false>
 __global__ void __launch_bounds__(NREG > 64 ? 512 : 1024)
     ss_idx_kernel(IdxArgs a, const uint32_t* __restrict__ codes_all) {
   using T = IdxT<Tin>;
@@ -122,7 +170,19 @@ __global__ void __launch_bounds__(NREG > 64 ? 512 : 1024)
   const int64_t r_end = min(a.n, r_begin + a.rows_per_chunk);
   const int nsub = r_end > r_begin ? (int)((r_end - r_begin + a.R - 1) / a.R) : 0;
   const int R = a.R, nb = a.nb;
-  const bool walker = wave < bpg;
+  // this wave's block (and bucket part); the index of its code list in a tile
+  int tb = t0 + wave, part = 0;
+  if constexpr (PARTS) {
+    tb = t0 + wave / a.nparts;
+    part = wave - (wave / a.nparts) * a.nparts;
+  }
+  const bool walker = PARTS ? wave < bpg * a.nparts : wave < bpg;
+  auto list_of = [&](int64_t tile) -> int64_t {
+    if constexpr (PARTS)
+      return (tile * a.zeta + tb) * a.nparts + part;
+    else
+      return tile * a.zeta + t0 + wave;
+  };
 
   AccFile f;
   acc_zero<NREG>(f);
@@ -160,7 +220,7 @@ __global__ void __launch_bounds__(NREG > 64 ? 512 : 1024)
     if (walker) {
       // (the address comes from a second copy of the codes pointer, so that
       // the restrict one never reaches an asm statement)
-      const unsigned char* csrc = a.codes_touch + ((r0 / R) * a.zeta + t0 + wave) * (int64_t)R * 8;
+      const unsigned char* csrc = a.codes_touch + list_of(r0 / R) * (int64_t)R * 8;
       const int cbytes = 8 * R;
       const uint32_t la = (uint32_t)__builtin_amdgcn_readfirstlane(
           (int)idx_lds_addr(smem + a.off_touch + wave * 1024));
@@ -192,7 +252,7 @@ __global__ void __launch_bounds__(NREG > 64 ? 512 : 1024)
       // this wave's codes for the tile (uniform address: scalar loads)
       // (a kernel argument marked restrict, never written here: the
       // compiler reads it with scalar loads)
-      const uint32_t* codes = codes_all + ((r0 / R) * a.zeta + t0 + wave) * (int64_t)(2 * R);
+      const uint32_t* codes = codes_all + list_of(r0 / R) * (int64_t)(2 * R);
       const uint32_t tbase = idx_lds_addr(smem + buf * a.buf_stride) + (uint32_t)(lane * ES);
       const int full = rv & ~(GR - 1);
       // full groups of GR rows: straight-line code, row offsets immediate;
@@ -235,10 +295,15 @@ __global__ void __launch_bounds__(NREG > 64 ? 512 : 1024)
 
   if (walker && lane < Cw) {
     Tacc* P = (Tacc*)a.P;
-    const int64_t rowbase = (int64_t)chunk * a.d + (int64_t)(t0 + wave) * nb;
+    int64_t rowbase = (int64_t)chunk * a.d + (int64_t)(t0 + wave) * nb;
+    int nstore = nb;
+    if constexpr (PARTS) {
+      rowbase = (int64_t)chunk * a.d + (int64_t)tb * nb + (int64_t)part * a.ps;
+      nstore = min(a.ps, nb - part * a.ps);
+    }
 #pragma unroll
     for (int s = 0; s < NREG / T::rpa; ++s) {
-      if (s < nb) {
+      if (s < nstore) {
         Tacc val;
         if constexpr (T::rpa == 2) {
           const uint64_t lo = acc_get<NREG>(f, 2 * s), hi = acc_get<NREG>(f, 2 * s + 1);
@@ -261,6 +326,9 @@ int env_i(const char* name, int dflt) {
   const char* v = std::getenv(name);
   return v ? std::atoi(v) : dflt;
 }
+// Dump slots of a parts plan: 8 registers (FP32 accumulators) or 4 register
+// pairs (FP64).
+int dump_slots(int dtype_in) { return dtype_in == SK_F64 ? 4 : 8; }
 // Accumulator register files compiled, and how many waves of each fit a SIMD
 // (the pinned file plus the kernel's other registers, 512 per SIMD lane).
 int idx_nreg(int dtype_in, int64_t nb) {
@@ -272,29 +340,49 @@ int idx_nreg(int dtype_in, int64_t nb) {
   return 0;
 }
 int idx_waves_per_simd(int nreg) { return nreg <= 32 ? 5 : (nreg <= 64 ? 4 : 2); }
+// Bucket parts of a block: 1 when its buckets fit one register file, else
+// (FP64 only) up to four parts (one wave each) of the 200-register file, the
+// last few slots of which are kept as the dump for the rows of the other
+// parts. Every part walks every row, so k parts cost k times the adds of one:
+// measured on 8388608 x 500 with d = 2000, zeta = 8 (250 buckets), FP64 takes
+// 30.1 ms with three parts against 34.6 ms on the sorted kernel, while FP32
+// (two parts, 12.1 ms against 11.9) and BF16 (14.4 against 12.2) do not gain
+// and stay on the sorted kernel.
+constexpr int kMaxParts = 4;
+int idx_parts(int dtype_in, int64_t nb) {
+  if (idx_nreg(dtype_in, nb) != 0) return 1;
+  if (dtype_in != SK_F64) return 0;
+  const int64_t cap = (dtype_in == SK_F64 ? 100 : 200) - dump_slots(dtype_in);
+  const int64_t np = (nb + cap - 1) / cap;
+  return np <= kMaxParts ? (int)np : 0;
+}
 }  // namespace
 
 bool idx_apply_fits(const sk_sketch* S, int dtype_in, int64_t m) {
   if (env_i("SKETCH_IDX", 1) == 0) return false;
-  return m > 4 && S->zeta >= 4 && idx_nreg(dtype_in, S->nb) != 0;
+  return m > 4 && S->zeta >= 4 && idx_parts(dtype_in, S->nb) != 0;
 }
 
 static int plan_idx_lb(const sk_sketch* S, int dtype_in, int64_t m, int load_bytes, RowsPlan* p) {
   const int es = (int)dtype_size(dtype_in);
   const int zeta = S->zeta;
-  const int nreg = idx_nreg(dtype_in, S->nb);
-  if (nreg == 0) {
+  const int nparts = idx_parts(dtype_in, S->nb);
+  if (nparts == 0) {
     set_error("sketch_apply: bucket register file too small for this block size");
     return SK_E_NOTSUP;
   }
+  const int nreg = nparts == 1 ? idx_nreg(dtype_in, S->nb) : 200;
   p->idx = true;
   p->narrow = false;
   p->jb = nreg;
+  p->nparts = nparts;
+  p->ps = (int)((S->nb + nparts - 1) / nparts);
   const int wps = idx_waves_per_simd(nreg);
   const int wmax = std::min(16, 4 * wps);
-  p->bpg = std::min(zeta, wmax);
+  // one wave per (block, part): the blocks of a group share the tile
+  p->bpg = std::min(zeta, std::max(1, wmax / nparts));
   p->n_groups = (zeta + p->bpg - 1) / p->bpg;
-  p->W = p->bpg;
+  p->W = p->bpg * nparts;
   p->H = 1;
   p->ranges = 1;
   p->per_range = (int)S->nb;
@@ -347,7 +435,8 @@ static int plan_idx_lb(const sk_sketch* S, int dtype_in, int64_t m, int load_byt
   p->n_tiles = (n + p->R - 1) / p->R;
   const size_t accb = dtype_in == SK_F64 ? 8 : 4;
   p->partial_bytes = a16((size_t)p->n_chunks * S->d * m * accb);
-  p->plan_bytes = a16((size_t)p->n_tiles * p->R * zeta * 8);
+  // codes: 2R words per (tile, block, part)
+  p->plan_bytes = a16((size_t)p->n_tiles * p->R * zeta * nparts * 8);
   return SK_OK;
 }
 
@@ -373,7 +462,7 @@ int plan_idx(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t
   return SK_E_NOTSUP;
 }
 
-template <typename Tin, int NREG, int LB>
+template <typename Tin, int NREG, int LB, bool PARTS = false>
 static int launch_idx_t(const sk_sketch* S, const RowsPlan& p, int64_t m, const void* A, int64_t lda, void* P,
                         const uint32_t* codes, hipStream_t st) {
   IdxArgs a;
@@ -397,8 +486,10 @@ static int launch_idx_t(const sk_sketch* S, const RowsPlan& p, int64_t m, const 
   a.nbuf = p.nbuf;
   a.off_touch = p.nbuf * p.rec_bytes;
   a.codes_touch = (const unsigned char*)codes;
+  a.nparts = p.nparts;
+  a.ps = p.ps;
   const int64_t grid = ((int64_t)(p.n_chunks + 7) / 8) * 8 * p.n_slabs * p.n_groups;
-  auto kern = ss_idx_kernel<Tin, NREG, LB>;
+  auto kern = ss_idx_kernel<Tin, NREG, LB, PARTS>;
   SK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes));
   {
     KernelTimer timer(S, st);
@@ -419,6 +510,7 @@ static int launch_idx_n(const sk_sketch* S, const RowsPlan& p, int64_t m, const 
     case 128:
       return launch_idx_t<Tin, 128, LB>(S, p, m, A, lda, P, codes, st);
     default:
+      if (p.nparts > 1) return launch_idx_t<Tin, 200, LB, true>(S, p, m, A, lda, P, codes, st);
       return launch_idx_t<Tin, 200, LB>(S, p, m, A, lda, P, codes, st);
   }
 }
@@ -427,11 +519,20 @@ static int launch_idx_n(const sk_sketch* S, const RowsPlan& p, int64_t m, const 
 int launch_idx_sketch(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64_t m, const void* A, int64_t lda,
                       void* ws, hipStream_t st) {
   uint32_t* codes = (uint32_t*)((unsigned char*)ws + p.partial_bytes);
-  {
+  const uint32_t one_hi = dtype_in == SK_F64 ? IdxT<double>::one_hi : IdxT<float>::one_hi;
+  const uint32_t rpa = dtype_in == SK_F64 ? 2u : 1u;
+  if (p.nparts > 1) {
     const int64_t total = p.n_tiles * p.R * ((S->zeta + 3) / 4);
     const int64_t blocks = std::min<int64_t>((total + 255) / 256, 16384);
-    const uint32_t one_hi = dtype_in == SK_F64 ? IdxT<double>::one_hi : IdxT<float>::one_hi;
-    const uint32_t rpa = dtype_in == SK_F64 ? 2u : 1u;
+    const uint32_t ndump = (uint32_t)dump_slots(dtype_in);
+    const uint32_t dump0 = (uint32_t)(200 / (int)rpa) - ndump;
+    hipLaunchKernelGGL(ss_idx_plan_parts_kernel, dim3((unsigned)std::max<int64_t>(1, blocks)), dim3(256), 0, st,
+                       S->n, p.n_tiles, p.R, S->zeta, (uint32_t)S->nb, p.nparts, p.ps, dump0, ndump, one_hi, rpa,
+                       S->k0, S->k1, codes);
+    SK_HIP(hipGetLastError());
+  } else {
+    const int64_t total = p.n_tiles * p.R * ((S->zeta + 3) / 4);
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 16384);
     hipLaunchKernelGGL(ss_idx_plan_kernel, dim3((unsigned)std::max<int64_t>(1, blocks)), dim3(256), 0, st, S->n,
                        p.n_tiles, p.R, S->zeta, (uint32_t)S->nb, one_hi, rpa, S->k0, S->k1, codes);
     SK_HIP(hipGetLastError());

@@ -87,6 +87,9 @@ CASES = [
     (30011, 40, 8000, 2, 16),  # 4000 buckets per block: five bucket ranges per block
     (20000, 16, 16384, 1, 18), # the largest block of the row apply (16384 buckets, 21 ranges)
     (4000, 5, 640, 64, 19),    # 64 blocks: the plan kernel's tile shrinks to fit its LDS
+    (20011, 100, 1200, 8, 29), # 150 buckets per block: two bucket parts of the register file
+    (12007, 500, 2000, 8, 30), # 250 buckets (the mixed-precision shape): three parts, eight slabs
+    (9001, 70, 1600, 4, 31),   # 400 buckets: four parts, one block per workgroup group
 ]
 
 
@@ -133,7 +136,8 @@ def test_apply_edge_cases(lib, n, m, d, zeta, seed):
                                              (3000, 16, 64, 8, 3), (1000, 500, 400, 8, 4),
                                              (100000, 64, 400, 8, 5), (30000, 1, 200, 4, 6),
                                              (20011, 3, 96, 8, 7), (20000, 64, 2048, 1, 8),
-                                             (7001, 24, 6000, 2, 9)])
+                                             (7001, 24, 6000, 2, 9), (9000, 130, 3200, 8, 10),
+                                             (15013, 64, 3200, 4, 11)])
 def test_apply_lowprec_parity(lib, dtype, n, m, d, zeta, seed):
     rng = np.random.default_rng(seed)
     A = torch.from_numpy(rng.standard_normal((n, m))).cuda().to(torch.float32).to(dtype)
