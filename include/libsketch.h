@@ -121,8 +121,7 @@ int sketch_info(sketch_t S, int* kind, int64_t* d, int64_t* n, int* zeta, uint64
  * (G, d x n F32, written into the workspace and one SGEMM; needs
  * d * n * 4 <= 8 GB). SRTT and SparseRTT take F64 input (F64 output).
  * The result is deterministic (the same inputs give bitwise identical SA on
- * every run: no atomics, fixed summation order), except the F32 Gaussian
- * path, whose GEMM follows rocBLAS.
+ * every run: no atomics, fixed summation order).
  */
 int sketch_apply(sketch_t S, int dtype_in, int layout, int64_t m, const void* A, int64_t lda,
                  int dtype_out, void* SA, int64_t ldsa, void* ws, size_t ws_bytes, void* stream);
@@ -142,11 +141,10 @@ int sketch_apply(sketch_t S, int dtype_in, int layout, int64_t m, const void* A,
  *     the same memory (A is then the column-major n x rows matrix A^T): two
  *     transposes through the workspace and the row-mode apply.
  *   Gaussian: F64 or F32 input; G (d x n) is generated into the workspace and
- *     Y = A G^T is one GEMM on the matrix cores (F32 GEMM for F32 input).
+ *     Y = A G^T is one GEMM on the matrix cores (sk_gemm; F32 for F32 input).
  *   SRTT and SparseRTT: one Walsh-Hadamard transform per row in LDS; needs
  *     npad * element size <= 160 KB (npad <= 2^15 for F32/BF16, 2^14 for F64).
- * Deterministic for SparseStack, SRTT and SparseRTT; the Gaussian GEMM
- * follows rocBLAS.
+ * Deterministic for every kind (no atomics, fixed summation order).
  */
 int sketch_apply_T(sketch_t S, int dtype_in, int layout, int64_t rows, const void* A, int64_t lda, int dtype_out,
                    void* Y, int64_t ldy, void* ws, size_t ws_bytes, void* stream);
@@ -540,6 +538,24 @@ typedef struct {
 
 int nystrom_psd(sketch_t S, int dtype, const void* A, int64_t lda, double* U, int64_t ldu, double* lambda,
                 sk_nystrom_info* info, void* stream);
+
+/*
+ * The library's dense GEMM on the matrix cores (v_mfma_f32_16x16x4f32 for
+ * SK_F32, v_mfma_f64_16x16x4f64 for SK_F64), used by the low-rank drivers
+ * (Alg. 1 and the Nystrom variants: Y^T Y, Y R^-1, Q^T A, Q U) and by the
+ * materialized Gaussian sketch: row-major C (M x N, ldc >= N) =
+ * alpha op(A) op(B) + beta C, op(A) M x K and op(B) K x N; A is M x K
+ * (lda >= K) or, with transA, K x M (lda >= M); B is K x N (ldb >= N) or,
+ * with transB, N x K (ldb >= K). beta = 0 does not read C. Long K with few
+ * output tiles is split over workgroups whose partial sums are added in a
+ * fixed order through the workspace (ws_bytes >= sk_gemm_workspace_size;
+ * NULL is accepted when that size is 0): deterministic. Asynchronous on
+ * stream; allocates nothing.
+ */
+int sk_gemm_workspace_size(int dtype, int64_t M, int64_t N, int64_t K, size_t* bytes);
+int sk_gemm(int dtype, int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const void* A,
+            int64_t lda, const void* B, int64_t ldb, double beta, void* C, int64_t ldc, void* ws, size_t ws_bytes,
+            void* stream);
 
 #ifdef __cplusplus
 }

@@ -111,7 +111,9 @@ struct sk_sketch {
   void* dws = nullptr;
   size_t dws_bytes = 0;
   void* h_pinned = nullptr;
-  void* blas = nullptr;  // rocBLAS handle of the low-rank driver (created on first use)
+  // split-K partial sums of the low-rank drivers' GEMMs (grown on first use)
+  void* gws = nullptr;
+  size_t gws_bytes = 0;
   // optional timing of the dominant kernel of each call (sketch_timing)
   mutable bool timing = false;
   mutable std::vector<std::pair<hipEvent_t, hipEvent_t>> events;

@@ -151,6 +151,9 @@ _DRIVER_SIGS = {
     "lstsq_batched_results": [_vp, ctypes.POINTER(LsProblem), _vp],
     "lstsq_batched_info": [_vp, _vp],
     "lstsq_batched_destroy": [_vp],
+    "sk_gemm_workspace_size": [ctypes.c_int, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
+    "sk_gemm": [ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64, _i64, _i64, ctypes.c_double, _vp, _i64, _vp, _i64,
+                ctypes.c_double, _vp, _i64, _vp, ctypes.c_size_t, _vp],
 }
 
 SK_BATCH_AUTOTUNE = 1
@@ -508,6 +511,26 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+def gemm(A, B, transA=False, transB=False, alpha=1.0, beta=0.0, C=None, stream=None):
+    """sk_gemm: C = alpha op(A) op(B) + beta C for 2-D row-major CUDA tensors (float32 or float64; rows may be
+    padded: stride(1) == 1). Returns C."""
+    dt = _DT[A.dtype]
+    assert A.dtype == B.dtype and A.is_cuda and B.is_cuda and A.stride(1) == 1 and B.stride(1) == 1
+    M = A.shape[1] if transA else A.shape[0]
+    K = A.shape[0] if transA else A.shape[1]
+    N = B.shape[0] if transB else B.shape[1]
+    assert (B.shape[1] if transB else B.shape[0]) == K
+    if C is None:
+        C = torch.zeros(M, N, dtype=A.dtype, device=A.device)
+    assert C.shape == (M, N) and C.stride(1) == 1 and C.dtype == A.dtype
+    nbytes = ctypes.c_size_t(0)
+    check(load().sk_gemm_workspace_size(dt, M, N, K, ctypes.byref(nbytes)))
+    ws = torch.empty(max(1, nbytes.value), dtype=torch.uint8, device=A.device)
+    check(load().sk_gemm(dt, int(transA), int(transB), M, N, K, float(alpha), _ptr(A), A.stride(0), _ptr(B),
+                         B.stride(0), float(beta), _ptr(C), C.stride(0), _ptr(ws), nbytes.value, _stream(stream)))
+    return C
 
 
 def solve_batched(problems, d_per_k=4, zeta=4, ws=None, stream=None):
