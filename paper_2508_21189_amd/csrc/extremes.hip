@@ -13,15 +13,16 @@
 // G v = S^T (S v) without forming G:
 //  * S v (d x n times n): a CSR form of S built once per call: the n*zeta
 //    (row, column) pairs from the Philox hash, sorted by row with a stable
-//    radix sort (hipCUB), so each row adds its entries in column order
-//    (deterministic), one thread per row;
+//    least-significant-digit radix sort (8-bit digits; per-block digit
+//    counts, one scan, a scatter in which each wave ranks equal digits by
+//    ballot and keeps per-digit running positions, so input order is kept),
+//    so each row adds its entries in column order (deterministic), one
+//    thread per row;
 //  * S^T y: the hash-based adjoint kernel (each column gathers its zeta
 //    entries).
 // Dot products reduce in a fixed order (per-block partial sums, then every
 // block re-adds the partials in order), so the estimate is bitwise
 // reproducible.
-#include <hipcub/hipcub.hpp>
-
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -51,6 +52,96 @@ __global__ void ext_pairs_kernel(int64_t n, int zeta, uint32_t nb, uint32_t k0, 
         }
       }
     }
+  }
+}
+
+// ---- stable LSD radix sort of (key, value) pairs, 8-bit digits
+constexpr int kRsBlocks = 1024;  // element ranges (one workgroup each)
+
+// Elements of range b: [b * per, min(N, (b + 1) * per)).
+__global__ void __launch_bounds__(256) rs_count_kernel(int64_t N, int64_t per, const uint32_t* __restrict__ keys,
+                                                       int shift, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[256];
+  const int b = blockIdx.x;
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t lo = (int64_t)b * per, hi = min(N, lo + per);
+  for (int64_t e = lo + threadIdx.x; e < hi; e += 256) atomicAdd(&h[(keys[e] >> shift) & 255u], 1u);
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * kRsBlocks + b] = h[threadIdx.x];  // digit-major
+}
+
+// Exclusive prefix sum of one digit's counts over the ranges (workgroup g
+// for digit g; kRsBlocks threads): hist[g][b] becomes the number of
+// elements of digit g in ranges before b, tot[g] the digit's total.
+__global__ void __launch_bounds__(kRsBlocks) rs_scan_kernel(uint32_t* __restrict__ hist, uint32_t* __restrict__ tot) {
+  __shared__ uint32_t s[kRsBlocks];
+  const int t = threadIdx.x;
+  uint32_t* h = hist + (int64_t)blockIdx.x * kRsBlocks;
+  const uint32_t x = h[t];
+  s[t] = x;
+  __syncthreads();
+  for (int off = 1; off < kRsBlocks; off <<= 1) {
+    const uint32_t y = t >= off ? s[t - off] : 0u;
+    __syncthreads();
+    s[t] += y;
+    __syncthreads();
+  }
+  h[t] = s[t] - x;
+  if (t == kRsBlocks - 1) tot[blockIdx.x] = s[t];
+}
+
+// Scatter of range b by one wave, in input order, 64 elements at a time: the
+// lanes holding the same digit are found by 8 ballots; a lane's position is
+// its digit's running position plus the number of lower lanes with that
+// digit, and the highest of them advances the running position.
+__global__ void __launch_bounds__(64) rs_scatter_kernel(int64_t N, int64_t per, const uint32_t* __restrict__ keys,
+                                                        const uint32_t* __restrict__ vals, int shift,
+                                                        const uint32_t* __restrict__ hist,
+                                                        const uint32_t* __restrict__ tot,
+                                                        uint32_t* __restrict__ okeys, uint32_t* __restrict__ ovals) {
+  __shared__ uint32_t run[256];
+  const int b = blockIdx.x, lane = threadIdx.x;
+  // digits 4 lane .. 4 lane + 3: their start = totals of the lower digits
+  uint32_t t4[4], acc = 0;
+  for (int j = 0; j < 4; ++j) {
+    t4[j] = tot[4 * lane + j];
+    acc += t4[j];
+  }
+  uint32_t incl = acc;  // inclusive scan of the lanes' sums
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
+  }
+  uint32_t start = incl - acc;
+  for (int j = 0; j < 4; ++j) {
+    const int g = 4 * lane + j;
+    run[g] = start + hist[(int64_t)g * kRsBlocks + b];
+    start += t4[j];
+  }
+  __syncthreads();
+  const int64_t lo = (int64_t)b * per, hi = min(N, lo + per);
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int64_t c = lo; c < hi; c += 64) {
+    const int64_t e = c + lane;
+    const bool valid = e < hi;
+    const uint32_t k = valid ? keys[e] : 0u;
+    const uint32_t v = valid ? vals[e] : 0u;
+    const uint32_t dg = (k >> shift) & 255u;
+    uint64_t same = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const uint64_t ones = __ballot(valid && ((dg >> bit) & 1u));
+      same &= ((dg >> bit) & 1u) ? ones : ~ones;
+    }
+    if (valid) {
+      const uint32_t pos = run[dg] + (uint32_t)__popcll(same & below);
+      okeys[pos] = k;
+      ovals[pos] = v;
+    }
+    __syncthreads();  // every lane has read run[] before it advances
+    if (valid && (same >> lane) == 1ull) run[dg] += (uint32_t)__popcll(same);
+    __syncthreads();
   }
 }
 
@@ -281,9 +372,7 @@ extern "C" int sketch_sv_extremes(sketch_t S, int steps, uint64_t start_seed, do
   // workspace: the sort's buffers, CSR, Lanczos vectors and scalars
   int end_bit = 1;
   while (end_bit < 32 && ((uint64_t)1 << end_bit) < (uint64_t)d) ++end_bit;
-  size_t sort_tmp = 0;
-  SK_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_tmp, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-                                            (const uint32_t*)nullptr, (uint32_t*)nullptr, (int)N, 0, end_bit, st));
+  const size_t sort_tmp = (size_t)256 * (kRsBlocks + 1) * sizeof(uint32_t);
   ExtCarve cv;
   auto carve = [&](ExtCarve& c, uint32_t** k0p, uint32_t** k1p, uint32_t** v0p, uint32_t** v1p, char** tmp,
                    int64_t** rowptr, double** v, double** vp, double** w, double** y, double** part, double** part2,
@@ -323,7 +412,33 @@ extern "C" int sketch_sv_extremes(sketch_t S, int steps, uint64_t start_seed, do
   const unsigned g1 = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384));
   hipLaunchKernelGGL(ext_pairs_kernel, dim3(g1), dim3(256), 0, st, n, zeta, (uint32_t)S->nb, S->k0, S->k1, keys, vals);
   SK_HIP(hipGetLastError());
-  SK_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, sort_tmp, keys, keys2, vals, vals2, (int)N, 0, end_bit, st));
+  {
+    // passes over 8 bits at a time, ping-ponging; the sorted pairs end in
+    // keys2 / vals2
+    const int passes = (end_bit + 7) / 8;
+    const int64_t per = (N + kRsBlocks - 1) / kRsBlocks;
+    uint32_t* hist = (uint32_t*)tmp;
+    uint32_t* tot = hist + 256 * kRsBlocks;
+    // an odd number of passes from keys / vals ends in keys2 / vals2; for
+    // an even number the input is first copied to keys2 / vals2 and sorted
+    // from there
+    uint32_t *ki = keys, *vi = vals, *ko = keys2, *vo = vals2;
+    if (passes % 2 == 0) {
+      SK_HIP(hipMemcpyAsync(keys2, keys, N * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+      SK_HIP(hipMemcpyAsync(vals2, vals, N * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+      std::swap(ki, ko);
+      std::swap(vi, vo);
+    }
+    for (int p = 0; p < passes; ++p) {
+      hipLaunchKernelGGL(rs_count_kernel, dim3(kRsBlocks), dim3(256), 0, st, N, per, (const uint32_t*)ki, 8 * p, hist);
+      hipLaunchKernelGGL(rs_scan_kernel, dim3(256), dim3(kRsBlocks), 0, st, hist, tot);
+      hipLaunchKernelGGL(rs_scatter_kernel, dim3(kRsBlocks), dim3(64), 0, st, N, per, (const uint32_t*)ki,
+                         (const uint32_t*)vi, 8 * p, (const uint32_t*)hist, (const uint32_t*)tot, ko, vo);
+      SK_HIP(hipGetLastError());
+      std::swap(ki, ko);
+      std::swap(vi, vo);
+    }
+  }
   const unsigned g2 = (unsigned)std::max<int64_t>(1, std::min<int64_t>((N + 256) / 256, 16384));
   hipLaunchKernelGGL(ext_rowptr_kernel, dim3(g2), dim3(256), 0, st, N, (const uint32_t*)keys2, d, rowptr);
   SK_HIP(hipGetLastError());
