@@ -42,6 +42,7 @@ int plan_rows(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_
 // The bucket-indexed apply (ss_idx.hip): whether it takes this input, its
 // plan, and the sketch kernel writing the partials P.
 bool idx_apply_fits(const sk_sketch* S, int dtype_in, int64_t m);
+int launch_idx_codes(const sk_sketch* S, int dtype_in, int64_t n_tiles, int R, uint32_t* codes, hipStream_t st);
 int plan_idx(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t lda, RowsPlan* plan);
 int launch_idx_sketch(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64_t m, const void* A, int64_t lda,
                       void* ws, hipStream_t st);
@@ -54,6 +55,12 @@ bool cols_kernel_fits(const sk_sketch* S, int dtype_in);
 int cols_workspace(const sk_sketch* S, int dtype_in, size_t* bytes);
 int launch_cols_apply(const sk_sketch* S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out,
                       void* Y, int64_t ldy, void* ws, size_t ws_bytes, hipStream_t st);
+// its bucket-indexed kernel (ss_cols_idx.hip), taken when a block's
+// accumulators fit one register file (A == NULL: for workspace queries)
+bool cols_idx_fits(const sk_sketch* S, int dtype_in, const void* A, int64_t lda);
+size_t cols_idx_workspace(const sk_sketch* S, int dtype_in);
+int launch_cols_idx(const sk_sketch* S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out, void* Y,
+                    int64_t ldy, void* ws, size_t ws_bytes, hipStream_t st);
 
 int launch_pattern(const sk_sketch* S, int32_t* bucket, int8_t* sign, hipStream_t st);
 int launch_adjoint(const sk_sketch* S, int64_t m, const double* Y, int64_t ldy, double* Z, int64_t ldz,

@@ -414,7 +414,8 @@ int cols_workspace(const sk_sketch* S, int dtype_in, size_t* bytes) {
   ColsPlan p;
   int rc = cols_plan(S, dtype_in, &p);
   if (rc != SK_OK) return rc;
-  *bytes = p.plan_bytes;
+  // either kernel's workspace: the bucket-indexed one's codes or the plan
+  *bytes = std::max(p.plan_bytes, cols_idx_fits(S, dtype_in, nullptr, 0) ? cols_idx_workspace(S, dtype_in) : 0);
   return SK_OK;
 }
 
@@ -479,6 +480,8 @@ static int launch_cols_jb(const sk_sketch* S, const ColsPlan& p, int64_t rows, c
 
 int launch_cols_apply(const sk_sketch* S, int dtype_in, int64_t rows, const void* A, int64_t lda, int dtype_out,
                       void* Y, int64_t ldy, void* ws, size_t ws_bytes, hipStream_t st) {
+  if (cols_idx_fits(S, dtype_in, A, lda))
+    return launch_cols_idx(S, dtype_in, rows, A, lda, dtype_out, Y, ldy, ws, ws_bytes, st);
   ColsPlan p;
   int rc = cols_plan(S, dtype_in, &p);
   if (rc != SK_OK) return rc;

@@ -515,6 +515,19 @@ static int launch_idx_n(const sk_sketch* S, const RowsPlan& p, int64_t m, const 
   }
 }
 
+// Codes of the n indices of S in tiles of R (the plan kernel above): used
+// by the column-mode kernel, whose tiles run over the columns of A.
+int launch_idx_codes(const sk_sketch* S, int dtype_in, int64_t n_tiles, int R, uint32_t* codes, hipStream_t st) {
+  const uint32_t one_hi = dtype_in == SK_F64 ? IdxT<double>::one_hi : IdxT<float>::one_hi;
+  const uint32_t rpa = dtype_in == SK_F64 ? 2u : 1u;
+  const int64_t total = n_tiles * R * ((S->zeta + 3) / 4);
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 16384);
+  hipLaunchKernelGGL(ss_idx_plan_kernel, dim3((unsigned)std::max<int64_t>(1, blocks)), dim3(256), 0, st, S->n, n_tiles,
+                     R, S->zeta, (uint32_t)S->nb, one_hi, rpa, S->k0, S->k1, codes);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
 // Workspace: the partials (partial_bytes), then the row codes (plan_bytes).
 int launch_idx_sketch(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64_t m, const void* A, int64_t lda,
                       void* ws, hipStream_t st) {

