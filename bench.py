@@ -217,9 +217,14 @@ def lsqr_mixed(libsketch, inputs, torch, reps, tol=1e-10, exact=True):
     x64 = None
     sols = {}
     out["apply_roofline"] = {}
+    # the apply kernel each precision takes at d/zeta = 250 buckets a block:
+    # FP64 the bucket-indexed kernel in three bucket parts, FP32 / BF16 the
+    # sorted kernel (BF16 rows of 1000 B: 4-byte loads)
+    kern = {"f64": "ss_idx_kernel<double,200,16,parts>", "f32": "ss_rows_kernel<float,64,16>",
+            "bf16": "ss_rows_kernel<bf16,64,4>"}
     for name, dt in (("f64", None), ("f32", torch.float32), ("bf16", torch.bfloat16)):
         As = A.to(dt) if dt is not None else None
-        out["apply_roofline"][name] = apply_roofline(S, As if As is not None else A, torch)
+        out["apply_roofline"][name] = apply_roofline(S, As if As is not None else A, torch, kernel=kern[name])
         xs = []
         out[name] = _solve_stats(libsketch, torch, S, A, b, reps, tol, As, keep_x=xs)
         sols[name] = xs[0]
@@ -290,7 +295,8 @@ def rsvd_variants(libsketch, inputs, torch, reps):
         S = libsketch.Sketch(kind, k, cols, zeta, SKETCH_SEED + 2)
         if kind == "sparsestack":
             # the column-mode apply Y = A S^T that the RSVD's sketch step runs
-            out["apply_roofline_colmode"] = apply_roofline(S, A, torch, transpose=True)
+            out["apply_roofline_colmode"] = apply_roofline(S, A, torch, transpose=True,
+                                                           kernel="ss_cols_idx_kernel<float,64,2>")
         S.rsvd(A)
         walls, infos = [], []
         for _ in range(reps):
