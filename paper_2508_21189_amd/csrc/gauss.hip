@@ -89,12 +89,14 @@ __device__ inline void gauss_operands(int64_t kb, int64_t i_end, uint32_t q, int
 // that the compiler's memory-counter bookkeeping does not make the MFMA
 // operand reads of the other buffer wait for them; the kernel waits for them
 // explicitly before the barrier that publishes the tile. M0 is saved and
-// restored around the load.
+// restored around the load, with the one wait state the ISA asks for between
+// a scalar write of M0 and an LDS-DMA load.
 __device__ inline void g_dma16(const void* gsrc, uint32_t lds_addr) {
   uint32_t saved;
   asm volatile(
       "s_mov_b32 %0, m0\n\t"
       "s_mov_b32 m0, %1\n\t"
+      "s_nop 0\n\t"
       "global_load_lds_dwordx4 %2, off\n\t"
       "s_mov_b32 m0, %0"
       : "=&s"(saved)
@@ -106,6 +108,7 @@ __device__ inline void g_dma4(const void* gsrc, uint32_t lds_addr) {
   asm volatile(
       "s_mov_b32 %0, m0\n\t"
       "s_mov_b32 m0, %1\n\t"
+      "s_nop 0\n\t"
       "global_load_lds_dword %2, off\n\t"
       "s_mov_b32 m0, %0"
       : "=&s"(saved)

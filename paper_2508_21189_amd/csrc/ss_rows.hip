@@ -43,12 +43,14 @@ __device__ inline void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memor
 // compiler's memory-counter bookkeeping does not make every later LDS access
 // wait for them (it cannot tell that they target the other tile buffer); the
 // kernel waits for them explicitly (wait_dma) before the barrier that
-// publishes the tile. M0 is saved and restored around the load.
+// publishes the tile. M0 is saved and restored around the load, with the one wait
+// state the ISA asks for between a scalar write of M0 and an LDS-DMA load.
 __device__ inline void dma_to_lds16(const void* gsrc, uint32_t lds_addr) {
   uint32_t saved;
   asm volatile(
       "s_mov_b32 %0, m0\n\t"
       "s_mov_b32 m0, %1\n\t"
+      "s_nop 0\n\t"
       "global_load_lds_dwordx4 %2, off\n\t"
       "s_mov_b32 m0, %0"
       : "=&s"(saved)
@@ -60,6 +62,7 @@ __device__ inline void dma_to_lds4(const void* gsrc, uint32_t lds_addr) {
   asm volatile(
       "s_mov_b32 %0, m0\n\t"
       "s_mov_b32 m0, %1\n\t"
+      "s_nop 0\n\t"
       "global_load_lds_dword %2, off\n\t"
       "s_mov_b32 m0, %0"
       : "=&s"(saved)

@@ -109,6 +109,24 @@ def test_apply_T_bucket_indexed(lib, monkeypatch, dtype, rows, n, d, zeta, seed)
         assert np.all(np.abs(old - ref) <= bound + extra)
 
 
+@pytest.mark.parametrize("dtype,off,pad", [(torch.float32, 1, 7), (torch.float64, 3, 5), (torch.float32, 0, 64)])
+def test_apply_T_bucket_indexed_strided(lib, dtype, off, pad):
+    """Rows of A inside a wider array (lda = n + pad) that starts off elements in: the bucket-indexed column kernel
+    takes any 4-byte aligned layout and reads only the n columns of each row."""
+    rows, n, d, zeta, seed = 150, 1111, 128, 8, 21
+    rng = np.random.default_rng(seed)
+    big = torch.from_numpy(rng.standard_normal((rows, n + pad + off))).to(dtype).cuda()
+    A = big[:, off:off + n]
+    assert A.stride(0) == n + pad + off
+    S = lib.Sketch("sparsestack", d, n, zeta, seed)
+    got = S.apply_T(A, out_dtype=torch.float64)
+    assert torch.equal(got, S.apply_T(A.contiguous(), out_dtype=torch.float64))
+    A64 = A.to(torch.float64).cpu().numpy()
+    u = 2.0 ** -53 if dtype == torch.float64 else 2.0 ** -24
+    ref = sk.sparsestack_apply_T(A64, d, zeta, seed)
+    assert np.all(np.abs(got.cpu().numpy() - ref) <= _bound_T(A64, d, zeta, seed, u))
+
+
 @pytest.mark.parametrize("kind,dtype,rows,n,d,zeta", [("sparsestack", torch.float64, 130, 777, 40, 4),
                                                      ("sparsestack", torch.float64, 70, 3001, 4000, 2),
                                                      ("sparsestack", torch.float32, 200, 1000, 64, 8),
