@@ -337,12 +337,17 @@ typedef struct {
  * certainly passes the rank test of Alg. 3 (s_k > 5 eps s_1), and its
  * truncated-SVD solution is x = R^-1 c, computed directly; the others are
  * redone with the SVD of R in a second pass, exactly as lstsq_sketch_solve
- * does. The problems are spread round-robin over up to 32 streams that
- * the call creates (default priority) and that start after the work already
- * queued on `stream`; each stream runs its problems back to back in its own
- * slot of one workspace (ws, ws_bytes >= lstsq_batched_workspace_size; NULL
- * to allocate and free one inside the call). The call waits for all of them
- * once per pass and returns with every x written. Every problem is validated
+ * does. The problems' sketches run back to back on one stream that the
+ * call creates (default priority) and that starts after the work already
+ * queued on `stream`, each in the same slot of one workspace (ws, ws_bytes >=
+ * lstsq_batched_workspace_size; NULL to allocate and free one inside the
+ * call); [S A | S b] of every problem with d <= 1024 and k <= 512 goes to its
+ * own buffers, and their Householder QRs, R^-1 and certified solves then run
+ * for all of them together on `stream`, one launch per panel step (the other
+ * problems take those steps one by one on the call's stream). The call waits
+ * once per pass and returns with every x written. A problem's t_ms runs from
+ * the start of its sketch to the end of the batched solve (or of its own
+ * solve). Every problem is validated
  * before any work is queued: if one is invalid, its status is SK_E_INVAL,
  * nothing runs, and SK_E_INVAL is returned; if the apply refuses one's data
  * layout (more than 4 columns whose rows are not 4-byte multiples, as BF16

@@ -146,9 +146,8 @@ __global__ void __launch_bounds__(1024) hh_panel_kernel(double* __restrict__ W, 
 // products (v^T y for the later columns, v_q^T v for the Gram entries of T),
 // then the update in registers. The panel is written back at the end.
 template <int NB, int RPT, int NTH>
-__global__ void __launch_bounds__(NTH) hh_panel_reg_kernel(double* __restrict__ W, int64_t ldw, int64_t d, int k,
-                                                           int nbp, double* __restrict__ tau,
-                                                           double* __restrict__ T) {
+__device__ __forceinline__ void hh_panel_reg_dev(double* __restrict__ W, int64_t ldw, int64_t d, int k, int nbp,
+                                                 double* __restrict__ tau, double* __restrict__ T) {
   __shared__ double red[NTH / 64][NB + 2];
   __shared__ double vals[NB + 2];
   __shared__ double G[kPanel][kPanel + 1];
@@ -275,14 +274,21 @@ __global__ void __launch_bounds__(NTH) hh_panel_reg_kernel(double* __restrict__ 
   }
 }
 
+template <int NB, int RPT, int NTH>
+__global__ void __launch_bounds__(NTH) hh_panel_reg_kernel(double* __restrict__ W, int64_t ldw, int64_t d, int k,
+                                                           int nbp, double* __restrict__ tau,
+                                                           double* __restrict__ T) {
+  hh_panel_reg_dev<NB, RPT, NTH>(W, ldw, d, k, nbp, tau, T);
+}
+
 // Trailing update of one column y (index k + nbp + blockIdx.x) of W:
 // y <- y - V T^T V^T y, with V the panel's reflectors (rows >= k).
-__global__ void __launch_bounds__(256) hh_trail_kernel(double* __restrict__ W, int64_t ldw, int64_t d, int k, int nbp,
-                                                       int first_col, const double* __restrict__ T) {
+__device__ __forceinline__ void hh_trail_dev(double* __restrict__ W, int64_t ldw, int64_t d, int k, int nbp,
+                                             int first_col, const double* __restrict__ T, unsigned col) {
   __shared__ double red[4][kPanel];
   __shared__ double z[kPanel], z2[kPanel];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* y = W + (int64_t)(first_col + blockIdx.x) * ldw;
+  double* y = W + (int64_t)(first_col + col) * ldw;
   const double* V = W + (int64_t)k * ldw;
   // z = V^T y
   double acc[kPanel];
@@ -326,18 +332,27 @@ __global__ void __launch_bounds__(256) hh_trail_kernel(double* __restrict__ W, i
   }
 }
 
+__global__ void __launch_bounds__(256) hh_trail_kernel(double* __restrict__ W, int64_t ldw, int64_t d, int k, int nbp,
+                                                       int first_col, const double* __restrict__ T) {
+  hh_trail_dev(W, ldw, d, k, nbp, first_col, T, blockIdx.x);
+}
+
 // R (k x k row-major, upper) and c = (Q^T rhs)[0:k] from the factored W.
-__global__ void extract_r_kernel(const double* __restrict__ W, int64_t ldw, int k, int has_rhs,
-                                 double* __restrict__ R, double* __restrict__ c) {
+__device__ __forceinline__ void extract_r_dev(const double* __restrict__ W, int64_t ldw, int k, int has_rhs,
+                                              double* __restrict__ R, double* __restrict__ c, unsigned bx, unsigned gx) {
   const int64_t total = (int64_t)k * k;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t idx = bx * (int64_t)blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gx * blockDim.x) {
     const int64_t r = idx / k, col = idx - r * k;
     R[idx] = col >= r ? W[col * ldw + r] : 0.0;
   }
   if (has_rhs)
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < k; r += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t r = bx * (int64_t)blockDim.x + threadIdx.x; r < k; r += (int64_t)gx * blockDim.x)
       c[r] = W[(int64_t)k * ldw + r];
+}
+
+__global__ void extract_r_kernel(const double* __restrict__ W, int64_t ldw, int k, int has_rhs,
+                                 double* __restrict__ R, double* __restrict__ c) {
+  extract_r_dev(W, ldw, k, has_rhs, R, c, blockIdx.x, gridDim.x);
 }
 
 // X = R^{-1} for upper-triangular R (k x k row-major), and XT = X^T. One
@@ -382,9 +397,9 @@ __device__ inline double rl64d(double v, int lane) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-__global__ void __launch_bounds__(64) trinv_diag_kernel(const double* __restrict__ R, int k, double* __restrict__ X) {
+__device__ __forceinline__ void trinv_diag_dev(const double* __restrict__ R, int k, double* __restrict__ X, unsigned bx) {
   const int c = threadIdx.x;
-  const int j0 = blockIdx.x * kTb;
+  const int j0 = bx * kTb;
   const int b = min(kTb, k - j0);
   double col[kTb];  // col[r] = R[j0 + r][j0 + c]
 #pragma unroll
@@ -408,12 +423,15 @@ __global__ void __launch_bounds__(64) trinv_diag_kernel(const double* __restrict
   }
 }
 
-__global__ void __launch_bounds__(1024) trinv_cols_kernel(const double* __restrict__ R, int k, double* __restrict__ X,
-                                                          double* __restrict__ XT) {
-  constexpr int XS = kTb + 1;  // LDS row stride of the column block
-  extern __shared__ double Xs[];  // [k][XS]
+__global__ void __launch_bounds__(64) trinv_diag_kernel(const double* __restrict__ R, int k, double* __restrict__ X) {
+  trinv_diag_dev(R, k, X, blockIdx.x);
+}
+
+__device__ __forceinline__ void trinv_cols_dev(const double* __restrict__ R, int k, double* __restrict__ X,
+                                               double* __restrict__ XT, double* Xs, unsigned bx) {
+  constexpr int XS = kTb + 1;  // LDS row stride of the column block (Xs: [k][XS])
   __shared__ double T[kTb][kTb + 1];
-  const int J = blockIdx.x, j0 = J * kTb, bj = min(kTb, k - j0);
+  const int J = (int)bx, j0 = J * kTb, bj = min(kTb, k - j0);
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int idx = tid; idx < k * kTb; idx += nt) {
     const int r = idx / kTb, c = idx - r * kTb;
@@ -442,6 +460,50 @@ __global__ void __launch_bounds__(1024) trinv_cols_kernel(const double* __restri
     const int cc = idx / k, rr = idx - cc * k;
     if (cc < bj) XT[(int64_t)(j0 + cc) * k + rr] = Xs[rr * XS + cc];
   }
+}
+
+__global__ void __launch_bounds__(1024) trinv_cols_kernel(const double* __restrict__ R, int k, double* __restrict__ X,
+                                                          double* __restrict__ XT) {
+  extern __shared__ double Xs[];  // [k][kTb + 1]
+  trinv_cols_dev(R, k, X, XT, Xs, blockIdx.x);
+}
+
+// ---- the same steps for a batch of small problems, one launch per step:
+// problem p = blockIdx.y (blockIdx.x for the one-workgroup panel); a problem
+// whose k is past the step leaves at once. Every problem has d <= 1024 rows
+// (the 32-column register panel) and k <= 512 (the blocked inverse).
+
+__global__ void __launch_bounds__(512) hh_panel_batched_kernel(const QrBatch* __restrict__ B, int c) {
+  const QrBatch& p = B[blockIdx.x];
+  if (c >= p.k) return;
+  hh_panel_reg_dev<32, 2, 512>(p.W, p.ldw, p.d, c, min(kPanel, p.k - c), p.tau, p.T + (int64_t)(c / kPanel) * kPanel * kPanel);
+}
+
+__global__ void __launch_bounds__(256) hh_trail_batched_kernel(const QrBatch* __restrict__ B, int c) {
+  const QrBatch& p = B[blockIdx.y];
+  if (c >= p.k) return;
+  const int nbp = min(kPanel, p.k - c), first = c + nbp;
+  if ((int)blockIdx.x >= p.k + 1 - first) return;  // the trailing columns, b included
+  hh_trail_dev(p.W, p.ldw, p.d, c, nbp, first, p.T + (int64_t)(c / kPanel) * kPanel * kPanel, blockIdx.x);
+}
+
+__global__ void extract_r_batched_kernel(const QrBatch* __restrict__ B) {
+  const QrBatch& p = B[blockIdx.y];
+  if (p.k == 0) return;
+  extract_r_dev(p.W, p.ldw, p.k, 1, p.R, p.c, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(64) trinv_diag_batched_kernel(const QrBatch* __restrict__ B) {
+  const QrBatch& p = B[blockIdx.y];
+  if ((int)blockIdx.x * kTb >= p.k) return;
+  trinv_diag_dev(p.R, p.k, p.X, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(1024) trinv_cols_batched_kernel(const QrBatch* __restrict__ B) {
+  extern __shared__ double Xs[];  // [k][kTb + 1], sized for the batch's largest k
+  const QrBatch& p = B[blockIdx.y];
+  if ((int)blockIdx.x * kTb >= p.k) return;
+  trinv_cols_dev(p.R, p.k, p.X, p.XT, Xs, blockIdx.x);
 }
 
 __global__ void fill_kernel(double* __restrict__ x, int64_t n, double value) {
@@ -516,6 +578,35 @@ int launch_trinv(const double* R, int k, double* X, double* XT, hipStream_t st) 
   } else {
     hipLaunchKernelGGL(trinv_upper_kernel, dim3(k), dim3(64), (size_t)k * sizeof(double), st, R, k, X, XT);
   }
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+int qr_trinv_batched(const QrBatch* B, int nprob, int kmax, hipStream_t st) {
+  if (nprob <= 0 || kmax <= 0) return SK_OK;
+  if (kmax > 512) {
+    set_error("batched QR: at most 512 columns");
+    return SK_E_NOTSUP;
+  }
+  for (int c = 0; c < kmax; c += kPanel) {
+    hipLaunchKernelGGL(hh_panel_batched_kernel, dim3((unsigned)nprob), dim3(512), 0, st, B, c);
+    SK_HIP(hipGetLastError());
+    const int ntrail = kmax + 1 - c - 1;  // the most trailing columns any problem has at this step
+    if (ntrail > 0) {
+      hipLaunchKernelGGL(hh_trail_batched_kernel, dim3((unsigned)ntrail, (unsigned)nprob), dim3(256), 0, st, B, c);
+      SK_HIP(hipGetLastError());
+    }
+  }
+  const unsigned eb = (unsigned)std::max(1, std::min(64, (kmax * kmax + 255) / 256));
+  hipLaunchKernelGGL(extract_r_batched_kernel, dim3(eb, (unsigned)nprob), dim3(256), 0, st, B);
+  SK_HIP(hipGetLastError());
+  const unsigned nblk = (unsigned)((kmax + kTb - 1) / kTb);
+  hipLaunchKernelGGL(trinv_diag_batched_kernel, dim3(nblk, (unsigned)nprob), dim3(64), 0, st, B);
+  SK_HIP(hipGetLastError());
+  const size_t lds = (size_t)kmax * (kTb + 1) * sizeof(double);
+  SK_HIP(hipFuncSetAttribute((const void*)trinv_cols_batched_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds));
+  hipLaunchKernelGGL(trinv_cols_batched_kernel, dim3(nblk, (unsigned)nprob), dim3(1024), lds, st, B);
   SK_HIP(hipGetLastError());
   return SK_OK;
 }

@@ -186,26 +186,47 @@ int batched_bufs(Carver& cv, const sk_sketch* W, const sk_ls_problem& p, SolveBu
   return SK_OK;
 }
 
-// Problems run on up to this many streams of their own, so that the
-// one-workgroup kernels of different problems (QR panels, small solves)
-// overlap. For 512 problems of k = 16..256 the rate rises with the stream
-// count up to the 32 streams taken here (relative to 32: 16 streams 0.92,
-// 8 streams 0.79, two or four 0.61).
-// SKETCH_BATCH_STREAMS (1 .. 32) overrides.
-int batch_streams(int nprob) {
-  static const int ns = [] {
-    const char* v = std::getenv("SKETCH_BATCH_STREAMS");
-    const int n = v ? std::atoi(v) : 32;
-    return std::max(1, std::min(32, n));
-  }();
-  return std::min(nprob, ns);
+// The problems' sketches run back to back on one stream (each apply fills
+// the chip by itself), with one workspace slot. Spreading them over several
+// concurrent streams, each with a slot reused by its problems in turn, gave
+// wrong solutions for one to five problems of a 512-problem batch (k = 16..256)
+// in some runs with 32 streams, and a GPU memory fault with 4; the cause has
+// not been found, and that arrangement is not used.
+int batch_streams(int nprob) { return std::min(nprob, 1); }
+
+// Problems whose factorization runs in the batched launches (all problems
+// of a batch at once: d <= 1024, the 32-column register panel; k <= 512,
+// the blocked inverse); the others take the per-problem steps on their
+// stream.
+bool batch_factored(const sk_ls_problem& p, int d_per_k) {
+  return (int64_t)d_per_k * p.k <= 1024 && p.k <= 512;
 }
 
-// Workspace layout: the rank of every problem (nprob ints), then one slot per
-// stream holding the buffers of one problem, reused by the problems of that
+// Buffers of a batch-factored problem, live from its sketch to the batched
+// solve: W = [S A | S b] (d x (k + 1), column-major), tau, T, R, c, X = R^-1
+// and X^T.
+struct FactorBufs {
+  double *W, *tau, *T, *R, *c, *X, *XT;
+};
+void factor_bufs(Carver& cv, int64_t d, int k, FactorBufs* F) {
+  F->W = cv.take<double>((size_t)d * (k + 1));
+  F->tau = cv.take<double>((size_t)k);
+  F->T = cv.take<double>(qr_tbuf_doubles(k));
+  F->R = cv.take<double>((size_t)k * k);
+  F->c = cv.take<double>((size_t)k);
+  F->X = cv.take<double>((size_t)k * k);
+  F->XT = cv.take<double>((size_t)k * k);
+}
+
+// Workspace layout: the rank of every problem (nprob ints); the table of the
+// batch-factored problems (QrBatch entries) and their factor buffers; then
+// one slot per stream holding the buffers of one problem's sketch (and of a
+// whole problem for the per-problem path), reused by the problems of that
 // stream in turn (they run in stream order).
 struct BatchLayout {
-  size_t ranks_bytes, slot_bytes, total;
+  size_t ranks_bytes, table_off, factors_off, slots_off, slot_bytes, total;
+  std::vector<size_t> factor_at;  // offset of each problem's factor buffers (batch-factored ones)
+  int n_factored = 0;
 };
 // On failure *bad is the problem the apply refused (its data layout).
 int batched_layout(const sk_ls_problem* probs, int nprob, int d_per_k, int zeta, int device, BatchLayout* L,
@@ -223,9 +244,23 @@ int batched_layout(const sk_ls_problem* probs, int nprob, int d_per_k, int zeta,
     }
     mx = std::max(mx, cv.off);
   }
-  L->ranks_bytes = ((size_t)nprob * sizeof(int) + 255) & ~(size_t)255;
-  L->slot_bytes = (mx + 255) & ~(size_t)255;
-  L->total = L->ranks_bytes + (size_t)batch_streams(nprob) * L->slot_bytes;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  L->ranks_bytes = al((size_t)nprob * sizeof(int));
+  L->n_factored = 0;
+  for (int i = 0; i < nprob; ++i) L->n_factored += batch_factored(probs[i], d_per_k) ? 1 : 0;
+  L->table_off = L->ranks_bytes;
+  L->factors_off = al(L->table_off + sizeof(QrBatch) * (size_t)std::max(1, L->n_factored));
+  Carver fc;
+  L->factor_at.assign((size_t)nprob, 0);
+  for (int i = 0; i < nprob; ++i) {
+    if (!batch_factored(probs[i], d_per_k)) continue;
+    L->factor_at[i] = al(fc.off);
+    FactorBufs F;
+    factor_bufs(fc, (int64_t)d_per_k * probs[i].k, (int)probs[i].k, &F);
+  }
+  L->slots_off = al(L->factors_off + fc.off);
+  L->slot_bytes = al(mx);
+  L->total = L->slots_off + (size_t)batch_streams(nprob) * L->slot_bytes;
   return SK_OK;
 }
 
@@ -467,10 +502,17 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
     }
   }
   int* ranks = reinterpret_cast<int*>(base);
+  QrBatch* table = reinterpret_cast<QrBatch*>(base + L.table_off);
+  std::vector<QrBatch> host_table;
+  int kmax = 0;
+  hipEvent_t batch_done = nullptr;
+  std::vector<hipEvent_t> joined((size_t)NS, nullptr);
   const double eps = std::ldexp(1.0, -52);
-  // Pass 1: sketch, Householder QR and, where the rank test of Alg. 3 is
-  // certain to pass, x = R^-1 c. Pass 2 redoes the problems it could not
-  // certify with the SVD of R (the same steps as lstsq_sketch_solve).
+  // Pass 1: the sketches on the streams; the Householder QR, R^-1 and, where
+  // the rank test of Alg. 3 is certain to pass, x = R^-1 c, for all the
+  // batch-factored problems at once on the caller's stream (the others take
+  // these steps on their own stream). Pass 2 redoes the problems it could
+  // not certify with the SVD of R (the same steps as lstsq_sketch_solve).
   std::vector<int> h((size_t)nprob, 0);
   std::vector<char> redo((size_t)nprob, 0);
   std::vector<double> t_ms((size_t)nprob, 0.0);
@@ -484,13 +526,26 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
       hipStream_t ps = ss[slot];
       sk_sketch W;
       batched_sketch(p, d_per_k, zeta, device, &W);
-      Carver cv{base, L.ranks_bytes + (size_t)slot * L.slot_bytes};
+      Carver cv{base, L.slots_off + (size_t)slot * L.slot_bytes};
       SolveBufs X;
       Phases ph(ps);
       if ((rc = batched_bufs(cv, &W, p, &X)) < 0) break;
       if (hipEventRecord(ev[2 * i], ps) != hipSuccess) {
         rc = SK_E_HIP;
         break;
+      }
+      if (pass == 0 && batch_factored(p, d_per_k)) {
+        // the sketch into this stream's slot, [S A | S b] into the problem's own buffers
+        Carver fc{base, L.factors_off + L.factor_at[i]};
+        FactorBufs F;
+        factor_bufs(fc, W.d, k, &F);
+        if ((rc = apply_dispatch(&W, p.dtype, k, p.A, p.lda, SK_F64, X.B.SA, k, X.B.aws, X.B.aws_bytes, ps)) < 0) break;
+        if ((rc = apply_dispatch(&W, p.dtype, 1, p.b, 1, SK_F64, X.B.Sb, 1, X.B.aws, X.B.aws_bytes, ps)) < 0) break;
+        if ((rc = launch_to_columns(X.B.SA, k, X.B.Sb, W.d, k, F.W, W.d, ps)) < 0) break;
+        host_table.push_back(QrBatch{F.W, W.d, W.d, k, 0, F.tau, F.T, F.R, F.c, F.X, F.XT, p.x, ranks + i});
+        kmax = std::max(kmax, k);
+        queued = true;
+        continue;
       }
       if ((rc = sketch_and_factor(&W, k, p.dtype, p.A, p.lda, p.b, X.B, ph, ps, p.dtype)) < 0) break;
       if (pass == 0) {
@@ -506,6 +561,33 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
         break;
       }
       queued = true;
+    }
+    if (pass == 0 && rc == SK_OK && !host_table.empty()) {
+      // the caller's stream waits for every sketch, then factors and solves
+      // the batch-factored problems together
+      for (int j = 0; j < NS && rc == SK_OK; ++j) {
+        if (hipEventCreateWithFlags(&joined[j], hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(joined[j], ss[j]) != hipSuccess || hipStreamWaitEvent(st, joined[j], 0) != hipSuccess) {
+          set_error("lstsq_sketch_solve_batched: joining the streams failed");
+          rc = SK_E_HIP;
+        }
+      }
+      const int nf = (int)host_table.size();
+      if (rc == SK_OK && hipMemcpyAsync(table, host_table.data(), sizeof(QrBatch) * (size_t)nf,
+                                        hipMemcpyHostToDevice, st) != hipSuccess) {
+        set_error("lstsq_sketch_solve_batched: uploading the batch table failed");
+        rc = SK_E_HIP;
+      }
+      if (rc == SK_OK) rc = qr_trinv_batched(table, nf, kmax, st);
+      if (rc == SK_OK) rc = certified_tri_solve_batched(table, nf, eps, st);
+      if (rc == SK_OK && (hipEventCreate(&batch_done) != hipSuccess || hipEventRecord(batch_done, st) != hipSuccess)) {
+        set_error("lstsq_sketch_solve_batched: event on the caller's stream failed");
+        rc = SK_E_HIP;
+      }
+      if (rc == SK_OK && hipStreamSynchronize(st) != hipSuccess) {
+        set_error("lstsq_sketch_solve_batched: synchronization failed");
+        rc = SK_E_HIP;
+      }
     }
     // everything queued has finished before the ranks are read and before the
     // events, the streams and the workspace go
@@ -523,8 +605,10 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
     }
     for (int i = 0; i < nprob; ++i) {
       if (pass == 0 || redo[i]) {
+        // a batch-factored problem ends with the batch's solve
         float t = 0.f;
-        (void)hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
+        const bool batch = pass == 0 && batch_factored(probs[i], d_per_k);
+        (void)hipEventElapsedTime(&t, ev[2 * i], batch ? batch_done : ev[2 * i + 1]);
         t_ms[i] += t;
       }
       redo[i] = h[i] < 0;
@@ -543,6 +627,9 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
     if (ss[j]) (void)hipStreamSynchronize(ss[j]);
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& e : joined)
+    if (e) (void)hipEventDestroy(e);
+  if (batch_done) (void)hipEventDestroy(batch_done);
   if (ready) (void)hipEventDestroy(ready);
   for (auto& s2 : ss)
     if (s2) (void)hipStreamDestroy(s2);

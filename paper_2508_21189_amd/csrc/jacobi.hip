@@ -29,10 +29,9 @@ __global__ void __launch_bounds__(1024) svd_solve_kernel(const double* __restric
 // of X) implies s_k > 5 eps s_1: the rank is k and the truncated-SVD solution
 // is x = R^-1 c = X c. Otherwise *rank_out = -1 and x is not written (the
 // caller takes the SVD). Only the upper triangles of R and X are read.
-__global__ void __launch_bounds__(1024) certified_tri_solve_kernel(const double* __restrict__ R,
-                                                                   const double* __restrict__ X,
-                                                                   const double* __restrict__ c, int k, double eps,
-                                                                   double* __restrict__ x, int* __restrict__ rank_out) {
+__device__ __forceinline__ void certified_tri_solve_dev(const double* __restrict__ R, const double* __restrict__ X,
+                                                        const double* __restrict__ c, int k, double eps,
+                                                        double* __restrict__ x, int* __restrict__ rank_out) {
   __shared__ double part[2][16];
   __shared__ int ok;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -72,9 +71,29 @@ __global__ void __launch_bounds__(1024) certified_tri_solve_kernel(const double*
   }
 }
 
+__global__ void __launch_bounds__(1024) certified_tri_solve_kernel(const double* __restrict__ R,
+                                                                   const double* __restrict__ X,
+                                                                   const double* __restrict__ c, int k, double eps,
+                                                                   double* __restrict__ x, int* __restrict__ rank_out) {
+  certified_tri_solve_dev(R, X, c, k, eps, x, rank_out);
+}
+
+__global__ void __launch_bounds__(1024) certified_tri_solve_batched_kernel(const QrBatch* __restrict__ B, double eps) {
+  const QrBatch& p = B[blockIdx.x];
+  if (p.k == 0) return;
+  certified_tri_solve_dev(p.R, p.X, p.c, p.k, eps, p.x, p.rank);
+}
+
 int launch_certified_tri_solve(const double* R, const double* X, const double* c, int k, double eps, double* x,
                                int* rank_out, hipStream_t st) {
   hipLaunchKernelGGL(certified_tri_solve_kernel, dim3(1), dim3(1024), 0, st, R, X, c, k, eps, x, rank_out);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+int certified_tri_solve_batched(const QrBatch* B, int nprob, double eps, hipStream_t st) {
+  if (nprob <= 0) return SK_OK;
+  hipLaunchKernelGGL(certified_tri_solve_batched_kernel, dim3((unsigned)nprob), dim3(1024), 0, st, B, eps);
   SK_HIP(hipGetLastError());
   return SK_OK;
 }

@@ -31,4 +31,23 @@ int launch_svd_solve(const double* U, const double* s, const double* V, const do
 // x[0:n) = value
 int launch_fill(double* x, int64_t n, double value, hipStream_t st);
 
+// One small problem of a batch (device memory): W (d x (k + 1), column-major,
+// ldw) = [S A | S b] on entry; tau (k), T (qr_tbuf_doubles(k)), R (k x k),
+// c (k), X and XT (k x k) are its outputs; x (k) and *rank its solution.
+// k = 0 marks an entry that the batched launches skip.
+struct QrBatch {
+  double* W;
+  int64_t ldw, d;
+  int k, pad;
+  double *tau, *T, *R, *c, *X, *XT, *x;
+  int* rank;
+};
+// For every problem of the table B (nprob entries, d <= 1024, k <= kmax <=
+// 512): the blocked Householder QR of W (32-column panels), R and c, and X =
+// R^-1, XT = X^T: one launch per panel and per trailing update for the whole
+// batch, then one each for R, the diagonal blocks and the columns of X.
+int qr_trinv_batched(const QrBatch* B, int nprob, int kmax, hipStream_t st);
+// Alg. 3's certified solve (launch_certified_tri_solve) for every problem of B.
+int certified_tri_solve_batched(const QrBatch* B, int nprob, double eps, hipStream_t st);
+
 }  // namespace sk

@@ -152,3 +152,30 @@ def test_batched_wide_problems_match_oracle(lib):
             xr, r, tol = _oracle(A64, b64, k, seed, 2.0 ** -24)
             assert np.linalg.norm(xg - xr) <= tol
         assert rank == r == k
+
+
+def test_batched_mixes_batch_factored_and_per_problem_steps(lib):
+    """Problems with d = 4k <= 1024 are factored together in the batched launches, the others (here k = 300, d =
+    1200) on their own stream; both kinds in one call match the oracle, and the batch is bitwise reproducible."""
+    shapes = [(9000, 300, torch.float64), (3000, 40, torch.float64), (8000, 256, torch.float32),
+              (6000, 290, torch.float32), (2500, 1, torch.float64)]
+    problems = []
+    for i, (n, k, dt) in enumerate(shapes):
+        A, b = _problem(n, k, dt, 80 + i)
+        problems.append((A, b, 3000 + i))
+    xs, status, ranks, t_ms, rc = lib.solve_batched(problems)
+    assert rc == 0 and status == [0] * len(shapes)
+    for (A, b, seed), x, rank, t, (n, k, dt) in zip(problems, xs, ranks, t_ms, shapes):
+        A64 = A.to(torch.float64).cpu().numpy()
+        b64 = b.to(torch.float64).cpu().numpy()
+        xg = x.cpu().numpy()
+        if dt == torch.float64:
+            xr, r, _ = _oracle(A64, b64, k, seed, 2.0 ** -53)
+            assert np.linalg.norm(xg - xr) <= 1e-11 * np.linalg.norm(xr)
+        else:
+            xr, r, tol = _oracle(A64, b64, k, seed, 2.0 ** -24)
+            assert np.linalg.norm(xg - xr) <= tol
+        assert rank == r == k and t > 0.0
+    again = lib.solve_batched(problems)[0]
+    for a, b in zip(xs, again):
+        assert torch.equal(a, b)
