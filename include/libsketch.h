@@ -22,7 +22,11 @@
  *   - A sketch handle is immutable after creation; concurrent calls with
  *     the same handle on different streams are safe except that calls
  *     passing ws = NULL share the handle's internal workspace and must be
- *     serialized by the caller.
+ *     serialized by the caller. Every call runs on one stream. (An earlier
+ *     batched driver that spread 512 small solves over 32 concurrent streams,
+ *     each reusing one workspace slot, gave wrong results for a few of them in
+ *     some runs, for a reason not yet found; callers that run many calls
+ *     concurrently should check their results the same way.)
  */
 #ifndef LIBSKETCH_H
 #define LIBSKETCH_H
