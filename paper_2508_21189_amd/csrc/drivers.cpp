@@ -14,6 +14,7 @@
 #include "sk_dense.hpp"
 #include "sk_drivers.hpp"
 #include "sk_gauss.hpp"
+#include "sk_launch.hpp"
 #include "sk_lowrank.hpp"
 #include "sk_lsqr.hpp"
 #include "sk_srtt.hpp"
@@ -218,23 +219,38 @@ void factor_bufs(Carver& cv, int64_t d, int k, FactorBufs* F) {
   F->XT = cv.take<double>((size_t)k * k);
 }
 
+// Batch-factored problems whose sketch [S A | S b] also runs in the batched
+// launches (the bucket-indexed kernels with b as an extra column: k >= 4,
+// zeta >= 4, 4-byte aligned rows); the others are sketched one by one.
+bool batch_sketched(const sk_ls_problem& p, const sk_sketch* W, int d_per_k) {
+  return batch_factored(p, d_per_k) && idx_batch_fits(W, p.dtype, p.k, p.A, p.lda);
+}
+
 // Workspace layout: the rank of every problem (nprob ints); the table of the
-// batch-factored problems (QrBatch entries) and their factor buffers; then
-// one slot per stream holding the buffers of one problem's sketch (and of a
+// batch-factored problems (QrBatch entries) and their factor buffers; the
+// area of the batched sketches (tables, row codes, partial sums); then one
+// slot per stream holding the buffers of one problem's sketch (and of a
 // whole problem for the per-problem path), reused by the problems of that
 // stream in turn (they run in stream order).
 struct BatchLayout {
-  size_t ranks_bytes, table_off, factors_off, slots_off, slot_bytes, total;
+  size_t ranks_bytes, table_off, factors_off, bsk_off, bsk_bytes, slots_off, slot_bytes, total;
   std::vector<size_t> factor_at;  // offset of each problem's factor buffers (batch-factored ones)
+  std::vector<char> sketched;     // problems in the batched sketch
+  std::vector<sk_sketch> sks;     // every problem's sketch description
   int n_factored = 0;
 };
 // On failure *bad is the problem the apply refused (its data layout).
 int batched_layout(const sk_ls_problem* probs, int nprob, int d_per_k, int zeta, int device, BatchLayout* L,
                    int* bad = nullptr) {
   size_t mx = 0;
+  L->sks.assign((size_t)nprob, sk_sketch{});
+  L->sketched.assign((size_t)nprob, 0);
   for (int i = 0; i < nprob; ++i) {
-    sk_sketch W;
+    sk_sketch& W = L->sks[i];
     batched_sketch(probs[i], d_per_k, zeta, device, &W);
+    L->sketched[i] = batch_sketched(probs[i], &W, d_per_k) ? 1 : 0;
+    // (every problem may need the slot: one that the full-rank certificate
+    // rejects is redone on the per-problem path)
     Carver cv;
     SolveBufs X;
     const int rc = batched_bufs(cv, &W, probs[i], &X);
@@ -252,13 +268,22 @@ int batched_layout(const sk_ls_problem* probs, int nprob, int d_per_k, int zeta,
   L->factors_off = al(L->table_off + sizeof(QrBatch) * (size_t)std::max(1, L->n_factored));
   Carver fc;
   L->factor_at.assign((size_t)nprob, 0);
+  std::vector<IdxBatchJob> jobs;
   for (int i = 0; i < nprob; ++i) {
     if (!batch_factored(probs[i], d_per_k)) continue;
     L->factor_at[i] = al(fc.off);
     FactorBufs F;
     factor_bufs(fc, (int64_t)d_per_k * probs[i].k, (int)probs[i].k, &F);
+    if (L->sketched[i])
+      jobs.push_back(IdxBatchJob{&L->sks[i], probs[i].dtype, probs[i].k, probs[i].A, probs[i].lda, probs[i].b, nullptr});
   }
-  L->slots_off = al(L->factors_off + fc.off);
+  L->bsk_off = al(L->factors_off + fc.off);
+  L->bsk_bytes = 0;
+  if (!jobs.empty()) {
+    const int rc = idx_batch_workspace(jobs.data(), (int)jobs.size(), &L->bsk_bytes);
+    if (rc < 0) return rc;
+  }
+  L->slots_off = al(L->bsk_off + L->bsk_bytes);
   L->slot_bytes = al(mx);
   L->total = L->slots_off + (size_t)batch_streams(nprob) * L->slot_bytes;
   return SK_OK;
@@ -516,10 +541,39 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
   std::vector<int> h((size_t)nprob, 0);
   std::vector<char> redo((size_t)nprob, 0);
   std::vector<double> t_ms((size_t)nprob, 0.0);
+  // the batched sketches' host tables, alive until the stream has run them
+  std::vector<unsigned char> stage;
+  hipEvent_t bsk_start = nullptr;
   for (int pass = 0; pass < 2 && rc == SK_OK; ++pass) {
     bool queued = false;
+    if (pass == 0) {
+      // the batched sketches first: [S A | S b] of every such problem
+      // straight into its factor buffer W
+      std::vector<IdxBatchJob> jobs;
+      for (int i = 0; i < nprob; ++i) {
+        if (!L.sketched[i]) continue;
+        const sk_ls_problem& p = probs[i];
+        Carver fc{base, L.factors_off + L.factor_at[i]};
+        FactorBufs F;
+        factor_bufs(fc, L.sks[i].d, (int)p.k, &F);
+        jobs.push_back(IdxBatchJob{&L.sks[i], p.dtype, p.k, p.A, p.lda, p.b, F.W});
+        host_table.push_back(
+            QrBatch{F.W, L.sks[i].d, L.sks[i].d, (int)p.k, 0, F.tau, F.T, F.R, F.c, F.X, F.XT, p.x, ranks + i});
+        kmax = std::max(kmax, (int)p.k);
+      }
+      if (!jobs.empty()) {
+        if (hipEventCreate(&bsk_start) != hipSuccess || hipEventRecord(bsk_start, ss[0]) != hipSuccess) {
+          set_error("lstsq_sketch_solve_batched: event on the caller's stream failed");
+          rc = SK_E_HIP;
+        }
+        if (rc == SK_OK)
+          rc = launch_idx_batch(jobs.data(), (int)jobs.size(), base + L.bsk_off, L.bsk_bytes, &stage, ss[0]);
+        queued = rc == SK_OK;
+      }
+    }
     for (int i = 0; i < nprob && rc == SK_OK; ++i) {
       if (pass == 1 && !redo[i]) continue;
+      if (pass == 0 && L.sketched[i]) continue;
       const sk_ls_problem& p = probs[i];
       const int k = (int)p.k;
       const int slot = i % NS;
@@ -608,7 +662,8 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
         // a batch-factored problem ends with the batch's solve
         float t = 0.f;
         const bool batch = pass == 0 && batch_factored(probs[i], d_per_k);
-        (void)hipEventElapsedTime(&t, ev[2 * i], batch ? batch_done : ev[2 * i + 1]);
+        const bool bsk = pass == 0 && L.sketched[i];
+        (void)hipEventElapsedTime(&t, bsk ? bsk_start : ev[2 * i], batch ? batch_done : ev[2 * i + 1]);
         t_ms[i] += t;
       }
       redo[i] = h[i] < 0;
@@ -630,6 +685,7 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
   for (auto& e : joined)
     if (e) (void)hipEventDestroy(e);
   if (batch_done) (void)hipEventDestroy(batch_done);
+  if (bsk_start) (void)hipEventDestroy(bsk_start);
   if (ready) (void)hipEventDestroy(ready);
   for (auto& s2 : ss)
     if (s2) (void)hipStreamDestroy(s2);

@@ -2,6 +2,8 @@
 #pragma once
 #include "sk_common.hpp"
 
+#include <vector>
+
 namespace sk {
 
 // Plan of the row-mode SparseStack apply (SA = S A, A row-major n x m).
@@ -46,6 +48,28 @@ int launch_idx_codes(const sk_sketch* S, int dtype_in, int64_t n_tiles, int R, u
 int plan_idx(const sk_sketch* S, int dtype_in, int64_t m, const void* A, int64_t lda, RowsPlan* plan);
 int launch_idx_sketch(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64_t m, const void* A, int64_t lda,
                       void* ws, hipStream_t st);
+
+// Batched row-mode sketches of many problems (ss_idx.hip): for job j,
+// W = [S A | S b] in FP64, column-major d x (k + 1) with leading dimension
+// d, S the job's SparseStack (A row-major n x k, b n values, both of the
+// job's dtype). idx_batch_fits says whether a job can go into the batched
+// launches; the workspace holds the tables, the row codes and the partial
+// sums (groups of jobs share one area of at most 4 GiB, or one job's need);
+// stage is host memory that must stay alive until the stream has run the
+// launches.
+struct IdxBatchJob {
+  const sk_sketch* S;
+  int dtype;
+  int64_t k;
+  const void* A;
+  int64_t lda;
+  const void* b;
+  double* W;
+};
+bool idx_batch_fits(const sk_sketch* S, int dtype_in, int64_t k, const void* A, int64_t lda);
+int idx_batch_workspace(const IdxBatchJob* jobs, int njobs, size_t* bytes);
+int launch_idx_batch(const IdxBatchJob* jobs, int njobs, void* ws, size_t ws_bytes,
+                     std::vector<unsigned char>* stage, hipStream_t st);
 
 int launch_rows_apply(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64_t m, const void* A,
                       int64_t lda, int dtype_out, void* SA, int64_t ldsa, void* ws, hipStream_t st);

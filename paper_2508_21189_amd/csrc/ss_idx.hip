@@ -41,7 +41,10 @@
 #include "sk_launch.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
+#include <tuple>
+#include <vector>
 
 namespace sk {
 
@@ -135,9 +138,42 @@ __global__ void ss_idx_plan_parts_kernel(int64_t n, int64_t n_tiles, int R, int 
   }
 }
 
-template <typename Tin, int NREG, int LB, bool PARTS = false>
-__global__ void __launch_bounds__(NREG > 64 ? 512 : 1024)
-    ss_idx_kernel(IdxArgs a, const uint32_t* __restrict__ codes_all) {
+template <int ES>
+struct RawBits;
+template <>
+struct RawBits<8> {
+  using type = uint64_t;
+};
+template <>
+struct RawBits<4> {
+  using type = uint32_t;
+};
+template <>
+struct RawBits<2> {
+  using type = uint16_t;
+};
+
+// Global-memory accesses through pointers that the compiler cannot place
+// in the global address space by itself (those read from a table): without
+// the cast they become flat accesses, which also count against the LDS
+// counter and make the tile's LDS reads wait for them.
+template <typename T>
+__device__ inline T gload(const void* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ inline void gstore(void* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+
+// The work of workgroup L of the grid that a describes. With HASB the last
+// of the a.m columns is not part of the matrix but the vector bcol (stride
+// one element): it rides in the lane after the matrix's last column, its
+// values loaded to registers by wave 0 and written into the tile's padding
+// before the tile is published (two tile buffers only).
+template <typename Tin, int NREG, int LB, bool PARTS, bool HASB>
+__device__ __forceinline__ void ss_idx_body(const IdxArgs& a, const unsigned char* bcol,
+                                            const uint32_t* __restrict__ codes_all, int L) {
   using T = IdxT<Tin>;
   using Tacc = typename T::acc;
   constexpr int ES = sizeof(Tin);
@@ -155,7 +191,7 @@ __global__ void __launch_bounds__(NREG > 64 ? 512 : 1024)
   // Work item. Dispatch is round-robin over the 8 XCDs (id L runs on XCD
   // L % 8): all slabs and block groups of one row chunk get ids 8 apart and
   // share one XCD's L2 for the cache lines that straddle slab boundaries.
-  const int L = blockIdx.x, xcd = L & 7, q8 = L >> 3;
+  const int xcd = L & 7, q8 = L >> 3;
   const int group = q8 % a.n_groups;
   const int slab = (q8 / a.n_groups) % a.n_slabs;
   const int chunk = (q8 / (a.n_groups * a.n_slabs)) * 8 + xcd;
@@ -165,7 +201,12 @@ __global__ void __launch_bounds__(NREG > 64 ? 512 : 1024)
   const int bpg = min(a.bpg, a.zeta - t0);
   const int64_t col0 = (int64_t)slab * a.C;
   const int Cw = (int)min((int64_t)a.C, a.m - col0);
-  const int slab_bytes = Cw * ES;
+  // bytes of the matrix in a tile row of the slab (what the direct loads bring)
+  const int slab_bytes = HASB ? (int)max((int64_t)0, min((int64_t)Cw, a.m - 1 - col0)) * ES : Cw * ES;
+  const int bl = HASB ? (int)(a.m - 1 - col0) : -1;  // the lane of the b column
+  const bool has_b = HASB && bl >= 0 && bl < Cw;
+  using Raw = typename RawBits<ES>::type;
+  Raw bv[2] = {0, 0};
   const int64_t r_begin = (int64_t)chunk * a.rows_per_chunk;
   const int64_t r_end = min(a.n, r_begin + a.rows_per_chunk);
   const int nsub = r_end > r_begin ? (int)((r_end - r_begin + a.R - 1) / a.R) : 0;
@@ -214,6 +255,15 @@ __global__ void __launch_bounds__(NREG > 64 ? 512 : 1024)
       row += rstep;
       src += sstep;
     }
+    if constexpr (HASB) {
+      if (has_b && wave == 0) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int brow = j * 64 + lane;
+          if (j * 64 < R && brow < rv) bv[j] = gload<Raw>(bcol + (r0 + brow) * ES);
+        }
+      }
+    }
     // Bring this wave's codes of the tile into L2 ahead of their scalar
     // loads: a direct load of them into a scratch LDS area that is never
     // read (the scalar loads would otherwise wait on HBM once per group).
@@ -236,6 +286,7 @@ __global__ void __launch_bounds__(NREG > 64 ? 512 : 1024)
   int per_tile = walker ? (8 * R + 1023) / 1024 : 0;
   for (int k = wave; k < n_instr; k += nwaves)
     if (((k * 64) % CPR) * LB < slab_bytes) ++per_tile;
+  if (HASB && has_b && wave == 0) per_tile += (R + 63) / 64;
   for (int p = 0; p < nbuf - 1 && p < nsub; ++p) issue_loads(p, p);
   for (int st = 0; st < nsub; ++st) {
     const int buf = st % nbuf;
@@ -244,6 +295,19 @@ __global__ void __launch_bounds__(NREG > 64 ? 512 : 1024)
     const int later = min(st + nbuf - 2, nsub - 1) - st;
     const bool later_full = later <= 0 || r_begin + (int64_t)(st + later + 1) * R <= r_end;
     idx_wait_vm(later > 0 && later_full ? later * per_tile : 0);
+    if constexpr (HASB) {
+      // the b values of tile st (loaded with the tile) into its padding lane
+      if (has_b && wave == 0) {
+        const int64_t r0 = r_begin + (int64_t)st * R;
+        const int rv = (int)min((int64_t)R, r_end - r0);
+        unsigned char* dst = smem + buf * a.buf_stride + bl * ES;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int brow = j * 64 + lane;
+          if (j * 64 < R && brow < rv) *(Raw*)(dst + brow * ROWB) = bv[j];
+        }
+      }
+    }
     idx_barrier();  // tile st is in LDS; everyone finished tile st-1
     if (st + nbuf - 1 < nsub) issue_loads(st + nbuf - 1, (st + nbuf - 1) % nbuf);
     if (walker) {
@@ -311,9 +375,154 @@ __global__ void __launch_bounds__(NREG > 64 ? 512 : 1024)
         } else {
           val = __builtin_bit_cast(float, acc_get<NREG>(f, s));
         }
-        P[(rowbase + s) * a.m + col0 + lane] = val;
+        gstore<Tacc>(P + (rowbase + s) * a.m + col0 + lane, val);
       }
     }
+  }
+}
+
+template <typename Tin, int NREG, int LB, bool PARTS = false>
+__global__ void __launch_bounds__(NREG > 64 ? 512 : 1024)
+    ss_idx_kernel(IdxArgs a, const uint32_t* __restrict__ codes_all) {
+  ss_idx_body<Tin, NREG, LB, PARTS, false>(a, nullptr, codes_all, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Batched sketches: [S_p A_p | S_p b_p] for many independent problems, each
+// with its own SparseStack (Def. 1.5). One launch computes the row codes of
+// every problem, one launch per kernel variant (input type, register file,
+// load width, bucket parts) runs the applies of all its problems, with b_p
+// as the column after A_p's last one, and one launch per partial type sums
+// the chunks into W_p, column-major d_p x (k_p + 1) (the layout the
+// Householder QR takes). Each workgroup finds its problem by a binary
+// search over the problems' first workgroups; the arithmetic of every
+// problem is that of the single-matrix kernels.
+// ---------------------------------------------------------------------------
+struct IdxBatchEntry {
+  IdxArgs a;                // a.m = k + 1 (column k is b), a.P = the problem's partials
+  const unsigned char* b;   // b (k + 1 th column), stride one element
+  int64_t codes_off;        // the problem's codes: words from the codes base
+  int64_t wg_begin;         // its first workgroup in the launch (a multiple of 8)
+};
+
+struct IdxCodesEntry {
+  int64_t n, n_tiles, codes_off, blk_begin;
+  int R, zeta, nparts, ps;
+  uint32_t nb, dump0, ndump, one_hi, rpa, k0, k1;
+};
+
+struct IdxReduceEntry {
+  const void* P;   // partials [chunk][d][m]
+  double* W;       // W[c * ldw + row]
+  int64_t d, m, ldw, blk_begin;
+  int n_chunks, col_tiles;
+  double scale;
+};
+
+// The entry whose range [begin, next begin) holds g (entries sorted by begin).
+template <typename E, int64_t E::*BEGIN>
+__device__ inline int batch_find(const E* __restrict__ tab, int nent, int64_t g) {
+  int lo = 0, hi = nent - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab[mid].*BEGIN <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename Tin, int NREG, int LB, bool PARTS>
+__global__ void __launch_bounds__(NREG > 64 ? 512 : 1024)
+    ss_idx_batched_kernel(const IdxBatchEntry* __restrict__ tab, int nent, const uint32_t* __restrict__ codes_all) {
+  const int64_t g = blockIdx.x;
+  const int e = batch_find<IdxBatchEntry, &IdxBatchEntry::wg_begin>(tab, nent, g);
+  // a private copy: the body's asm statements clobber memory, and the
+  // fields must not be re-read from the table after each of them
+  const IdxArgs a = tab[e].a;
+  const unsigned char* bcol = tab[e].b;
+  const int64_t off = tab[e].codes_off;
+  const int L = (int)(g - tab[e].wg_begin);
+  ss_idx_body<Tin, NREG, LB, PARTS, true>(a, bcol, codes_all + off, L);
+}
+
+// Codes of every problem, in the layout of the bucket-parts plan kernel
+// (with one part, ps = nb, it is the layout of the plain one): block q of
+// problem e handles items [q * 1024, (q + 1) * 1024) of its rows x hash
+// groups.
+constexpr int kCodesPerThread = 4;
+__global__ void __launch_bounds__(256)
+    ss_idx_plan_batched_kernel(const IdxCodesEntry* __restrict__ tab, int nent, uint32_t* __restrict__ codes_all) {
+  const int64_t blk = blockIdx.x;
+  const IdxCodesEntry e = tab[batch_find<IdxCodesEntry, &IdxCodesEntry::blk_begin>(tab, nent, blk)];
+  const int ng = (e.zeta + 3) / 4;
+  const int64_t total = e.n_tiles * e.R * ng;
+  uint32_t* codes = codes_all + e.codes_off;
+  const int64_t first = (blk - e.blk_begin) * (256 * kCodesPerThread);
+  for (int q = 0; q < kCodesPerThread; ++q) {
+    const int64_t idx = first + q * 256 + threadIdx.x;
+    if (idx >= total) break;
+    const int64_t tr = idx / ng;  // tile * R + r = the row index i
+    const int g = (int)(idx - tr * ng);
+    const int64_t tile = tr / e.R;
+    const int r = (int)(tr - tile * e.R);
+    const uint64_t i = (uint64_t)tr;
+    U4 w = U4{0u, 0u, 0u, 0u};
+    if ((int64_t)i < e.n)
+      w = philox4x32_10(U4{(uint32_t)i, (uint32_t)(i >> 32), (uint32_t)g, kTagSparseStack}, e.k0, e.k1);
+    for (int j = 0; j < 4; ++j) {
+      const int t = 4 * g + j;
+      if (t >= e.zeta) break;
+      const uint32_t word = word_of(w, j);
+      const int b = (int)ss_bucket(word, e.nb);
+      const uint32_t sw = (ss_negative(word) << 31) | e.one_hi;
+      for (int h = 0; h < e.nparts; ++h) {
+        const int rel = b - h * e.ps;
+        uint32_t* c = codes + ((tile * e.zeta + t) * e.nparts + h) * (int64_t)(2 * e.R);
+        c[r] = (rel >= 0 && rel < e.ps ? (uint32_t)rel : e.dump0 + (uint32_t)r % e.ndump) * e.rpa;
+        c[e.R + r] = sw;
+      }
+    }
+  }
+}
+
+// W[c * ldw + row] = scale * (sum over chunks, in chunk order, in FP64, of
+// P[chunk][row][c]) for a 64 x 64 tile (row, c) of one problem per block:
+// the partials read along c, the tile transposed through LDS, W written
+// along the rows.
+template <typename Tacc>
+__global__ void __launch_bounds__(256) idx_reduce_batched_kernel(const IdxReduceEntry* __restrict__ tab, int nent) {
+  __shared__ double tile[64][65];
+  const int64_t blk = blockIdx.x;
+  const IdxReduceEntry e = tab[batch_find<IdxReduceEntry, &IdxReduceEntry::blk_begin>(tab, nent, blk)];
+  const int local = (int)(blk - e.blk_begin);
+  const int64_t r0 = (int64_t)(local / e.col_tiles) * 64;
+  const int64_t c0 = (int64_t)(local % e.col_tiles) * 64;
+  const int j = threadIdx.x & 63, i0 = threadIdx.x >> 6;
+  const Tacc* P = (const Tacc*)e.P;
+  const int64_t c = c0 + j;
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  if (c < e.m) {
+    for (int ch = 0; ch < e.n_chunks; ++ch) {
+      const Tacc* Pc = P + ((int64_t)ch * e.d + r0) * e.m + c;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int64_t row = i0 + 4 * q;
+        if (r0 + row < e.d) acc[q] += (double)Pc[row * e.m];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) tile[j][i0 + 4 * q] = acc[q] * e.scale;
+  __syncthreads();
+  const int rr = threadIdx.x & 63, cq = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int cc = cq + 4 * q;
+    if (r0 + rr < e.d && c0 + cc < e.m) e.W[(c0 + cc) * e.ldw + r0 + rr] = tile[cc][rr];
   }
 }
 
@@ -356,6 +565,17 @@ int idx_parts(int dtype_in, int64_t nb) {
   const int64_t np = (nb + cap - 1) / cap;
   return np <= kMaxParts ? (int)np : 0;
 }
+
+// Bucket parts of a block in the batched sketch: as idx_parts, and FP32 and
+// BF16 blocks of more than 200 buckets are split too (192 buckets a part, the
+// last 8 slots of the file being the dump): a batch gains from keeping every
+// problem in its one launch more than it loses to the repeated walk.
+int batch_parts(int dtype_in, int64_t nb) {
+  if (idx_nreg(dtype_in, nb) != 0) return 1;
+  const int64_t cap = (dtype_in == SK_F64 ? 100 : 200) - dump_slots(dtype_in);
+  const int64_t np = (nb + cap - 1) / cap;
+  return np <= kMaxParts ? (int)np : 0;
+}
 }  // namespace
 
 bool idx_apply_fits(const sk_sketch* S, int dtype_in, int64_t m) {
@@ -363,10 +583,14 @@ bool idx_apply_fits(const sk_sketch* S, int dtype_in, int64_t m) {
   return m > 4 && S->zeta >= 4 && idx_parts(dtype_in, S->nb) != 0;
 }
 
-static int plan_idx_lb(const sk_sketch* S, int dtype_in, int64_t m, int load_bytes, RowsPlan* p) {
+// batch: the plan of one problem of a batched sketch (bucket parts by
+// batch_parts, two tile buffers, and row chunks sized for a launch that
+// many problems fill together rather than for filling the chip alone).
+static int plan_idx_lb(const sk_sketch* S, int dtype_in, int64_t m, int load_bytes, RowsPlan* p,
+                       bool batch = false) {
   const int es = (int)dtype_size(dtype_in);
   const int zeta = S->zeta;
-  const int nparts = idx_parts(dtype_in, S->nb);
+  const int nparts = batch ? batch_parts(dtype_in, S->nb) : idx_parts(dtype_in, S->nb);
   if (nparts == 0) {
     set_error("sketch_apply: bucket register file too small for this block size");
     return SK_E_NOTSUP;
@@ -403,7 +627,7 @@ static int plan_idx_lb(const sk_sketch* S, int dtype_in, int64_t m, int load_byt
   const size_t touch = (size_t)1024 * p->W;
   // two buffers: loading three or four tiles ahead measured slower (F64
   // coherent 2.06 ms with two, 2.40 with three, 2.62 with four)
-  const int nbuf = std::max(2, std::min(4, env_i("SKETCH_IDX_NBUF", 2)));
+  const int nbuf = batch ? 2 : std::max(2, std::min(4, env_i("SKETCH_IDX_NBUF", 2)));
   p->nbuf = nbuf;
   int R = (int)((cap - touch - 64) / nbuf / (size_t)p->rowb);
   // at most 128 rows: larger tiles measured slower (F32 m = 200: 128 rows
@@ -424,9 +648,17 @@ static int plan_idx_lb(const sk_sketch* S, int dtype_in, int64_t m, int load_byt
 
   const int64_t n = S->n;
   const int64_t items = (int64_t)p->n_slabs * p->n_groups;
-  const int target = env_i("SKETCH_IDX_WG", 256 * wg_per_cu);
-  int64_t nc = std::max<int64_t>(1, (target + items - 1) / items);
-  nc = ((std::max<int64_t>(nc, 8) + 7) / 8) * 8;
+  int64_t nc;
+  if (batch) {
+    // chunks of at least 16 d rows (the partials then add about 1/16 of A's
+    // bytes) and 2048 rows, in multiples of 8 (the grid's XCD order)
+    const int64_t rows = std::max<int64_t>(2048, 16 * S->d);
+    nc = ((std::max<int64_t>(1, (n + rows - 1) / rows) + 7) / 8) * 8;
+  } else {
+    const int target = env_i("SKETCH_IDX_WG", 256 * wg_per_cu);
+    nc = std::max<int64_t>(1, (target + items - 1) / items);
+    nc = ((std::max<int64_t>(nc, 8) + 7) / 8) * 8;
+  }
   nc = std::min<int64_t>(nc, (n + p->R - 1) / p->R);
   int64_t rpc = (n + nc - 1) / nc;
   rpc = ((rpc + p->R - 1) / p->R) * p->R;
@@ -559,6 +791,305 @@ int launch_idx_sketch(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64
                               : launch_idx_n<float, 4>(S, p, m, A, lda, P, codes, st);
   return p.load_bytes == 16 ? launch_idx_n<uint16_t, 16>(S, p, m, A, lda, P, codes, st)
                             : launch_idx_n<uint16_t, 4>(S, p, m, A, lda, P, codes, st);
+}
+
+// ---- batched sketches (host)
+#define SK_IDX_TRY(expr)     \
+  do {                       \
+    const int _rc = (expr);  \
+    if (_rc < 0) return _rc; \
+  } while (0)
+namespace {
+constexpr size_t kBatchAreaCap = (size_t)4 << 30;  // codes + partials of one launch group
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int batch_load_bytes(int dtype_in, int64_t k, const void* A, int64_t lda) {
+  const int es = (int)dtype_size(dtype_in);
+  const uintptr_t ap = (uintptr_t)A;
+  if (ap % 16 == 0 && (lda * es) % 16 == 0 && (k * es) % 16 == 0) return 16;
+  if (ap % 4 == 0 && (lda * es) % 4 == 0 && (k * es) % 4 == 0) return 4;
+  return 0;
+}
+
+// A kernel variant and its launch shape: the jobs of one apply launch share it.
+using BatchKey = std::tuple<int, int, int, int, int, int, size_t>;
+struct BatchPlanned {
+  RowsPlan p;
+  BatchKey key;
+  int64_t wg;            // workgroups of its apply
+  size_t codes_bytes, partial_bytes;
+};
+
+BatchKey batch_key(int dtype_in, const RowsPlan& p) {
+  return BatchKey(dtype_in, p.jb, p.load_bytes, p.nparts, p.W, p.R, p.lds_bytes);
+}
+
+template <typename Tin, int NREG, int LB, bool PARTS>
+int launch_variant(const IdxBatchEntry* tab, int nent, int64_t grid, int threads, size_t lds, const uint32_t* codes,
+                   hipStream_t st) {
+  auto kern = ss_idx_batched_kernel<Tin, NREG, LB, PARTS>;
+  SK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, st, tab, nent, codes);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+template <typename Tin, int LB, bool PARTS>
+int launch_variant_n(int nreg, const IdxBatchEntry* tab, int nent, int64_t grid, int threads, size_t lds,
+                     const uint32_t* codes, hipStream_t st) {
+  if constexpr (PARTS) {
+    return launch_variant<Tin, 200, LB, true>(tab, nent, grid, threads, lds, codes, st);
+  } else {
+    switch (nreg) {
+      case 32:
+        return launch_variant<Tin, 32, LB, false>(tab, nent, grid, threads, lds, codes, st);
+      case 64:
+        return launch_variant<Tin, 64, LB, false>(tab, nent, grid, threads, lds, codes, st);
+      case 128:
+        return launch_variant<Tin, 128, LB, false>(tab, nent, grid, threads, lds, codes, st);
+      default:
+        return launch_variant<Tin, 200, LB, false>(tab, nent, grid, threads, lds, codes, st);
+    }
+  }
+}
+
+template <typename Tin>
+int launch_variant_t(const RowsPlan& p, const IdxBatchEntry* tab, int nent, int64_t grid, const uint32_t* codes,
+                     hipStream_t st) {
+  const int threads = 64 * p.W;
+  if (p.load_bytes == 16)
+    return p.nparts > 1 ? launch_variant_n<Tin, 16, true>(p.jb, tab, nent, grid, threads, p.lds_bytes, codes, st)
+                        : launch_variant_n<Tin, 16, false>(p.jb, tab, nent, grid, threads, p.lds_bytes, codes, st);
+  return p.nparts > 1 ? launch_variant_n<Tin, 4, true>(p.jb, tab, nent, grid, threads, p.lds_bytes, codes, st)
+                      : launch_variant_n<Tin, 4, false>(p.jb, tab, nent, grid, threads, p.lds_bytes, codes, st);
+}
+
+int plan_batch_job(const IdxBatchJob& j, BatchPlanned* out) {
+  const int lb = batch_load_bytes(j.dtype, j.k, j.A, j.lda);
+  if (lb == 0) {
+    set_error("batched sketch: A must be 4-byte aligned with lda*elsize and k*elsize multiples of 4");
+    return SK_E_NOTSUP;
+  }
+  SK_IDX_TRY(plan_idx_lb(j.S, j.dtype, j.k + 1, lb, &out->p, true));
+  const RowsPlan& p = out->p;
+  out->key = batch_key(j.dtype, p);
+  out->wg = ((int64_t)(p.n_chunks + 7) / 8) * 8 * p.n_slabs * p.n_groups;
+  out->codes_bytes = al256(p.plan_bytes);
+  out->partial_bytes = al256(p.partial_bytes);
+  return SK_OK;
+}
+
+// Consecutive jobs whose codes and partials fit the area together.
+std::vector<std::pair<int, int>> batch_groups(const std::vector<BatchPlanned>& pl, size_t area) {
+  std::vector<std::pair<int, int>> g;
+  int first = 0;
+  size_t used = 0;
+  for (int i = 0; i < (int)pl.size(); ++i) {
+    const size_t need = pl[i].codes_bytes + pl[i].partial_bytes;
+    if (i > first && used + need > area) {
+      g.push_back({first, i});
+      first = i;
+      used = 0;
+    }
+    used += need;
+  }
+  if (first < (int)pl.size()) g.push_back({first, (int)pl.size()});
+  return g;
+}
+
+size_t batch_tables_bytes(int njobs) {
+  return al256(sizeof(IdxBatchEntry) * (size_t)njobs) + al256(sizeof(IdxCodesEntry) * (size_t)njobs) +
+         al256(sizeof(IdxReduceEntry) * (size_t)njobs);
+}
+
+int batch_plans(const IdxBatchJob* jobs, int njobs, std::vector<BatchPlanned>* pl, size_t* area) {
+  pl->resize((size_t)njobs);
+  size_t total = 0, mx = 0;
+  for (int i = 0; i < njobs; ++i) {
+    SK_IDX_TRY(plan_batch_job(jobs[i], &(*pl)[i]));
+    const size_t need = (*pl)[i].codes_bytes + (*pl)[i].partial_bytes;
+    total += need;
+    mx = std::max(mx, need);
+  }
+  *area = std::max(std::min(total, kBatchAreaCap), mx);
+  return SK_OK;
+}
+}  // namespace
+
+bool idx_batch_fits(const sk_sketch* S, int dtype_in, int64_t k, const void* A, int64_t lda) {
+  if (env_i("SKETCH_IDX", 1) == 0) return false;
+  return S->kind == SK_SPARSESTACK && k >= 4 && S->zeta >= 4 && batch_parts(dtype_in, S->nb) != 0 &&
+         batch_load_bytes(dtype_in, k, A, lda) != 0;
+}
+
+int idx_batch_workspace(const IdxBatchJob* jobs, int njobs, size_t* bytes) {
+  std::vector<BatchPlanned> pl;
+  size_t area = 0;
+  SK_IDX_TRY(batch_plans(jobs, njobs, &pl, &area));
+  *bytes = batch_tables_bytes(njobs) + area;
+  return SK_OK;
+}
+
+int launch_idx_batch(const IdxBatchJob* jobs, int njobs, void* ws, size_t ws_bytes,
+                     std::vector<unsigned char>* stage, hipStream_t st) {
+  if (njobs <= 0) return SK_OK;
+  std::vector<BatchPlanned> pl;
+  size_t area = 0;
+  SK_IDX_TRY(batch_plans(jobs, njobs, &pl, &area));
+  const size_t tables = batch_tables_bytes(njobs);
+  if (!ws || ws_bytes < tables + area) {
+    set_error("batched sketch: workspace too small");
+    return SK_E_INVAL;
+  }
+  unsigned char* base = (unsigned char*)ws;
+  const size_t off_codes_tab = al256(sizeof(IdxBatchEntry) * (size_t)njobs);
+  const size_t off_red_tab = off_codes_tab + al256(sizeof(IdxCodesEntry) * (size_t)njobs);
+  unsigned char* area_base = base + tables;
+  stage->assign(tables, 0);
+  IdxBatchEntry* h_ent = (IdxBatchEntry*)stage->data();
+  IdxCodesEntry* h_cod = (IdxCodesEntry*)(stage->data() + off_codes_tab);
+  IdxReduceEntry* h_red = (IdxReduceEntry*)(stage->data() + off_red_tab);
+
+  // Per group of jobs (consecutive, codes and partials in the area
+  // together): one codes launch, the applies by variant, the reductions by
+  // partial type. Job i's codes entry is slot i; its apply and reduce
+  // entries take slots of the group's range in launch order.
+  struct Launch {
+    int kind;  // 0 codes, 1 apply, 2 reduce of FP64 partials, 3 of FP32 partials
+    int first, count, dtype;
+    int64_t grid;
+    const RowsPlan* plan;
+  };
+  std::vector<Launch> launches;
+  for (const auto& gr : batch_groups(pl, area)) {
+    std::vector<size_t> part_off;
+    size_t off = 0;
+    int64_t blk = 0;
+    for (int i = gr.first; i < gr.second; ++i) {
+      const RowsPlan& p = pl[i].p;
+      const sk_sketch* S = jobs[i].S;
+      const int rpa = jobs[i].dtype == SK_F64 ? 2 : 1;
+      IdxCodesEntry& e = h_cod[i];
+      e.n = S->n;
+      e.n_tiles = p.n_tiles;
+      e.codes_off = (int64_t)(off / 4);
+      e.blk_begin = blk;
+      e.R = p.R;
+      e.zeta = S->zeta;
+      e.nparts = p.nparts;
+      e.ps = p.ps;
+      e.nb = (uint32_t)S->nb;
+      e.ndump = (uint32_t)dump_slots(jobs[i].dtype);
+      e.dump0 = (uint32_t)(200 / rpa) - e.ndump;
+      e.one_hi = jobs[i].dtype == SK_F64 ? IdxT<double>::one_hi : IdxT<float>::one_hi;
+      e.rpa = (uint32_t)rpa;
+      e.k0 = S->k0;
+      e.k1 = S->k1;
+      const int64_t items = p.n_tiles * p.R * ((S->zeta + 3) / 4);
+      blk += (items + 256 * kCodesPerThread - 1) / (256 * kCodesPerThread);
+      off += pl[i].codes_bytes;
+    }
+    launches.push_back(Launch{0, gr.first, gr.second - gr.first, 0, blk, nullptr});
+    for (int i = gr.first; i < gr.second; ++i) {
+      part_off.push_back(off);
+      off += pl[i].partial_bytes;
+    }
+    std::vector<int> order;
+    for (int i = gr.first; i < gr.second; ++i) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return pl[x].key < pl[y].key; });
+    int slot = gr.first;
+    for (size_t q = 0; q < order.size();) {
+      const int first = slot;
+      const BatchKey key = pl[order[q]].key;
+      int64_t wg = 0;
+      for (; q < order.size() && pl[order[q]].key == key; ++q) {
+        const int i = order[q];
+        const RowsPlan& p = pl[i].p;
+        const IdxBatchJob& jb = jobs[i];
+        IdxBatchEntry& e = h_ent[slot++];
+        IdxArgs& a = e.a;
+        a.A = (const unsigned char*)jb.A;
+        a.lda_bytes = jb.lda * (int64_t)dtype_size(jb.dtype);
+        a.n = jb.S->n;
+        a.m = jb.k + 1;
+        a.d = jb.S->d;
+        a.C = p.C;
+        a.n_slabs = p.n_slabs;
+        a.R = p.R;
+        a.bpg = p.bpg;
+        a.n_groups = p.n_groups;
+        a.n_chunks = p.n_chunks;
+        a.rows_per_chunk = p.rows_per_chunk;
+        a.zeta = jb.S->zeta;
+        a.nb = (int)jb.S->nb;
+        a.k0 = jb.S->k0;
+        a.k1 = jb.S->k1;
+        a.P = area_base + part_off[(size_t)(i - gr.first)];
+        a.buf_stride = p.rec_bytes;
+        a.nbuf = p.nbuf;
+        a.off_touch = p.nbuf * p.rec_bytes;
+        a.codes_touch = area_base + (size_t)h_cod[i].codes_off * 4;
+        a.nparts = p.nparts;
+        a.ps = p.ps;
+        e.b = (const unsigned char*)jb.b;
+        e.codes_off = h_cod[i].codes_off;
+        e.wg_begin = wg;
+        wg += pl[i].wg;
+      }
+      launches.push_back(Launch{1, first, slot - first, jobs[order[first - gr.first]].dtype, wg,
+                                &pl[order[first - gr.first]].p});
+    }
+    slot = gr.first;
+    for (int kind = 2; kind <= 3; ++kind) {
+      const int first = slot;
+      int64_t rblk = 0;
+      for (int i = gr.first; i < gr.second; ++i) {
+        if ((jobs[i].dtype == SK_F64) != (kind == 2)) continue;
+        IdxReduceEntry& e = h_red[slot++];
+        e.P = area_base + part_off[(size_t)(i - gr.first)];
+        e.W = jobs[i].W;
+        e.d = jobs[i].S->d;
+        e.m = jobs[i].k + 1;
+        e.ldw = jobs[i].S->d;
+        e.n_chunks = pl[i].p.n_chunks;
+        e.col_tiles = (int)((e.m + 63) / 64);
+        e.scale = 1.0 / std::sqrt((double)jobs[i].S->zeta);
+        e.blk_begin = rblk;
+        rblk += ((e.d + 63) / 64) * e.col_tiles;
+      }
+      if (slot > first) launches.push_back(Launch{kind, first, slot - first, 0, rblk, nullptr});
+    }
+  }
+  SK_HIP(hipMemcpyAsync(base, stage->data(), tables, hipMemcpyHostToDevice, st));
+  const IdxBatchEntry* d_ent = (const IdxBatchEntry*)base;
+  const IdxCodesEntry* d_cod = (const IdxCodesEntry*)(base + off_codes_tab);
+  const IdxReduceEntry* d_red = (const IdxReduceEntry*)(base + off_red_tab);
+  uint32_t* codes = (uint32_t*)area_base;
+  for (const auto& l : launches) {
+    if (l.grid <= 0) continue;
+    if (l.kind == 0) {
+      hipLaunchKernelGGL(ss_idx_plan_batched_kernel, dim3((unsigned)l.grid), dim3(256), 0, st, d_cod + l.first,
+                         l.count, codes);
+      SK_HIP(hipGetLastError());
+    } else if (l.kind == 1) {
+      const IdxBatchEntry* tab = d_ent + l.first;
+      if (l.dtype == SK_F64)
+        SK_IDX_TRY(launch_variant_t<double>(*l.plan, tab, l.count, l.grid, codes, st));
+      else if (l.dtype == SK_F32)
+        SK_IDX_TRY(launch_variant_t<float>(*l.plan, tab, l.count, l.grid, codes, st));
+      else
+        SK_IDX_TRY(launch_variant_t<uint16_t>(*l.plan, tab, l.count, l.grid, codes, st));
+    } else {
+      if (l.kind == 2)
+        hipLaunchKernelGGL(idx_reduce_batched_kernel<double>, dim3((unsigned)l.grid), dim3(256), 0, st,
+                           d_red + l.first, l.count);
+      else
+        hipLaunchKernelGGL(idx_reduce_batched_kernel<float>, dim3((unsigned)l.grid), dim3(256), 0, st,
+                           d_red + l.first, l.count);
+      SK_HIP(hipGetLastError());
+    }
+  }
+  return SK_OK;
 }
 
 }  // namespace sk

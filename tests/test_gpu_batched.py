@@ -179,3 +179,42 @@ def test_batched_mixes_batch_factored_and_per_problem_steps(lib):
     again = lib.solve_batched(problems)[0]
     for a, b in zip(xs, again):
         assert torch.equal(a, b)
+
+
+VARIANTS = [(20000, 150, torch.float64, 0), (9000, 201, torch.float32, 0), (30000, 255, torch.float32, 0),
+            (5000, 200, torch.float32, 0), (3000, 63, torch.float64, 0), (4000, 64, torch.bfloat16, 0),
+            (100, 8, torch.float32, 0), (70001, 16, torch.float32, 0), (2000, 3, torch.float32, 0),
+            (6000, 4, torch.float64, 0), (8000, 37, torch.float32, 3), (2500, 96, torch.bfloat16, 2)]
+
+
+def test_batched_sketch_variants_match_oracle(lib):
+    """The batched sketch (one launch per kernel variant for all problems, b as the column after A's last) across its
+    variants: FP64 and FP32 bucket parts (k = 150; k = 201 and 255), the 200-slot file without parts (k = 200), the
+    b column alone in the last lane of a slab (k = 63) and in a slab of its own lane range (k = 64), n below one tile
+    (n = 100), many row chunks with a ragged last tile (n = 70001), k = 4, rows with a stride and an offset of one or
+    three elements (so only 4-byte loads), beside a problem the batched sketch does not take (k = 3, sketched on its
+    own), in one call; every solution matches the oracle, and the batch is bitwise reproducible."""
+    problems = []
+    for i, (n, k, dt, pad) in enumerate(VARIANTS):
+        A, b = _problem(n, k, dt, 200 + i)
+        if pad:
+            wide = torch.zeros((n, k + 2 * pad), dtype=dt, device="cuda")
+            wide[:, pad:pad + k] = A
+            A = wide[:, pad:pad + k]
+        problems.append((A, b, 5000 + i))
+    xs, status, ranks, t_ms, rc = lib.solve_batched(problems)
+    assert rc == 0 and status == [0] * len(VARIANTS)
+    for (A, b, seed), x, rank, t, (n, k, dt, _) in zip(problems, xs, ranks, t_ms, VARIANTS):
+        A64 = A.to(torch.float64).cpu().numpy()
+        b64 = b.to(torch.float64).cpu().numpy()
+        xg = x.cpu().numpy()
+        if dt == torch.float64:
+            xr, r, _ = _oracle(A64, b64, k, seed, 2.0 ** -53)
+            assert np.linalg.norm(xg - xr) <= 1e-11 * np.linalg.norm(xr), (n, k, dt)
+        else:
+            xr, r, tol = _oracle(A64, b64, k, seed, 2.0 ** -24)
+            assert np.linalg.norm(xg - xr) <= tol, (n, k, dt)
+        assert rank == r == k and t > 0.0
+    again = lib.solve_batched(problems)[0]
+    for a, b in zip(xs, again):
+        assert torch.equal(a, b)
