@@ -13,6 +13,12 @@ namespace sk {
 
 constexpr int kPanel = 32;  // panel width of the blocked QR
 
+// Global loads and stores through table pointers (which the compiler would
+// otherwise access as flat memory); the loads are made unconditional by the
+// callers (clamped addresses) so that they issue back to back.
+__device__ inline double gld(const double* p) { return *(const __attribute__((address_space(1))) double*)p; }
+__device__ inline void gst(double* p, double v) { *(__attribute__((address_space(1))) double*)p = v; }
+
 // Block-wide sum of one double per thread (blockDim.x a multiple of 64, <= 1024).
 __device__ inline double block_sum(double v, double* red) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -158,11 +164,16 @@ __device__ __forceinline__ void hh_panel_reg_dev(double* __restrict__ W, int64_t
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // x[i * NB + q]: row k + tid + NT * i, panel column q (all indices static)
   double x[RPT * NB];
+  // unconditional loads (clamped addresses, the value then selected): the
+  // panel's loads issue back to back instead of each behind a branch
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int64_t r = k + tid + (int64_t)NT * i;
 #pragma unroll
-    for (int q = 0; q < NB; ++q) x[i * NB + q] = (r < d && q < nbp) ? W[(int64_t)(k + q) * ldw + r] : 0.0;
+    for (int q = 0; q < NB; ++q) {
+      const double w = gld(W + (int64_t)(k + min(q, nbp - 1)) * ldw + min(r, d - 1));
+      x[i * NB + q] = (r < d && q < nbp) ? w : 0.0;
+    }
   }
   for (int jj = 0; jj < nbp; ++jj) {
     // pivot column jj of this thread's rows (selected with static indices)
@@ -255,7 +266,7 @@ __device__ __forceinline__ void hh_panel_reg_dev(double* __restrict__ W, int64_t
     const int64_t r = k + tid + (int64_t)NT * i;
 #pragma unroll
     for (int q = 0; q < NB; ++q)
-      if (r < d && q < nbp) W[(int64_t)(k + q) * ldw + r] = x[i * NB + q];
+      if (r < d && q < nbp) gst(W + (int64_t)(k + q) * ldw + r, x[i * NB + q]);
   }
   // T: T[i][i] = tau_i; T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
   for (int i = 0; i < nbp; ++i) {
@@ -479,12 +490,97 @@ __global__ void __launch_bounds__(512) hh_panel_batched_kernel(const QrBatch* __
   hh_panel_reg_dev<32, 2, 512>(p.W, p.ldw, p.d, c, min(kPanel, p.k - c), p.tau, p.T + (int64_t)(c / kPanel) * kPanel * kPanel);
 }
 
-__global__ void __launch_bounds__(256) hh_trail_batched_kernel(const QrBatch* __restrict__ B, int c) {
-  const QrBatch& p = B[blockIdx.y];
-  if (c >= p.k) return;
-  const int nbp = min(kPanel, p.k - c), first = c + nbp;
-  if ((int)blockIdx.x >= p.k + 1 - first) return;  // the trailing columns, b included
-  hh_trail_dev(p.W, p.ldw, p.d, c, nbp, first, p.T + (int64_t)(c / kPanel) * kPanel * kPanel, blockIdx.x);
+// Trailing update by column blocks: workgroup (x, p) applies the panel's
+// Q^T = I - V T^T V^T to trailing columns [32 x, 32 x + 32) of problem p:
+// Z = V^T Y over 64-row tiles of V and Y staged in LDS (each thread four
+// entries of Z), Z2 = T^T Z, then Y -= V Z2 with each thread holding one
+// row of V and updating eight columns of it. V is read twice and Y read and
+// written once per block of 32 columns, where the column-by-column kernel
+// re-reads V for every column.
+constexpr int kTrailRows = 64;
+__global__ void __launch_bounds__(256) hh_trail_blk_batched_kernel(const QrBatch* __restrict__ B, int c) {
+  __shared__ double Vs[kTrailRows][kPanel + 1];
+  __shared__ double Ys[kTrailRows][kPanel + 1];
+  __shared__ double Zs[kPanel][kPanel + 1];
+  const QrBatch& pb = B[blockIdx.y];
+  const int k = pb.k;
+  if (c >= k) return;
+  const int nbp = min(kPanel, k - c), first = c + nbp;
+  const int cb = (int)blockIdx.x * kPanel;
+  const int nc = min(kPanel, k + 1 - first - cb);  // this block's columns (b included)
+  if (nc <= 0) return;
+  double* W = pb.W;
+  const int64_t ldw = pb.ldw, d = pb.d;
+  const double* T = pb.T + (int64_t)(c / kPanel) * kPanel * kPanel;
+  double* Y = W + (int64_t)(first + cb) * ldw;
+  const int tid = threadIdx.x;
+  // V[i][q] (rows i >= c): the reflector below its diagonal, 1 on it, 0 above
+  auto vat = [&](int64_t i, int q) -> double {
+    const double w = gld(W + (int64_t)(c + min(q, nbp - 1)) * ldw + min(i, d - 1));
+    const int64_t diag = c + q;
+    return (q < nbp && i < d) ? (i > diag ? w : (i == diag ? 1.0 : 0.0)) : 0.0;
+  };
+  // Z = V^T Y: thread (pr, cc) = (tid / 32, tid % 32) owns Z[pr + 8 j][cc]
+  const int cc = tid & 31, pr = tid >> 5;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t r0 = c; r0 < d; r0 += kTrailRows) {
+    {
+      const int rr = tid & 63, g = tid >> 6;  // rows by lane: coalesced along a column
+      const int64_t i = r0 + rr;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int q = g + 4 * m;
+        Vs[rr][q] = vat(i, q);
+        const double y = gld(Y + (int64_t)min(q, nc - 1) * ldw + min(i, d - 1));
+        Ys[rr][q] = (q < nc && i < d) ? y : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int rr = 0; rr < kTrailRows; ++rr) {
+      const double y = Ys[rr][cc];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] += Vs[rr][pr + 8 * j] * y;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) Zs[pr + 8 * j][cc] = acc[j];
+  __syncthreads();
+  // Z2 = T^T Z (T upper: Z2[p][cc] = sum_{q <= p} T[q][p] Z[q][cc])
+  double z2[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int pp = pr + 8 * j;
+    double s = 0.0;
+    if (pp < nbp)
+      for (int q = 0; q <= pp; ++q) s += gld(T + q * kPanel + pp) * Zs[q][cc];
+    z2[j] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 4; ++j) Zs[pr + 8 * j][cc] = z2[j];
+  __syncthreads();
+  // Y -= V Z2: thread (rr, g) = (tid % 64, tid / 64) updates row r0 + rr in
+  // columns g + 4 m
+  const int rr = tid & 63, g = tid >> 6;
+  for (int64_t r0 = c; r0 < d; r0 += kTrailRows) {
+    const int64_t i = r0 + rr;
+    if (i >= d) continue;
+    double v[kPanel];
+#pragma unroll
+    for (int q = 0; q < kPanel; ++q) v[q] = vat(i, q);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int col = g + 4 * m;
+      if (col >= nc) continue;
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < kPanel; ++q) s += v[q] * Zs[q][col];
+      double* y = Y + (int64_t)col * ldw + i;
+      gst(y, gld(y) - s);
+    }
+  }
 }
 
 __global__ void extract_r_batched_kernel(const QrBatch* __restrict__ B) {
@@ -593,7 +689,8 @@ int qr_trinv_batched(const QrBatch* B, int nprob, int kmax, hipStream_t st) {
     SK_HIP(hipGetLastError());
     const int ntrail = kmax + 1 - c - 1;  // the most trailing columns any problem has at this step
     if (ntrail > 0) {
-      hipLaunchKernelGGL(hh_trail_batched_kernel, dim3((unsigned)ntrail, (unsigned)nprob), dim3(256), 0, st, B, c);
+      const unsigned nblk = (unsigned)((ntrail + kPanel - 1) / kPanel);
+      hipLaunchKernelGGL(hh_trail_blk_batched_kernel, dim3(nblk, (unsigned)nprob), dim3(256), 0, st, B, c);
       SK_HIP(hipGetLastError());
     }
   }

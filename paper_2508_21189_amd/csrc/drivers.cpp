@@ -506,13 +506,15 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
   std::vector<hipStream_t> ss((size_t)NS, nullptr);
   hipEvent_t ready = nullptr;
   int rc = SK_OK;
-  for (auto& e : ev) {
-    if (hipEventCreate(&e) != hipSuccess) {
+  // start and end events of the problems sketched one by one (made when
+  // first needed: the problems of the batched sketch share one start)
+  auto event = [&](int j) -> hipEvent_t {
+    if (!ev[j] && hipEventCreate(&ev[j]) != hipSuccess) {
       set_error("lstsq_sketch_solve_batched: hipEventCreate failed");
-      rc = SK_E_HIP;
-      break;
+      ev[j] = nullptr;
     }
-  }
+    return ev[j];
+  };
   // the problems' streams start after the work already queued on `stream`
   if (rc == SK_OK && (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
                       hipEventRecord(ready, st) != hipSuccess)) {
@@ -584,7 +586,7 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
       SolveBufs X;
       Phases ph(ps);
       if ((rc = batched_bufs(cv, &W, p, &X)) < 0) break;
-      if (hipEventRecord(ev[2 * i], ps) != hipSuccess) {
+      if (!event(2 * i) || hipEventRecord(ev[2 * i], ps) != hipSuccess) {
         rc = SK_E_HIP;
         break;
       }
@@ -610,7 +612,7 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
         if ((rc = launch_jacobi_svd(X.B.R, k, X.U, X.sv, X.V, X.work, ps)) < 0) break;
         if ((rc = launch_svd_solve(X.U, X.sv, X.V, X.B.c, k, eps, p.x, X.z, ranks + i, ps)) < 0) break;
       }
-      if (hipEventRecord(ev[2 * i + 1], ps) != hipSuccess) {
+      if (!event(2 * i + 1) || hipEventRecord(ev[2 * i + 1], ps) != hipSuccess) {
         rc = SK_E_HIP;
         break;
       }

@@ -257,11 +257,10 @@ __device__ __forceinline__ void ss_idx_body(const IdxArgs& a, const unsigned cha
     }
     if constexpr (HASB) {
       if (has_b && wave == 0) {
+        // unconditional loads (rows past the tile read its last row; they
+        // are not written to LDS), so that nothing waits behind a branch
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int brow = j * 64 + lane;
-          if (j * 64 < R && brow < rv) bv[j] = gload<Raw>(bcol + (r0 + brow) * ES);
-        }
+        for (int j = 0; j < 2; ++j) bv[j] = gload<Raw>(bcol + (r0 + min(j * 64 + lane, rv - 1)) * ES);
       }
     }
     // Bring this wave's codes of the tile into L2 ahead of their scalar
@@ -286,7 +285,7 @@ __device__ __forceinline__ void ss_idx_body(const IdxArgs& a, const unsigned cha
   int per_tile = walker ? (8 * R + 1023) / 1024 : 0;
   for (int k = wave; k < n_instr; k += nwaves)
     if (((k * 64) % CPR) * LB < slab_bytes) ++per_tile;
-  if (HASB && has_b && wave == 0) per_tile += (R + 63) / 64;
+  if (HASB && has_b && wave == 0) per_tile += 2;
   for (int p = 0; p < nbuf - 1 && p < nsub; ++p) issue_loads(p, p);
   for (int st = 0; st < nsub; ++st) {
     const int buf = st % nbuf;
@@ -502,17 +501,36 @@ __global__ void __launch_bounds__(256) idx_reduce_batched_kernel(const IdxReduce
   const int j = threadIdx.x & 63, i0 = threadIdx.x >> 6;
   const Tacc* P = (const Tacc*)e.P;
   const int64_t c = c0 + j;
+  const int nr = (int)min((int64_t)64, e.d - r0);  // rows of the tile
   double acc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = 0.0;
   if (c < e.m) {
-    for (int ch = 0; ch < e.n_chunks; ++ch) {
-      const Tacc* Pc = P + ((int64_t)ch * e.d + r0) * e.m + c;
+    // two chunks' loads in flight before their adds (in chunk order); the
+    // loads are unconditional (rows past the tile read its last row and are
+    // never stored), so that none waits behind a branch
+    const int64_t cs = e.d * e.m;  // chunk stride
+    const Tacc* Pc = P + r0 * e.m + c;
+    int64_t ro[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) ro[q] = (int64_t)min(i0 + 4 * q, nr - 1) * e.m;
+    int ch = 0;
+    for (; ch + 1 < e.n_chunks; ch += 2, Pc += 2 * cs) {
+      Tacc v0[16], v1[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
-        const int64_t row = i0 + 4 * q;
-        if (r0 + row < e.d) acc[q] += (double)Pc[row * e.m];
+        v0[q] = gload<Tacc>(Pc + ro[q]);
+        v1[q] = gload<Tacc>(Pc + cs + ro[q]);
       }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        acc[q] += (double)v0[q];
+        acc[q] += (double)v1[q];
+      }
+    }
+    if (ch < e.n_chunks) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[q] += (double)gload<Tacc>(Pc + ro[q]);
     }
   }
 #pragma unroll
@@ -522,7 +540,7 @@ __global__ void __launch_bounds__(256) idx_reduce_batched_kernel(const IdxReduce
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int cc = cq + 4 * q;
-    if (r0 + rr < e.d && c0 + cc < e.m) e.W[(c0 + cc) * e.ldw + r0 + rr] = tile[cc][rr];
+    if (r0 + rr < e.d && c0 + cc < e.m) gstore<double>(e.W + (c0 + cc) * e.ldw + r0 + rr, tile[cc][rr]);
   }
 }
 
@@ -650,10 +668,11 @@ static int plan_idx_lb(const sk_sketch* S, int dtype_in, int64_t m, int load_byt
   const int64_t items = (int64_t)p->n_slabs * p->n_groups;
   int64_t nc;
   if (batch) {
-    // chunks of at least 16 d rows (the partials then add about 1/16 of A's
-    // bytes) and 2048 rows, in multiples of 8 (the grid's XCD order)
+    // chunks of at least 16 d rows (the partials then add at most about
+    // 1/16 of A's bytes) and 2048 rows; not rounded up to a multiple of 8
+    // (the grid is, and its surplus workgroups exit at once)
     const int64_t rows = std::max<int64_t>(2048, 16 * S->d);
-    nc = ((std::max<int64_t>(1, (n + rows - 1) / rows) + 7) / 8) * 8;
+    nc = std::max<int64_t>(1, (n + rows - 1) / rows);
   } else {
     const int target = env_i("SKETCH_IDX_WG", 256 * wg_per_cu);
     nc = std::max<int64_t>(1, (target + items - 1) / items);
@@ -996,7 +1015,12 @@ int launch_idx_batch(const IdxBatchJob* jobs, int njobs, void* ws, size_t ws_byt
     }
     std::vector<int> order;
     for (int i = gr.first; i < gr.second; ++i) order.push_back(i);
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return pl[x].key < pl[y].key; });
+    // by variant; within one, the problems with the longest row chunks first
+    // (workgroups start in grid order, so the longest ones do not trail)
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      if (pl[x].key != pl[y].key) return pl[x].key < pl[y].key;
+      return pl[x].p.rows_per_chunk > pl[y].p.rows_per_chunk;
+    });
     int slot = gr.first;
     for (size_t q = 0; q < order.size();) {
       const int first = slot;

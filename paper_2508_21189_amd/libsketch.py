@@ -441,10 +441,17 @@ def _batched_array(problems):
     """sk_ls_problem array for [(A, b, seed), ...] (A n x k row-major, b n elements of A's dtype, CUDA)."""
     arr = (LsProblem * len(problems))()
     xs = []
+    # one allocation for every solution (each x a view of k elements)
+    ks = [int(A.shape[1]) for A, _, _ in problems]
+    offs = [0]
+    for k in ks:
+        offs.append(offs[-1] + ((k + 31) // 32) * 32)
+    xall = torch.empty(max(1, offs[-1]), dtype=torch.float64, device=problems[0][0].device) if problems else None
     for i, (A, b, seed) in enumerate(problems):
         assert A.is_cuda and A.dim() == 2 and A.stride(1) == 1 and A.dtype in _DT
         assert b.is_cuda and b.dtype == A.dtype and b.numel() == A.shape[0] and b.is_contiguous()
-        x = torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
+        assert A.device == xall.device
+        x = xall[offs[i]:offs[i] + ks[i]]
         xs.append(x)
         arr[i] = LsProblem(A.shape[0], A.shape[1], _DT[A.dtype], _ptr(A), A.stride(0), _ptr(b), _ptr(x),
                            int(seed) & 0xFFFFFFFFFFFFFFFF, 0, 0, 0.0)
