@@ -19,6 +19,35 @@ constexpr int kPanel = 32;  // panel width of the blocked QR
 __device__ inline double gld(const double* p) { return *(const __attribute__((address_space(1))) double*)p; }
 __device__ inline void gst(double* p, double v) { *(__attribute__((address_space(1))) double*)p = v; }
 
+// Sums over the wave of N values per lane (N = 8, 16 or 32), returned
+// transposed: lane l gets the sum of a[l >> (6 - log2 N)]. Each halving step
+// trades half of a lane's values with the lane whose bit differs (the lane
+// with the bit set keeps the upper half) and adds, so the N sums cost N - 1
+// exchanges and adds instead of N full reductions; the lanes that share an
+// entry then finish it with ordinary exchanges.
+template <int N>
+__device__ inline double wave_sum_transposed(const double* a, int lane) {
+  static_assert(N == 8 || N == 16 || N == 32, "N");
+  double v[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] = a[j];
+  int bit = 32;
+#pragma unroll
+  for (int n = N; n > 1; n /= 2) {
+    const bool hi = (lane & bit) != 0;
+#pragma unroll
+    for (int j = 0; j < n / 2; ++j) {
+      const double send = hi ? v[j] : v[n / 2 + j];
+      const double keep = hi ? v[n / 2 + j] : v[j];
+      v[j] = keep + __shfl_xor(send, bit, 64);
+    }
+    bit /= 2;
+  }
+#pragma unroll
+  for (int b = 32 / N; b >= 1; b /= 2) v[0] += __shfl_xor(v[0], b, 64);
+  return v[0];
+}
+
 // Block-wide sum of one double per thread (blockDim.x a multiple of 64, <= 1024).
 __device__ inline double block_sum(double v, double* red) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -229,10 +258,12 @@ __device__ __forceinline__ void hh_panel_reg_dev(double* __restrict__ W, int64_t
       acc[q] = sacc;
     }
     __syncthreads();  // red is reused
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const double v = wave_sum_dpp(acc[q]);
-      if (lane == 0) red[wave][q] = v;
+    {
+      // the NB wave sums at once: lane l ends with the sum of entry
+      // l >> (6 - log2 NB) (transposed reduction, one exchange per halving)
+      const double v = wave_sum_transposed<NB>(acc, lane);
+      constexpr int kShift = NB == 32 ? 1 : (NB == 16 ? 2 : 3);
+      if ((lane & ((1 << kShift) - 1)) == 0) red[wave][lane >> kShift] = v;
     }
     __syncthreads();
     if (tid < nbp && tid != jj) {

@@ -54,7 +54,7 @@ int launch_idx_sketch(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64
 // d, S the job's SparseStack (A row-major n x k, b n values, both of the
 // job's dtype). idx_batch_fits says whether a job can go into the batched
 // launches; the workspace holds the tables, the row codes and the partial
-// sums (groups of jobs share one area of at most 4 GiB, or one job's need);
+// sums (groups of jobs share one area of at most 16 GiB, or one job's need);
 // stage is host memory that must stay alive until the stream has run the
 // launches.
 struct IdxBatchJob {

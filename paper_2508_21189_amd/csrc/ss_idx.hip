@@ -66,6 +66,7 @@ struct IdxArgs {
   // bucket parts (more buckets than one register file): parts per block
   // and buckets per part
   int nparts, ps;
+  int lb;  // width of the direct loads (16 or 4) where the kernel takes it at run time
 };
 
 // Row codes of row i = tile * R + r and block t, at base = (tile * zeta + t)
@@ -180,7 +181,9 @@ __device__ __forceinline__ void ss_idx_body(const IdxArgs& a, const unsigned cha
   // Tile rows sit at a fixed stride of one element per lane, so the LDS
   // offsets of the rows of a 64-row group are compile-time immediates.
   constexpr int ROWB = 64 * ES;
-  constexpr int CPR = ROWB / LB;  // load chunks per tile row (a power of two)
+  // load width: the template's, or (LB = 0, the batched kernels) the argument's
+  const int lb = LB ? LB : a.lb;
+  const int CPR = ROWB / lb;  // load chunks per tile row (a power of two)
   constexpr int GR = 16;          // rows whose codes one scalar group holds
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
@@ -228,7 +231,7 @@ __device__ __forceinline__ void ss_idx_body(const IdxArgs& a, const unsigned cha
   AccFile f;
   acc_zero<NREG>(f);
 
-  // Chunk q of a tile (LB bytes) is row q / CPR, bytes (q % CPR) * LB of it;
+  // Chunk q of a tile (lb bytes) is row q / CPR, bytes (q % CPR) * lb of it;
   // chunks past the slab's bytes are padding and are not loaded.
   const int n_instr = (R * CPR + 63) / 64;
   auto issue_loads = [&](int st, int buf) {
@@ -239,15 +242,15 @@ __device__ __forceinline__ void ss_idx_body(const IdxArgs& a, const unsigned cha
     // load k covers chunks [64 k, 64 k + 64): a lane's chunk advances by
     // 64 W chunks = RSTEP rows per load of its wave, at a fixed byte offset
     const int q0 = wave * 64 + lane;
-    const int cb = (q0 % CPR) * LB;
+    const int cb = (q0 % CPR) * lb;
     const int rstep = (nwaves * 64) / CPR;
     int row = q0 / CPR;
     const unsigned char* src = tsrc + (int64_t)row * a.lda_bytes + cb;
     const int64_t sstep = (int64_t)rstep * a.lda_bytes;
     for (int k = wave; k < n_instr; k += nwaves) {
-      const uint32_t la = (uint32_t)__builtin_amdgcn_readfirstlane((int)idx_lds_addr(dst + k * 64 * LB));
+      const uint32_t la = (uint32_t)__builtin_amdgcn_readfirstlane((int)idx_lds_addr(dst + k * 64 * lb));
       if (row < rv && cb < slab_bytes) {
-        if constexpr (LB == 16)
+        if (lb == 16)
           idx_dma16(src, la);
         else
           idx_dma4(src, la);
@@ -284,7 +287,7 @@ __device__ __forceinline__ void ss_idx_body(const IdxArgs& a, const unsigned cha
   const int nbuf = a.nbuf;
   int per_tile = walker ? (8 * R + 1023) / 1024 : 0;
   for (int k = wave; k < n_instr; k += nwaves)
-    if (((k * 64) % CPR) * LB < slab_bytes) ++per_tile;
+    if (((k * 64) % CPR) * lb < slab_bytes) ++per_tile;
   if (HASB && has_b && wave == 0) per_tile += 2;
   for (int p = 0; p < nbuf - 1 && p < nsub; ++p) issue_loads(p, p);
   for (int st = 0; st < nsub; ++st) {
@@ -739,6 +742,7 @@ static int launch_idx_t(const sk_sketch* S, const RowsPlan& p, int64_t m, const 
   a.codes_touch = (const unsigned char*)codes;
   a.nparts = p.nparts;
   a.ps = p.ps;
+  a.lb = LB;
   const int64_t grid = ((int64_t)(p.n_chunks + 7) / 8) * 8 * p.n_slabs * p.n_groups;
   auto kern = ss_idx_kernel<Tin, NREG, LB, PARTS>;
   SK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes));
@@ -819,7 +823,7 @@ int launch_idx_sketch(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64
     if (_rc < 0) return _rc; \
   } while (0)
 namespace {
-constexpr size_t kBatchAreaCap = (size_t)4 << 30;  // codes + partials of one launch group
+constexpr size_t kBatchAreaCap = (size_t)16 << 30;  // codes + partials of one launch group
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int batch_load_bytes(int dtype_in, int64_t k, const void* A, int64_t lda) {
@@ -839,8 +843,9 @@ struct BatchPlanned {
   size_t codes_bytes, partial_bytes;
 };
 
+// (the load width is an argument of the batched kernels: both widths share a launch)
 BatchKey batch_key(int dtype_in, const RowsPlan& p) {
-  return BatchKey(dtype_in, p.jb, p.load_bytes, p.nparts, p.W, p.R, p.lds_bytes);
+  return BatchKey(dtype_in, p.jb, 0, p.nparts, p.W, p.R, p.lds_bytes);
 }
 
 template <typename Tin, int NREG, int LB, bool PARTS>
@@ -876,11 +881,8 @@ template <typename Tin>
 int launch_variant_t(const RowsPlan& p, const IdxBatchEntry* tab, int nent, int64_t grid, const uint32_t* codes,
                      hipStream_t st) {
   const int threads = 64 * p.W;
-  if (p.load_bytes == 16)
-    return p.nparts > 1 ? launch_variant_n<Tin, 16, true>(p.jb, tab, nent, grid, threads, p.lds_bytes, codes, st)
-                        : launch_variant_n<Tin, 16, false>(p.jb, tab, nent, grid, threads, p.lds_bytes, codes, st);
-  return p.nparts > 1 ? launch_variant_n<Tin, 4, true>(p.jb, tab, nent, grid, threads, p.lds_bytes, codes, st)
-                      : launch_variant_n<Tin, 4, false>(p.jb, tab, nent, grid, threads, p.lds_bytes, codes, st);
+  return p.nparts > 1 ? launch_variant_n<Tin, 0, true>(p.jb, tab, nent, grid, threads, p.lds_bytes, codes, st)
+                      : launch_variant_n<Tin, 0, false>(p.jb, tab, nent, grid, threads, p.lds_bytes, codes, st);
 }
 
 int plan_batch_job(const IdxBatchJob& j, BatchPlanned* out) {
@@ -1055,6 +1057,7 @@ int launch_idx_batch(const IdxBatchJob* jobs, int njobs, void* ws, size_t ws_byt
         a.codes_touch = area_base + (size_t)h_cod[i].codes_off * 4;
         a.nparts = p.nparts;
         a.ps = p.ps;
+        a.lb = p.load_bytes;
         e.b = (const unsigned char*)jb.b;
         e.codes_off = h_cod[i].codes_off;
         e.wg_begin = wg;
