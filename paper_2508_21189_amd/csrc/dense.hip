@@ -323,62 +323,6 @@ __global__ void __launch_bounds__(NTH) hh_panel_reg_kernel(double* __restrict__ 
   hh_panel_reg_dev<NB, RPT, NTH>(W, ldw, d, k, nbp, tau, T);
 }
 
-// Trailing update of one column y (index k + nbp + blockIdx.x) of W:
-// y <- y - V T^T V^T y, with V the panel's reflectors (rows >= k).
-__device__ __forceinline__ void hh_trail_dev(double* __restrict__ W, int64_t ldw, int64_t d, int k, int nbp,
-                                             int first_col, const double* __restrict__ T, unsigned col) {
-  __shared__ double red[4][kPanel];
-  __shared__ double z[kPanel], z2[kPanel];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* y = W + (int64_t)(first_col + col) * ldw;
-  const double* V = W + (int64_t)k * ldw;
-  // z = V^T y
-  double acc[kPanel];
-#pragma unroll
-  for (int p = 0; p < kPanel; ++p) acc[p] = 0;
-  for (int64_t i = k + tid; i < d; i += blockDim.x) {
-    const double yi = y[i];
-    const int64_t rel = i - k;
-#pragma unroll
-    for (int p = 0; p < kPanel; ++p) {
-      if (p < nbp) {
-        const double vip = rel > p ? V[(int64_t)p * ldw + i] : (rel == p ? 1.0 : 0.0);
-        acc[p] += vip * yi;
-      }
-    }
-  }
-#pragma unroll
-  for (int p = 0; p < kPanel; ++p) {
-    const double v = wave_sum_dpp(acc[p]);
-    if (lane == 0) red[wave][p] = v;
-  }
-  __syncthreads();
-  if (tid < nbp) z[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-  __syncthreads();
-  // z2 = T^T z  (T upper: (T^T z)_p = sum_{q <= p} T[q][p] z_q)
-  if (tid < nbp) {
-    double s = 0;
-    for (int q = 0; q <= tid; ++q) s += T[q * kPanel + tid] * z[q];
-    z2[tid] = s;
-  }
-  __syncthreads();
-  // y -= V z2
-  for (int64_t i = k + tid; i < d; i += blockDim.x) {
-    const int64_t rel = i - k;
-    double s = 0;
-    for (int p = 0; p < nbp; ++p) {
-      const double vip = rel > p ? V[(int64_t)p * ldw + i] : (rel == p ? 1.0 : 0.0);
-      s += vip * z2[p];
-    }
-    y[i] -= s;
-  }
-}
-
-__global__ void __launch_bounds__(256) hh_trail_kernel(double* __restrict__ W, int64_t ldw, int64_t d, int k, int nbp,
-                                                       int first_col, const double* __restrict__ T) {
-  hh_trail_dev(W, ldw, d, k, nbp, first_col, T, blockIdx.x);
-}
-
 // R (k x k row-major, upper) and c = (Q^T rhs)[0:k] from the factored W.
 __device__ __forceinline__ void extract_r_dev(const double* __restrict__ W, int64_t ldw, int k, int has_rhs,
                                               double* __restrict__ R, double* __restrict__ c, unsigned bx, unsigned gx) {
@@ -522,96 +466,122 @@ __global__ void __launch_bounds__(512) hh_panel_batched_kernel(const QrBatch* __
 }
 
 // Trailing update by column blocks: workgroup (x, p) applies the panel's
-// Q^T = I - V T^T V^T to trailing columns [32 x, 32 x + 32) of problem p:
-// Z = V^T Y over 64-row tiles of V and Y staged in LDS (each thread four
-// entries of Z), Z2 = T^T Z, then Y -= V Z2 with each thread holding one
-// row of V and updating eight columns of it. V is read twice and Y read and
-// written once per block of 32 columns, where the column-by-column kernel
-// re-reads V for every column.
+// Q^T = I - V T^T V^T to trailing columns [32 x, 32 x + 32) of problem p,
+// over 64-row tiles of V and Y staged in LDS (zero past the matrix):
+//   Z = V^T Y  on the FP64 matrix cores, wave w owning the 16 x 16 block
+//              (w & 1, w >> 1) of Z;
+//   Z2 = T^T Z (T upper triangular; VALU, from LDS);
+//   Y -= V Z2  on the matrix cores, wave w owning rows 16 w of each tile.
+// v_mfma_f64_16x16x4f64: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16];
+// item v of the result is row 4 v + l / 16, column l % 16. V is read twice
+// and Y read and written once per block of 32 columns.
 constexpr int kTrailRows = 64;
-__global__ void __launch_bounds__(256) hh_trail_blk_batched_kernel(const QrBatch* __restrict__ B, int c) {
+typedef double v4d __attribute__((ext_vector_type(4)));
+// W: d rows, ncols columns (column-major, ldw); the panel is columns
+// [c, c + nbp) with its T; block bx updates columns first + 32 bx onwards.
+__device__ __forceinline__ void hh_trail_blk_dev(double* W, int64_t ldw, int64_t d, int ncols, int c, int nbp,
+                                                 const double* T, int bx) {
   __shared__ double Vs[kTrailRows][kPanel + 1];
   __shared__ double Ys[kTrailRows][kPanel + 1];
   __shared__ double Zs[kPanel][kPanel + 1];
-  const QrBatch& pb = B[blockIdx.y];
-  const int k = pb.k;
-  if (c >= k) return;
-  const int nbp = min(kPanel, k - c), first = c + nbp;
-  const int cb = (int)blockIdx.x * kPanel;
-  const int nc = min(kPanel, k + 1 - first - cb);  // this block's columns (b included)
+  const int first = c + nbp;
+  const int cb = bx * kPanel;
+  const int nc = min(kPanel, ncols - first - cb);  // this block's columns
   if (nc <= 0) return;
-  double* W = pb.W;
-  const int64_t ldw = pb.ldw, d = pb.d;
-  const double* T = pb.T + (int64_t)(c / kPanel) * kPanel * kPanel;
   double* Y = W + (int64_t)(first + cb) * ldw;
-  const int tid = threadIdx.x;
-  // V[i][q] (rows i >= c): the reflector below its diagonal, 1 on it, 0 above
-  auto vat = [&](int64_t i, int q) -> double {
-    const double w = gld(W + (int64_t)(c + min(q, nbp - 1)) * ldw + min(i, d - 1));
-    const int64_t diag = c + q;
-    return (q < nbp && i < d) ? (i > diag ? w : (i == diag ? 1.0 : 0.0)) : 0.0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  // Stage rows [r0, r0 + 64) of V (the reflector below its diagonal, 1 on
+  // it, 0 above and past nbp) and of Y (0 past nc and d): lanes along the
+  // rows (coalesced), unconditional loads from clamped addresses.
+  auto stage = [&](int64_t r0) {
+    const int rr = tid & 63, g = tid >> 6;
+    const int64_t i = r0 + rr, ic = min(i, d - 1);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int q = g + 4 * m;
+      const double w = gld(W + (int64_t)(c + min(q, nbp - 1)) * ldw + ic);
+      const double y = gld(Y + (int64_t)min(q, nc - 1) * ldw + ic);
+      const int64_t diag = c + q;
+      Vs[rr][q] = (q < nbp && i < d) ? (i > diag ? w : (i == diag ? 1.0 : 0.0)) : 0.0;
+      Ys[rr][q] = (q < nc && i < d) ? y : 0.0;
+    }
   };
-  // Z = V^T Y: thread (pr, cc) = (tid / 32, tid % 32) owns Z[pr + 8 j][cc]
-  const int cc = tid & 31, pr = tid >> 5;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  // Z = V^T Y
+  const int zp = (wave & 1) * 16, zc = (wave >> 1) * 16;
+  v4d z = {0.0, 0.0, 0.0, 0.0};
   for (int64_t r0 = c; r0 < d; r0 += kTrailRows) {
-    {
-      const int rr = tid & 63, g = tid >> 6;  // rows by lane: coalesced along a column
-      const int64_t i = r0 + rr;
-#pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        const int q = g + 4 * m;
-        Vs[rr][q] = vat(i, q);
-        const double y = gld(Y + (int64_t)min(q, nc - 1) * ldw + min(i, d - 1));
-        Ys[rr][q] = (q < nc && i < d) ? y : 0.0;
-      }
-    }
+    stage(r0);
     __syncthreads();
-#pragma unroll 8
-    for (int rr = 0; rr < kTrailRows; ++rr) {
-      const double y = Ys[rr][cc];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[j] += Vs[rr][pr + 8 * j] * y;
-    }
+    for (int r = 0; r < kTrailRows; r += 4)
+      z = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[r + lk][zp + li], Ys[r + lk][zc + li], z, 0, 0, 0);
     __syncthreads();
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) Zs[pr + 8 * j][cc] = acc[j];
+  for (int v = 0; v < 4; ++v) Zs[zp + 4 * v + lk][zc + li] = z[v];
   __syncthreads();
-  // Z2 = T^T Z (T upper: Z2[p][cc] = sum_{q <= p} T[q][p] Z[q][cc])
+  // Z2 = T^T Z (T upper: Z2[p][cc] = sum_{q <= p} T[q][p] Z[q][cc]), negated
+  // for the update
+  const int cc = tid & 31, pr = tid >> 5;
   double z2[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int pp = pr + 8 * j;
-    double s = 0.0;
+    double sum = 0.0;
     if (pp < nbp)
-      for (int q = 0; q <= pp; ++q) s += gld(T + q * kPanel + pp) * Zs[q][cc];
-    z2[j] = s;
+      for (int q = 0; q <= pp; ++q) sum += gld(T + q * kPanel + pp) * Zs[q][cc];
+    z2[j] = -sum;
   }
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < 4; ++j) Zs[pr + 8 * j][cc] = z2[j];
   __syncthreads();
-  // Y -= V Z2: thread (rr, g) = (tid % 64, tid / 64) updates row r0 + rr in
-  // columns g + 4 m
-  const int rr = tid & 63, g = tid >> 6;
+  // Y -= V Z2, tile by tile: wave w updates rows [16 w, 16 w + 16) of the
+  // tile in both 16-column blocks, in LDS, then the tile is stored
+  const int yr = wave * 16;
   for (int64_t r0 = c; r0 < d; r0 += kTrailRows) {
-    const int64_t i = r0 + rr;
-    if (i >= d) continue;
-    double v[kPanel];
+    stage(r0);
+    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < kPanel; ++q) v[q] = vat(i, q);
+    for (int cbk = 0; cbk < 2; ++cbk) {
+      const int yc = cbk * 16;
+      v4d acc;
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      const int col = g + 4 * m;
-      if (col >= nc) continue;
-      double s = 0.0;
+      for (int v = 0; v < 4; ++v) acc[v] = Ys[yr + 4 * v + lk][yc + li];
 #pragma unroll
-      for (int q = 0; q < kPanel; ++q) s += v[q] * Zs[q][col];
-      double* y = Y + (int64_t)col * ldw + i;
-      gst(y, gld(y) - s);
+      for (int s = 0; s < kPanel; s += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[yr + li][s + lk], Zs[s + lk][yc + li], acc, 0, 0, 0);
+      // (each wave writes only its own rows of Ys, which no other wave reads)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Ys[yr + 4 * v + lk][yc + li] = acc[v];
     }
+    __syncthreads();
+    {
+      const int rr = tid & 63, g = tid >> 6;
+      const int64_t i = r0 + rr;
+      if (i < d) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const int q = g + 4 * m;
+          if (q < nc) gst(Y + (int64_t)q * ldw + i, Ys[rr][q]);
+        }
+      }
+    }
+    __syncthreads();
   }
+}
+
+__global__ void __launch_bounds__(256) hh_trail_blk_batched_kernel(const QrBatch* __restrict__ B, int c) {
+  const QrBatch& pb = B[blockIdx.y];
+  if (c >= pb.k) return;
+  hh_trail_blk_dev(pb.W, pb.ldw, pb.d, pb.k + 1, c, min(kPanel, pb.k - c),
+                   pb.T + (int64_t)(c / kPanel) * kPanel * kPanel, (int)blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) hh_trail_blk_kernel(double* __restrict__ W, int64_t ldw, int64_t d, int ncols,
+                                                           int c, int nbp, const double* __restrict__ T) {
+  hh_trail_blk_dev(W, ldw, d, ncols, c, nbp, T, (int)blockIdx.x);
 }
 
 __global__ void extract_r_batched_kernel(const QrBatch* __restrict__ B) {
@@ -660,7 +630,8 @@ int qr_columns(double* W, int64_t ldw, int64_t d, int k, int extra_cols, double*
     const int first = c + nbp;
     const int ntrail = k + extra_cols - first;
     if (ntrail > 0) {
-      hipLaunchKernelGGL(hh_trail_kernel, dim3(ntrail), dim3(256), 0, st, W, ldw, d, c, nbp, first, T);
+      const unsigned nblk = (unsigned)((ntrail + kPanel - 1) / kPanel);
+      hipLaunchKernelGGL(hh_trail_blk_kernel, dim3(nblk), dim3(256), 0, st, W, ldw, d, k + extra_cols, c, nbp, T);
       SK_HIP(hipGetLastError());
     }
   }
