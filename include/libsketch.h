@@ -341,17 +341,24 @@ typedef struct {
  * certainly passes the rank test of Alg. 3 (s_k > 5 eps s_1), and its
  * truncated-SVD solution is x = R^-1 c, computed directly; the others are
  * redone with the SVD of R in a second pass, exactly as lstsq_sketch_solve
- * does. The problems' sketches run back to back on one stream that the
- * call creates (default priority) and that starts after the work already
- * queued on `stream`, each in the same slot of one workspace (ws, ws_bytes >=
- * lstsq_batched_workspace_size; NULL to allocate and free one inside the
- * call); [S A | S b] of every problem with d <= 1024 and k <= 512 goes to its
- * own buffers, and their Householder QRs, R^-1 and certified solves then run
- * for all of them together on `stream`, one launch per panel step (the other
- * problems take those steps one by one on the call's stream). The call waits
- * once per pass and returns with every x written. A problem's t_ms runs from
- * the start of its sketch to the end of the batched solve (or of its own
- * solve). Every problem is validated
+ * does. The work runs on one stream that the call creates (default
+ * priority) and that starts after the work already queued on `stream`, in
+ * one workspace (ws, ws_bytes >= lstsq_batched_workspace_size; NULL to
+ * allocate and free one inside the call). For the problems with d <= 1024
+ * and k <= 512 (and, for their sketch, k >= 4, zeta >= 4 and rows of A that
+ * are 4-byte aligned), [S A | S b] is computed for all of them together: one
+ * launch for the row codes, one per accumulator register file for the
+ * applies (b as the column after A's last), one for the chunk sums, each
+ * problem's result landing in its own buffer; their Householder QRs, R^-1
+ * and certified solves then run together on `stream`, one launch per panel
+ * step. The other problems take the single-problem steps one by one, in one
+ * slot of the workspace. The batched sketch keeps every problem's row codes
+ * and partial sums in the workspace at once (about 8 and 4 bytes per row and
+ * block, and 1/16 of A's bytes; problems are grouped when that passes
+ * 16 GiB). The call waits once per pass and returns with every x written. A
+ * problem's t_ms runs from the start of its sketch (the batched sketch's
+ * start for the problems in it) to the end of the batched solve (or of its
+ * own solve). Every problem is validated
  * before any work is queued: if one is invalid, its status is SK_E_INVAL,
  * nothing runs, and SK_E_INVAL is returned; if the apply refuses one's data
  * layout (more than 4 columns whose rows are not 4-byte multiples, as BF16
