@@ -823,7 +823,12 @@ int launch_idx_sketch(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64
     if (_rc < 0) return _rc; \
   } while (0)
 namespace {
-constexpr size_t kBatchAreaCap = (size_t)16 << 30;  // codes + partials of one launch group
+// Codes and partials of one launch group: 16 GiB, or SKETCH_BATCH_AREA_MB
+// (a smaller area splits a batch into more groups; the results do not change).
+size_t batch_area_cap() {
+  const int mb = env_i("SKETCH_BATCH_AREA_MB", 0);
+  return mb > 0 ? (size_t)mb << 20 : (size_t)16 << 30;
+}
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int batch_load_bytes(int dtype_in, int64_t k, const void* A, int64_t lda) {
@@ -932,7 +937,7 @@ int batch_plans(const IdxBatchJob* jobs, int njobs, std::vector<BatchPlanned>* p
     total += need;
     mx = std::max(mx, need);
   }
-  *area = std::max(std::min(total, kBatchAreaCap), mx);
+  *area = std::max(std::min(total, batch_area_cap()), mx);
   return SK_OK;
 }
 }  // namespace

@@ -218,3 +218,20 @@ def test_batched_sketch_variants_match_oracle(lib):
     again = lib.solve_batched(problems)[0]
     for a, b in zip(xs, again):
         assert torch.equal(a, b)
+
+
+def test_batched_sketch_groups_do_not_change_results(lib, monkeypatch):
+    """A batch whose codes and partials do not fit one area is sketched in several launch groups (here one problem
+    a group, through SKETCH_BATCH_AREA_MB); every problem's plan and arithmetic are its own, so the solutions are
+    bitwise those of the one-group run."""
+    problems = []
+    for i, (n, k, dt, pad) in enumerate(VARIANTS[:8]):
+        A, b = _problem(n, k, dt, 300 + i)
+        problems.append((A, b, 6000 + i))
+    one = lib.solve_batched(problems)
+    assert one[4] == 0
+    monkeypatch.setenv("SKETCH_BATCH_AREA_MB", "1")
+    split = lib.solve_batched(problems)
+    assert split[4] == 0 and split[1] == one[1] and split[2] == one[2]
+    for a, b in zip(one[0], split[0]):
+        assert torch.equal(a, b)
