@@ -275,7 +275,8 @@ int batched_layout(const sk_ls_problem* probs, int nprob, int d_per_k, int zeta,
     FactorBufs F;
     factor_bufs(fc, (int64_t)d_per_k * probs[i].k, (int)probs[i].k, &F);
     if (L->sketched[i])
-      jobs.push_back(IdxBatchJob{&L->sks[i], probs[i].dtype, probs[i].k, probs[i].A, probs[i].lda, probs[i].b, nullptr});
+      jobs.push_back(
+          IdxBatchJob{&L->sks[i], probs[i].dtype, probs[i].k, probs[i].A, probs[i].lda, probs[i].b, nullptr, 0});
   }
   L->bsk_off = al(L->factors_off + fc.off);
   L->bsk_bytes = 0;
@@ -544,7 +545,7 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
   std::vector<char> redo((size_t)nprob, 0);
   std::vector<double> t_ms((size_t)nprob, 0.0);
   // the batched sketches' host tables, alive until the stream has run them
-  std::vector<unsigned char> stage;
+  IdxBatchProgram stage;
   hipEvent_t bsk_start = nullptr;
   for (int pass = 0; pass < 2 && rc == SK_OK; ++pass) {
     bool queued = false;
@@ -558,7 +559,7 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
         Carver fc{base, L.factors_off + L.factor_at[i]};
         FactorBufs F;
         factor_bufs(fc, L.sks[i].d, (int)p.k, &F);
-        jobs.push_back(IdxBatchJob{&L.sks[i], p.dtype, p.k, p.A, p.lda, p.b, F.W});
+        jobs.push_back(IdxBatchJob{&L.sks[i], p.dtype, p.k, p.A, p.lda, p.b, F.W, 0});
         host_table.push_back(
             QrBatch{F.W, L.sks[i].d, L.sks[i].d, (int)p.k, 0, F.tau, F.T, F.R, F.c, F.X, F.XT, p.x, ranks + i});
         kmax = std::max(kmax, (int)p.k);

@@ -84,6 +84,24 @@ __global__ void __launch_bounds__(1024) certified_tri_solve_batched_kernel(const
   certified_tri_solve_dev(p.R, p.X, p.c, p.k, eps, p.x, p.rank);
 }
 
+__global__ void __launch_bounds__(1024) svd_fallback_batched_kernel(const QrBatch* __restrict__ B, double eps) {
+  const QrBatch& p = B[blockIdx.x];
+  if (p.k == 0 || !p.Uc) return;
+  // (every thread reads the rank before any thread of a problem that goes on
+  // can write it: the first write comes after the SVD's barriers)
+  if (*p.rank >= 0) return;
+  jacobi_svd_dev(p.R, p.k, p.X, p.sv, p.XT, p.Uc, p.Vc);
+  __syncthreads();
+  svd_solve_dev(p.X, p.sv, p.XT, p.c, p.k, eps, p.x, p.z, p.rank);
+}
+
+int svd_fallback_batched(const QrBatch* B, int nprob, double eps, hipStream_t st) {
+  if (nprob <= 0) return SK_OK;
+  hipLaunchKernelGGL(svd_fallback_batched_kernel, dim3((unsigned)nprob), dim3(1024), 0, st, B, eps);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
 int launch_certified_tri_solve(const double* R, const double* X, const double* c, int k, double eps, double* x,
                                int* rank_out, hipStream_t st) {
   hipLaunchKernelGGL(certified_tri_solve_kernel, dim3(1), dim3(1024), 0, st, R, X, c, k, eps, x, rank_out);

@@ -34,13 +34,15 @@ int launch_fill(double* x, int64_t n, double value, hipStream_t st);
 // One small problem of a batch (device memory): W (d x (k + 1), column-major,
 // ldw) = [S A | S b] on entry; tau (k), T (qr_tbuf_doubles(k)), R (k x k),
 // c (k), X and XT (k x k) are its outputs; x (k) and *rank its solution.
-// k = 0 marks an entry that the batched launches skip.
+// k = 0 marks an entry that the batched launches skip. Uc, Vc (k x k) and
+// sv, z (k) are the SVD fallback's buffers (null: no fallback for it).
 struct QrBatch {
   double* W;
   int64_t ldw, d;
   int k, pad;
   double *tau, *T, *R, *c, *X, *XT, *x;
   int* rank;
+  double *Uc, *Vc, *sv, *z;
 };
 // For every problem of the table B (nprob entries, d <= 1024, k <= kmax <=
 // 512): the blocked Householder QR of W (32-column panels), R and c, and X =
@@ -49,5 +51,9 @@ struct QrBatch {
 int qr_trinv_batched(const QrBatch* B, int nprob, int kmax, hipStream_t st);
 // Alg. 3's certified solve (launch_certified_tri_solve) for every problem of B.
 int certified_tri_solve_batched(const QrBatch* B, int nprob, double eps, hipStream_t st);
+// For every problem of B whose certificate failed (*rank < 0): the Jacobi SVD
+// of R and the truncated solve (Alg. 3), one workgroup a problem, with X and
+// XT as U and V (R^-1 is not needed any more) and Uc, Vc, sv, z as the rest.
+int svd_fallback_batched(const QrBatch* B, int nprob, double eps, hipStream_t st);
 
 }  // namespace sk

@@ -54,9 +54,13 @@ int launch_idx_sketch(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64
 // d, S the job's SparseStack (A row-major n x k, b n values, both of the
 // job's dtype). idx_batch_fits says whether a job can go into the batched
 // launches; the workspace holds the tables, the row codes and the partial
-// sums (groups of jobs share one area of at most 16 GiB, or one job's need);
-// stage is host memory that must stay alive until the stream has run the
-// launches.
+// sums (groups of jobs share one area of at most 16 GiB, or one job's need).
+// idx_batch_prepare plans the jobs into the workspace and writes the
+// tables (host copy, to be uploaded to the start of ws); idx_batch_enqueue
+// queues the kernels only (no copies: it may be captured);
+// launch_idx_batch does both with an asynchronous upload, so prog (host
+// memory) must stay alive until the stream has run it. chunk_mult: row
+// chunks of at least chunk_mult * d rows (0: 16).
 struct IdxBatchJob {
   const sk_sketch* S;
   int dtype;
@@ -65,11 +69,26 @@ struct IdxBatchJob {
   int64_t lda;
   const void* b;
   double* W;
+  int chunk_mult;
+};
+struct IdxBatchLaunch {
+  int kind;  // 0 codes, 1 apply, 2 chunk sums of FP64 partials, 3 of FP32 partials
+  int first, count, dtype;
+  int64_t grid;
+  RowsPlan plan;  // the apply variant's launch shape
+};
+struct IdxBatchProgram {
+  std::vector<unsigned char> tables;
+  std::vector<IdxBatchLaunch> launches;
+  void* ws = nullptr;
+  int njobs = 0;
 };
 bool idx_batch_fits(const sk_sketch* S, int dtype_in, int64_t k, const void* A, int64_t lda);
 int idx_batch_workspace(const IdxBatchJob* jobs, int njobs, size_t* bytes);
-int launch_idx_batch(const IdxBatchJob* jobs, int njobs, void* ws, size_t ws_bytes,
-                     std::vector<unsigned char>* stage, hipStream_t st);
+int idx_batch_prepare(const IdxBatchJob* jobs, int njobs, void* ws, size_t ws_bytes, IdxBatchProgram* prog);
+int idx_batch_enqueue(const IdxBatchProgram& prog, hipStream_t st);
+int launch_idx_batch(const IdxBatchJob* jobs, int njobs, void* ws, size_t ws_bytes, IdxBatchProgram* prog,
+                     hipStream_t st);
 
 int launch_rows_apply(const sk_sketch* S, const RowsPlan& p, int dtype_in, int64_t m, const void* A,
                       int64_t lda, int dtype_out, void* SA, int64_t ldsa, void* ws, hipStream_t st);

@@ -240,15 +240,25 @@ __device__ __forceinline__ void ss_idx_body(const IdxArgs& a, const unsigned cha
     unsigned char* dst = smem + buf * a.buf_stride;
     const unsigned char* tsrc = a.A + r0 * a.lda_bytes + col0 * ES;
     // load k covers chunks [64 k, 64 k + 64): a lane's chunk advances by
-    // 64 W chunks = RSTEP rows per load of its wave, at a fixed byte offset
+    // 64 W chunks per load of its wave. When that is a whole number RSTEP of
+    // rows, the lane keeps a fixed byte offset; otherwise (128 chunks a row,
+    // FP64 with 4-byte loads, and an odd number of waves) its row and offset
+    // are recomputed for every load.
     const int q0 = wave * 64 + lane;
-    const int cb = (q0 % CPR) * lb;
+    int cb = (q0 % CPR) * lb;
+    const bool whole_rows = (nwaves * 64) % CPR == 0;
     const int rstep = (nwaves * 64) / CPR;
     int row = q0 / CPR;
     const unsigned char* src = tsrc + (int64_t)row * a.lda_bytes + cb;
     const int64_t sstep = (int64_t)rstep * a.lda_bytes;
     for (int k = wave; k < n_instr; k += nwaves) {
       const uint32_t la = (uint32_t)__builtin_amdgcn_readfirstlane((int)idx_lds_addr(dst + k * 64 * lb));
+      if (!whole_rows) {
+        const int q = k * 64 + lane;
+        row = q / CPR;
+        cb = (q % CPR) * lb;
+        src = tsrc + (int64_t)row * a.lda_bytes + cb;
+      }
       if (row < rv && cb < slab_bytes) {
         if (lb == 16)
           idx_dma16(src, la);
@@ -608,7 +618,7 @@ bool idx_apply_fits(const sk_sketch* S, int dtype_in, int64_t m) {
 // batch_parts, two tile buffers, and row chunks sized for a launch that
 // many problems fill together rather than for filling the chip alone).
 static int plan_idx_lb(const sk_sketch* S, int dtype_in, int64_t m, int load_bytes, RowsPlan* p,
-                       bool batch = false) {
+                       bool batch = false, int chunk_mult = 16) {
   const int es = (int)dtype_size(dtype_in);
   const int zeta = S->zeta;
   const int nparts = batch ? batch_parts(dtype_in, S->nb) : idx_parts(dtype_in, S->nb);
@@ -671,10 +681,11 @@ static int plan_idx_lb(const sk_sketch* S, int dtype_in, int64_t m, int load_byt
   const int64_t items = (int64_t)p->n_slabs * p->n_groups;
   int64_t nc;
   if (batch) {
-    // chunks of at least 16 d rows (the partials then add at most about
-    // 1/16 of A's bytes) and 2048 rows; not rounded up to a multiple of 8
-    // (the grid is, and its surplus workgroups exit at once)
-    const int64_t rows = std::max<int64_t>(2048, 16 * S->d);
+    // chunks of at least chunk_mult d rows (16 by default: the partials
+    // then add at most about 1/16 of A's bytes) and 2048 rows; not rounded
+    // up to a multiple of 8 (the grid is, and its surplus workgroups exit at
+    // once)
+    const int64_t rows = std::max<int64_t>(2048, (int64_t)std::max(1, chunk_mult) * S->d);
     nc = std::max<int64_t>(1, (n + rows - 1) / rows);
   } else {
     const int target = env_i("SKETCH_IDX_WG", 256 * wg_per_cu);
@@ -896,7 +907,7 @@ int plan_batch_job(const IdxBatchJob& j, BatchPlanned* out) {
     set_error("batched sketch: A must be 4-byte aligned with lda*elsize and k*elsize multiples of 4");
     return SK_E_NOTSUP;
   }
-  SK_IDX_TRY(plan_idx_lb(j.S, j.dtype, j.k + 1, lb, &out->p, true));
+  SK_IDX_TRY(plan_idx_lb(j.S, j.dtype, j.k + 1, lb, &out->p, true, j.chunk_mult > 0 ? j.chunk_mult : 16));
   const RowsPlan& p = out->p;
   out->key = batch_key(j.dtype, p);
   out->wg = ((int64_t)(p.n_chunks + 7) / 8) * 8 * p.n_slabs * p.n_groups;
@@ -944,7 +955,7 @@ int batch_plans(const IdxBatchJob* jobs, int njobs, std::vector<BatchPlanned>* p
 
 bool idx_batch_fits(const sk_sketch* S, int dtype_in, int64_t k, const void* A, int64_t lda) {
   if (env_i("SKETCH_IDX", 1) == 0) return false;
-  return S->kind == SK_SPARSESTACK && k >= 4 && S->zeta >= 4 && batch_parts(dtype_in, S->nb) != 0 &&
+  return S->kind == SK_SPARSESTACK && k >= 4 && S->zeta >= 1 && batch_parts(dtype_in, S->nb) != 0 &&
          batch_load_bytes(dtype_in, k, A, lda) != 0;
 }
 
@@ -956,8 +967,11 @@ int idx_batch_workspace(const IdxBatchJob* jobs, int njobs, size_t* bytes) {
   return SK_OK;
 }
 
-int launch_idx_batch(const IdxBatchJob* jobs, int njobs, void* ws, size_t ws_bytes,
-                     std::vector<unsigned char>* stage, hipStream_t st) {
+int idx_batch_prepare(const IdxBatchJob* jobs, int njobs, void* ws, size_t ws_bytes, IdxBatchProgram* prog) {
+  prog->tables.clear();
+  prog->launches.clear();
+  prog->ws = ws;
+  prog->njobs = njobs;
   if (njobs <= 0) return SK_OK;
   std::vector<BatchPlanned> pl;
   size_t area = 0;
@@ -971,6 +985,7 @@ int launch_idx_batch(const IdxBatchJob* jobs, int njobs, void* ws, size_t ws_byt
   const size_t off_codes_tab = al256(sizeof(IdxBatchEntry) * (size_t)njobs);
   const size_t off_red_tab = off_codes_tab + al256(sizeof(IdxCodesEntry) * (size_t)njobs);
   unsigned char* area_base = base + tables;
+  std::vector<unsigned char>* stage = &prog->tables;
   stage->assign(tables, 0);
   IdxBatchEntry* h_ent = (IdxBatchEntry*)stage->data();
   IdxCodesEntry* h_cod = (IdxCodesEntry*)(stage->data() + off_codes_tab);
@@ -980,13 +995,8 @@ int launch_idx_batch(const IdxBatchJob* jobs, int njobs, void* ws, size_t ws_byt
   // together): one codes launch, the applies by variant, the reductions by
   // partial type. Job i's codes entry is slot i; its apply and reduce
   // entries take slots of the group's range in launch order.
-  struct Launch {
-    int kind;  // 0 codes, 1 apply, 2 reduce of FP64 partials, 3 of FP32 partials
-    int first, count, dtype;
-    int64_t grid;
-    const RowsPlan* plan;
-  };
-  std::vector<Launch> launches;
+  using Launch = IdxBatchLaunch;
+  std::vector<Launch>& launches = prog->launches;
   for (const auto& gr : batch_groups(pl, area)) {
     std::vector<size_t> part_off;
     size_t off = 0;
@@ -1015,7 +1025,7 @@ int launch_idx_batch(const IdxBatchJob* jobs, int njobs, void* ws, size_t ws_byt
       blk += (items + 256 * kCodesPerThread - 1) / (256 * kCodesPerThread);
       off += pl[i].codes_bytes;
     }
-    launches.push_back(Launch{0, gr.first, gr.second - gr.first, 0, blk, nullptr});
+    launches.push_back(Launch{0, gr.first, gr.second - gr.first, 0, blk, RowsPlan{}});
     for (int i = gr.first; i < gr.second; ++i) {
       part_off.push_back(off);
       off += pl[i].partial_bytes;
@@ -1069,7 +1079,7 @@ int launch_idx_batch(const IdxBatchJob* jobs, int njobs, void* ws, size_t ws_byt
         wg += pl[i].wg;
       }
       launches.push_back(Launch{1, first, slot - first, jobs[order[first - gr.first]].dtype, wg,
-                                &pl[order[first - gr.first]].p});
+                                pl[order[first - gr.first]].p});
     }
     slot = gr.first;
     for (int kind = 2; kind <= 3; ++kind) {
@@ -1089,15 +1099,24 @@ int launch_idx_batch(const IdxBatchJob* jobs, int njobs, void* ws, size_t ws_byt
         e.blk_begin = rblk;
         rblk += ((e.d + 63) / 64) * e.col_tiles;
       }
-      if (slot > first) launches.push_back(Launch{kind, first, slot - first, 0, rblk, nullptr});
+      if (slot > first) launches.push_back(Launch{kind, first, slot - first, 0, rblk, RowsPlan{}});
     }
   }
-  SK_HIP(hipMemcpyAsync(base, stage->data(), tables, hipMemcpyHostToDevice, st));
+  return SK_OK;
+}
+
+int idx_batch_enqueue(const IdxBatchProgram& prog, hipStream_t st) {
+  if (prog.launches.empty()) return SK_OK;
+  const int njobs = prog.njobs;
+  unsigned char* base = (unsigned char*)prog.ws;
+  const size_t off_codes_tab = al256(sizeof(IdxBatchEntry) * (size_t)njobs);
+  const size_t off_red_tab = off_codes_tab + al256(sizeof(IdxCodesEntry) * (size_t)njobs);
+  unsigned char* area_base = base + batch_tables_bytes(njobs);
   const IdxBatchEntry* d_ent = (const IdxBatchEntry*)base;
   const IdxCodesEntry* d_cod = (const IdxCodesEntry*)(base + off_codes_tab);
   const IdxReduceEntry* d_red = (const IdxReduceEntry*)(base + off_red_tab);
   uint32_t* codes = (uint32_t*)area_base;
-  for (const auto& l : launches) {
+  for (const auto& l : prog.launches) {
     if (l.grid <= 0) continue;
     if (l.kind == 0) {
       hipLaunchKernelGGL(ss_idx_plan_batched_kernel, dim3((unsigned)l.grid), dim3(256), 0, st, d_cod + l.first,
@@ -1106,11 +1125,11 @@ int launch_idx_batch(const IdxBatchJob* jobs, int njobs, void* ws, size_t ws_byt
     } else if (l.kind == 1) {
       const IdxBatchEntry* tab = d_ent + l.first;
       if (l.dtype == SK_F64)
-        SK_IDX_TRY(launch_variant_t<double>(*l.plan, tab, l.count, l.grid, codes, st));
+        SK_IDX_TRY(launch_variant_t<double>(l.plan, tab, l.count, l.grid, codes, st));
       else if (l.dtype == SK_F32)
-        SK_IDX_TRY(launch_variant_t<float>(*l.plan, tab, l.count, l.grid, codes, st));
+        SK_IDX_TRY(launch_variant_t<float>(l.plan, tab, l.count, l.grid, codes, st));
       else
-        SK_IDX_TRY(launch_variant_t<uint16_t>(*l.plan, tab, l.count, l.grid, codes, st));
+        SK_IDX_TRY(launch_variant_t<uint16_t>(l.plan, tab, l.count, l.grid, codes, st));
     } else {
       if (l.kind == 2)
         hipLaunchKernelGGL(idx_reduce_batched_kernel<double>, dim3((unsigned)l.grid), dim3(256), 0, st,
@@ -1122,6 +1141,14 @@ int launch_idx_batch(const IdxBatchJob* jobs, int njobs, void* ws, size_t ws_byt
     }
   }
   return SK_OK;
+}
+
+int launch_idx_batch(const IdxBatchJob* jobs, int njobs, void* ws, size_t ws_bytes, IdxBatchProgram* prog,
+                     hipStream_t st) {
+  SK_IDX_TRY(idx_batch_prepare(jobs, njobs, ws, ws_bytes, prog));
+  if (prog->launches.empty()) return SK_OK;
+  SK_HIP(hipMemcpyAsync(ws, prog->tables.data(), prog->tables.size(), hipMemcpyHostToDevice, st));
+  return idx_batch_enqueue(*prog, st);
 }
 
 }  // namespace sk

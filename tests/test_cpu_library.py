@@ -125,12 +125,12 @@ def test_batched_rejects_invalid_problems_before_any_work():
     assert lib.lstsq_batched_workspace_size(arr, 2, 4, 4, ctypes.byref(size)) == libsketch.SK_E_INVAL
 
 
-def test_batch_plan_is_switched_off():
-    """The persistent batch plan is disabled until the hang of its first device run is explained:
-    lstsq_batched_create refuses with SK_E_NOTSUP (before any device call) and says why."""
+def test_batch_plan_validates_before_any_device_call():
+    """lstsq_batched_create checks every problem before it touches the device: an empty problem (n = 0, null
+    pointers) is refused with SK_E_INVAL and a message naming it, and no plan is returned."""
     from paper_2508_21189_amd import libsketch
     lib = libsketch.load()
     arr = (libsketch.LsProblem * 1)()
     h = ctypes.c_void_p()
-    assert lib.lstsq_batched_create(arr, 1, 4, 4, 0, ctypes.byref(h)) == libsketch.SK_E_NOTSUP
-    assert h.value is None and "disabled" in libsketch.last_error()
+    assert lib.lstsq_batched_create(arr, 1, 4, 4, 0, ctypes.byref(h)) == libsketch.SK_E_INVAL
+    assert h.value is None and "problem 0" in libsketch.last_error()

@@ -90,6 +90,8 @@ CASES = [
     (20011, 100, 1200, 8, 29), # 150 buckets per block: two bucket parts of the register file
     (12007, 500, 2000, 8, 30), # 250 buckets (the mixed-precision shape): three parts, eight slabs
     (9001, 70, 1600, 4, 31),   # 400 buckets: four parts, one block per workgroup group
+    (20011, 33, 500, 5, 32),   # zeta = 5, FP64 rows of 264 bytes (4-byte loads): 1.5 tile rows a load step
+    (9001, 51, 700, 7, 33),    # zeta = 7, the same with seven waves a workgroup
 ]
 
 
