@@ -370,64 +370,63 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
                                void* stream);
 
 /*
- * Batch plan of the batched sketch-and-solve: DISABLED in this build.
- * lstsq_batched_create returns SK_E_NOTSUP (its first device run did not
- * complete and the cause is not yet identified); the other plan calls
- * need a plan and so cannot be reached. The design it implements:
- *
- * Batched sketch-and-solve (Alg. 3 for every problem, as lstsq_sketch_solve):
- * problem p is solved with its own SparseStack sketch of d = d_per_k * k
- * rows in zeta blocks (zeta must divide d; d <= 1024) under key p.seed,
- * reading A and b in their own precision (F32 and BF16 accumulate the sketch
- * in F32; the QR, the SVD and the solve are F64). After the Householder QR
- * S [A b] = Q [R c; 0 *], a problem whose ||R||_F ||R^-1||_F < 1e-3 / (5 eps)
- * certainly passes the rank test of Alg. 3 (s_k > 5 eps s_1) and gets
- * x = R^-1 c; the others get the truncated-SVD solution from the SVD of R,
- * exactly as lstsq_sketch_solve.
+ * Batch plan of the batched sketch-and-solve (Alg. 3 for every problem, as
+ * lstsq_sketch_solve): problem p is solved with its own SparseStack sketch
+ * of d = d_per_k * k rows in zeta blocks (zeta must divide d; d <= 1024,
+ * k <= 512) under key p.seed, reading A and b in their own precision (F32
+ * and BF16 accumulate the sketch in F32; the QR, the SVD and the solve are
+ * F64). After the Householder QR S [A b] = Q [R c; 0 *], a problem whose
+ * ||R||_F ||R^-1||_F < 1e-3 / (5 eps) certainly passes the rank test of
+ * Alg. 3 (s_k > 5 eps s_1) and gets x = R^-1 c; the others get the
+ * truncated-SVD solution from the Jacobi SVD of R, exactly as
+ * lstsq_sketch_solve.
  *
  * A batch plan fixes the problems (their shapes and device pointers) and
- * runs the whole batch as one graph launch of five kernels: counter
- * initialization, the row codes of every problem, a persistent sketch worker
- * whose workgroups pop (problem, row chunk, column slab) units from eight
- * per-XCD device queues and reduce the partial sums of each problem as soon
- * as its last unit is done, a persistent solve worker (blocked Householder
- * QR and the certified triangular solve, one workgroup per problem, largest
- * k first), and the SVD fallback for problems the certificate rejects.
+ * runs the whole batch as one graph launch: the row codes of every problem,
+ * the bucket-indexed applies (one kernel per accumulator register file, b
+ * as the column after A's last), the chunk sums into each problem's
+ * column-major [S A | S b], the batched Householder QR (one panel and one
+ * trailing-update kernel per 32 columns), R^-1, the certified solve and the
+ * SVD fallback (which returns at once for the certified problems).
  * Everything lives in one caller workspace; a launch allocates nothing,
- * waits for nothing and records no memset, so it may also be captured into
- * a caller's graph (lstsq_batched_enqueue).
+ * waits for nothing and records no memset or copy, so it may also be
+ * captured into a caller's graph (lstsq_batched_enqueue).
  *
- * lstsq_batched_create validates the problems (SK_E_INVAL / SK_E_NOTSUP, the
- * error names the problem) and chooses each problem's tile rows and row-chunk
- * length from the tuning cache: a JSON file (SKETCH_TUNE_CACHE, else
- * $XDG_CACHE_HOME/libsketch/batched_tune.json, else
- * ~/.cache/libsketch/batched_tune.json) keyed by device, input type, column
- * slabs, bucket parts and waves per unit. With SK_BATCH_AUTOTUNE, classes
- * missing from the cache are timed first on (up to 16 of) the batch's own
- * problems, which reads their A and b, writes their x, allocates a
- * temporary workspace and synchronizes; the winners are written to the
- * cache. SK_BATCH_NOTUNE ignores the cache (default parameters).
+ * lstsq_batched_create validates the problems before any device call
+ * (SK_E_INVAL for an invalid problem; SK_E_NOTSUP, naming the problem, for
+ * d > 1024, k > 512 or k < 4, rows of A that are not 4-byte aligned, or b or
+ * x not aligned to their element size) and chooses each problem's row-chunk
+ * length (8, 16 or 32 times d rows; 16 by default) from the tuning cache: a
+ * JSON file (SKETCH_TUNE_CACHE, else $XDG_CACHE_HOME/libsketch/batched_tune.json,
+ * else ~/.cache/libsketch/batched_tune.json) keyed by device, input type,
+ * accumulator register file and bucket parts. With SK_BATCH_AUTOTUNE,
+ * classes missing from the cache are timed first on (up to 16 of) the
+ * batch's own problems (the batched sketch alone: it reads their A and b,
+ * allocates a temporary workspace and synchronizes); the winners are written
+ * to the cache. SK_BATCH_NOTUNE ignores the cache (the default length).
  * lstsq_batched_workspace gives the workspace bytes; lstsq_batched_bind
  * uploads the plan's tables into ws (256-byte aligned; synchronizes
  * `stream`) and captures the graph, which stays bound to ws: the workspace
  * must outlive the plan's launches and hold nothing else meanwhile.
- * lstsq_batched_launch enqueues one graph launch on `stream`;
- * lstsq_batched_enqueue enqueues the same kernels one by one (for callers
- * capturing `stream` themselves). Launches on one plan must not overlap.
- * lstsq_batched_results waits for `stream` and fills status, rank and t_ms
- * of probs[0 .. nprob) (SK_W_RANKDEF if some problem was rank deficient).
+ * lstsq_batched_launch enqueues one graph launch on `stream`, bracketed by
+ * two events; lstsq_batched_enqueue enqueues the same kernels one by one
+ * (for callers capturing `stream` themselves). Launches on one plan must not
+ * overlap. lstsq_batched_results waits for `stream` and fills status, rank
+ * and t_ms of probs[0 .. nprob) (t_ms: the device time of the last
+ * lstsq_batched_launch, the same for every problem; 0 after an enqueue),
+ * returning SK_W_RANKDEF if some problem was rank deficient.
  * lstsq_batched_info reports the plan's graph launches and shape.
  */
 typedef struct sk_batch* sk_batch_t;
 enum { SK_BATCH_AUTOTUNE = 1, SK_BATCH_NOTUNE = 2 };
 typedef struct {
   int64_t graph_launches;  /* lstsq_batched_launch calls so far */
-  int kernel_nodes;        /* kernel nodes in the batch graph */
-  int sketch_workgroups;   /* workgroups of the persistent sketch worker */
-  int solve_workgroups;    /* workgroups of the persistent solve worker */
-  int sketch_items;        /* items in the static sketch queues */
-  int reduce_items;        /* reduce items (pushed to the ready queue) */
-  int tuned;               /* problems whose tile parameters came from the tuning cache */
+  int kernel_nodes;        /* nodes in the batch graph (all kernels) */
+  int sketch_workgroups;   /* workgroups of the apply launches, summed */
+  int solve_workgroups;    /* workgroups of each solve launch (one a problem) */
+  int sketch_items;        /* apply launches (one per accumulator register file) */
+  int reduce_items;        /* workgroups of the chunk-sum launches */
+  int tuned;               /* problems whose chunk length came from the tuning cache */
   int pad_;
   size_t workspace_bytes;
 } sk_batch_info;
