@@ -458,6 +458,44 @@ def batched_solves(libsketch, torch, reps, nprob=512):
         walls.append(time.perf_counter() - t0)
         lat = t_ms
     err = [float((x - xp).norm() / xp.norm()) for x, xp in zip(xs, planted)]
+    # the same batch through a batch plan: one graph launch per batch (default chunk lengths, then tuned ones
+    # from a fresh cache); the plan's workspace and graph are made outside the timed region
+    plans = {}
+    import tempfile
+    with tempfile.TemporaryDirectory() as tdir:
+        old_cache = os.environ.get("SKETCH_TUNE_CACHE")
+        os.environ["SKETCH_TUNE_CACHE"] = os.path.join(tdir, "tune.json")
+        try:
+            for name, flags in (("default", libsketch.SK_BATCH_NOTUNE), ("tuned", libsketch.SK_BATCH_AUTOTUNE)):
+                plan = libsketch.BatchPlan(problems, 4, 4, flags)
+                plan.bind()
+                plan.launch()
+                plan.results()
+                pw = []
+                for _ in range(max(1, reps)):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    plan.launch()
+                    _, rk, pt, prc = plan.results()
+                    pw.append(time.perf_counter() - t0)
+                same = all(torch.equal(a, b) for a, b in zip(plan.xs, xs)) if name == "default" else None
+                inf = plan.info()
+                plans[name] = {"wall_s": round(statistics.median(pw), 4),
+                               "problems_per_s": round(nprob / statistics.median(pw), 1),
+                               "device_ms": round(pt[0], 3), "status": prc, "kernel_nodes": inf.kernel_nodes,
+                               "tuned_problems": inf.tuned}
+                if same is not None:
+                    plans[name]["bitwise_equal_to_one_call"] = same
+                print("bench: batch plan (%s) %.3f s (%.0f problems/s)" % (name, plans[name]["wall_s"],
+                                                                          plans[name]["problems_per_s"]),
+                      file=sys.stderr, flush=True)
+                plan.close()
+                del plan
+        finally:
+            if old_cache is None:
+                os.environ.pop("SKETCH_TUNE_CACHE", None)
+            else:
+                os.environ["SKETCH_TUNE_CACHE"] = old_cache
     lat_sorted = sorted(lat)
     wall = statistics.median(walls)
     out = {"workload": "%d problems, n log-uniform [1e4, 1e6], k uniform [16, 256], f32 N(0,1), d=4k, zeta=4"
@@ -467,7 +505,7 @@ def batched_solves(libsketch, torch, reps, nprob=512):
                                                                                           int(0.99 * len(lat)))], 4),
            "latency": "per problem, from the start of its sketch to the end of the batch's factorization and solve",
            "status": rc, "all_full_rank": all(r == int(k) for r, k in zip(ranks, ks)),
-           "median_rel_err_vs_planted": statistics.median(err)}
+           "median_rel_err_vs_planted": statistics.median(err), "plan": plans}
     print("bench: batched %d problems %.3f s (%.0f problems/s), p50 %.3f ms, p99 %.3f ms" %
           (nprob, wall, out["problems_per_s"], out["p50_ms"], out["p99_ms"]), file=sys.stderr, flush=True)
     del problems, planted, ws, xs
