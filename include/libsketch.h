@@ -414,7 +414,8 @@ int lstsq_sketch_solve_batched(sk_ls_problem* probs, int nprob, int d_per_k, int
  * overlap. lstsq_batched_results waits for `stream` and fills status, rank
  * and t_ms of probs[0 .. nprob) (t_ms: the device time of the last
  * lstsq_batched_launch, the same for every problem; 0 after an enqueue),
- * returning SK_W_RANKDEF if some problem was rank deficient.
+ * returning SK_W_RANKDEF if some problem was rank deficient (SK_E_INVAL when
+ * nothing was launched or enqueued since the workspace was bound).
  * lstsq_batched_info reports the plan's graph launches and shape.
  */
 typedef struct sk_batch* sk_batch_t;

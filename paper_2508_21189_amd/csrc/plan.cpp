@@ -46,7 +46,8 @@ struct sk_batch {
   int64_t graph_launches = 0;
   int sketch_workgroups = 0, sketch_launches = 0, reduce_blocks = 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  bool timed = false;  // e0 and e1 bracket the last graph launch
+  bool timed = false;     // e0 and e1 bracket the last graph launch
+  bool launched = false;  // a launch or an enqueue since the last bind
   void* h_ranks = nullptr;
   bool bound = false;
 };
@@ -321,6 +322,8 @@ int bind(sk_batch* B, void* ws, hipStream_t st) {
   SK_HIP(hipGraphGetNodes(B->graph, nullptr, &nn));
   B->kernel_nodes = (int)nn;
   B->bound = true;
+  B->launched = false;
+  B->timed = false;
   return SK_OK;
 }
 
@@ -585,6 +588,7 @@ int lstsq_batched_launch(sk_batch_t B, void* stream) {
   SK_HIP(hipGraphLaunch(B->exec, st));
   SK_HIP(hipEventRecord(B->e1, st));
   B->timed = true;
+  B->launched = true;
   ++B->graph_launches;
   return SK_OK;
 }
@@ -595,12 +599,17 @@ int lstsq_batched_enqueue(sk_batch_t B, void* stream) {
     return SK_E_INVAL;
   }
   B->timed = false;
+  B->launched = true;
   return plan::enqueue_all(B, (hipStream_t)stream);
 }
 
 int lstsq_batched_results(sk_batch_t B, sk_ls_problem* probs, void* stream) {
   if (!B || !probs || !B->bound) {
     set_error("lstsq_batched_results: null argument or no workspace bound");
+    return SK_E_INVAL;
+  }
+  if (!B->launched) {
+    set_error("lstsq_batched_results: nothing was launched since the workspace was bound");
     return SK_E_INVAL;
   }
   return plan::results(B, probs, (hipStream_t)stream);

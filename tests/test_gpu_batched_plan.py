@@ -223,3 +223,6 @@ def test_plan_refuses_oversized_sketch_and_small_workspace(lib):
         plan.bind(ws)
     with pytest.raises(lib.SketchError):
         plan.launch()
+    plan.bind()
+    with pytest.raises(lib.SketchError):
+        plan.results()  # bound, but nothing launched yet
