@@ -1,6 +1,6 @@
 // Device helpers of the bucket-indexed SparseStack apply (register
 // accumulators addressed through the VALU's GPR-index mode), shared by the
-// single-matrix kernel and the batched persistent kernel.
+// row-mode kernels (single-matrix and batched) and the column-mode kernel.
 #pragma once
 #include "sk_common.hpp"
 
