@@ -55,6 +55,39 @@ __device__ inline void idx_dma4(const void* gsrc, uint32_t lds_addr) {
       : "s"(lds_addr), "v"(gsrc)
       : "memory");
 }
+// G 4-byte direct loads under one M0 setting: load j reads global address
+// g[j] + j * STEP and writes LDS at M0 + j * STEP + lane * 4 (the instruction
+// offset moves both addresses alike), so the caller passes g[j] already
+// lowered by j * STEP. (j * STEP must fit the 13-bit signed offset.)
+template <int G, int STEP>
+__device__ inline void idx_dma4_group(const void* const* g, uint32_t lds_addr) {
+  static_assert((G - 1) * STEP <= 4095, "instruction offset");
+  uint32_t saved;
+  if constexpr (G == 4)
+    asm volatile(
+        "s_mov_b32 %0, m0\n\t"
+        "s_mov_b32 m0, %1\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dword %2, off\n\t"
+        "global_load_lds_dword %3, off offset:%c6\n\t"
+        "global_load_lds_dword %4, off offset:%c7\n\t"
+        "global_load_lds_dword %5, off offset:%c8\n\t"
+        "s_mov_b32 m0, %0"
+        : "=&s"(saved)
+        : "s"(lds_addr), "v"(g[0]), "v"(g[1]), "v"(g[2]), "v"(g[3]), "i"(STEP), "i"(2 * STEP), "i"(3 * STEP)
+        : "memory");
+  else
+    asm volatile(
+        "s_mov_b32 %0, m0\n\t"
+        "s_mov_b32 m0, %1\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dword %2, off\n\t"
+        "global_load_lds_dword %3, off offset:%c4\n\t"
+        "s_mov_b32 m0, %0"
+        : "=&s"(saved)
+        : "s"(lds_addr), "v"(g[0]), "v"(g[1]), "i"(STEP)
+        : "memory");
+}
 __device__ inline uint32_t idx_lds_addr(const void* p) {
   return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const void*)p;
 }

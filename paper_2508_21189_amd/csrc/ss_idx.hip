@@ -251,7 +251,44 @@ __device__ __forceinline__ void ss_idx_body(const IdxArgs& a, const unsigned cha
     int row = q0 / CPR;
     const unsigned char* src = tsrc + (int64_t)row * a.lda_bytes + cb;
     const int64_t sstep = (int64_t)rstep * a.lda_bytes;
-    for (int k = wave; k < n_instr; k += nwaves) {
+    // A full tile read with 4-byte loads by 4 or 8 waves: the wave's loads go
+    // out 4 (or 2) under one M0 setting, 256 W bytes apart in LDS through the
+    // instruction offset (every row of a full tile is valid; a lane skips
+    // only chunks past the slab's bytes). This halves the instructions that
+    // the loads of such tiles cost.
+    const bool grouped = (LB == 0 || LB == 4) && lb == 4 && whole_rows && rv == R && (nwaves == 4 || nwaves == 8);
+    if (grouped) {
+      const int iters = (n_instr - wave + nwaves - 1) / nwaves;
+      int it = 0;
+      if (nwaves == 4) {
+        for (; it + 4 <= iters; it += 4) {
+          const uint32_t la =
+              (uint32_t)__builtin_amdgcn_readfirstlane((int)idx_lds_addr(dst + (wave + it * 4) * 256));
+          if (cb < slab_bytes) {
+            const void* g[4] = {src, src + sstep - 1024, src + 2 * sstep - 2048, src + 3 * sstep - 3072};
+            idx_dma4_group<4, 1024>(g, la);
+          }
+          src += 4 * sstep;
+        }
+      } else {
+        for (; it + 2 <= iters; it += 2) {
+          const uint32_t la =
+              (uint32_t)__builtin_amdgcn_readfirstlane((int)idx_lds_addr(dst + (wave + it * 8) * 256));
+          if (cb < slab_bytes) {
+            const void* g[2] = {src, src + sstep - 2048};
+            idx_dma4_group<2, 2048>(g, la);
+          }
+          src += 2 * sstep;
+        }
+      }
+      for (; it < iters; ++it) {
+        const uint32_t la =
+            (uint32_t)__builtin_amdgcn_readfirstlane((int)idx_lds_addr(dst + (wave + it * nwaves) * 256));
+        if (cb < slab_bytes) idx_dma4(src, la);
+        src += sstep;
+      }
+    }
+    for (int k = grouped ? n_instr : wave; k < n_instr; k += nwaves) {
       const uint32_t la = (uint32_t)__builtin_amdgcn_readfirstlane((int)idx_lds_addr(dst + k * 64 * lb));
       if (!whole_rows) {
         const int q = k * 64 + lane;
