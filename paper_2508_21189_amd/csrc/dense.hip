@@ -185,6 +185,8 @@ __device__ __forceinline__ void hh_panel_reg_dev(double* __restrict__ W, int64_t
                                                  double* __restrict__ tau, double* __restrict__ T) {
   __shared__ double red[NTH / 64][NB + 2];
   __shared__ double vals[NB + 2];
+  __shared__ double pivot[NB];
+  __shared__ double coef[4];  // beta, scale and t of the current column
   __shared__ double G[kPanel][kPanel + 1];
   __shared__ double Ts[kPanel][kPanel + 1];
   __shared__ double taus[kPanel];
@@ -204,6 +206,10 @@ __device__ __forceinline__ void hh_panel_reg_dev(double* __restrict__ W, int64_t
       x[i * NB + q] = (r < d && q < nbp) ? w : 0.0;
     }
   }
+  // Per column step one reduction and two barriers: D_q = sum over the rows
+  // below the pivot of x_jj x_q gives sigma^2 (q = jj) and, with the pivot
+  // row x_q[jj] (from the thread that holds it), v^T x_q = x_q[jj] + scale D_q
+  // for every other column, v being the reflector scaled to a unit pivot.
   for (int jj = 0; jj < nbp; ++jj) {
     // pivot column jj of this thread's rows (selected with static indices)
     double pc[RPT];
@@ -214,50 +220,18 @@ __device__ __forceinline__ void hh_panel_reg_dev(double* __restrict__ W, int64_t
       for (int q = 0; q < NB; ++q) v = (q == jj) ? x[i * NB + q] : v;
       pc[i] = v;
     }
-    double part = 0, alpha_part = 0;
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int lr = tid + NT * i;
-      if (lr > jj) part += pc[i] * pc[i];
-      if (lr == jj) alpha_part = pc[i];
-    }
-    // wave sums by DPP row rotations and broadcasts (no LDS traffic)
-    part = wave_sum_dpp(part);
-    alpha_part = wave_sum_dpp(alpha_part);
-    if (lane == 0) {
-      red[wave][0] = part;
-      red[wave][1] = alpha_part;
-    }
-    __syncthreads();
-    double sig2 = 0, alpha = 0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      sig2 += red[w][0];
-      alpha += red[w][1];
-    }
-    double t = 0, beta = alpha, scale = 0;
-    if (sig2 > 0) {
-      beta = -copysign(sqrt(alpha * alpha + sig2), alpha);
-      t = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    // v: scaled below the pivot, the implicit 1 at the pivot
-    double vv[RPT];
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int lr = tid + NT * i;
-      if (lr > jj && t != 0) pc[i] *= scale;
-      vv[i] = lr > jj ? pc[i] : (lr == jj ? 1.0 : 0.0);
-    }
     double acc[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       double sacc = 0;
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) sacc += vv[i] * x[i * NB + q];
+      for (int i = 0; i < RPT; ++i) sacc += (tid + NT * i > jj ? pc[i] : 0.0) * x[i * NB + q];
       acc[q] = sacc;
     }
-    __syncthreads();  // red is reused
+    if (tid == jj) {  // row jj is this thread's first (jj < NB <= NT)
+#pragma unroll
+      for (int q = 0; q < NB; ++q) pivot[q] = x[q];
+    }
     {
       // the NB wave sums at once: lane l ends with the sum of entry
       // l >> (6 - log2 NB) (transposed reduction, one exchange per halving)
@@ -266,23 +240,46 @@ __device__ __forceinline__ void hh_panel_reg_dev(double* __restrict__ W, int64_t
       if ((lane & ((1 << kShift) - 1)) == 0) red[wave][lane >> kShift] = v;
     }
     __syncthreads();
-    if (tid < nbp && tid != jj) {
-      double sacc = 0;
+    if (tid < nbp) {
+      double sig2 = 0, D = 0;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) sacc += red[w][tid];
-      vals[tid] = sacc;
-      if (tid < jj) G[tid][jj] = sacc;
-    }
-    if (tid == 0) {
-      tau[k + jj] = t;
-      taus[jj] = t;
+      for (int w = 0; w < NW; ++w) {
+        sig2 += red[w][jj];
+        D += red[w][tid];
+      }
+      const double alpha = pivot[jj];
+      double t = 0, beta = alpha, scale = 0;
+      if (sig2 > 0) {
+        beta = -copysign(sqrt(alpha * alpha + sig2), alpha);
+        t = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      const double vq = pivot[tid] + scale * D;  // v^T x_tid (x_tid holds v_tid below its pivot for tid < jj)
+      if (tid < jj) G[tid][jj] = vq;
+      vals[tid] = (t != 0 && tid > jj) ? t * vq : 0.0;
+      if (tid == jj) {
+        coef[0] = beta;
+        coef[1] = scale;
+        coef[2] = t;
+        tau[k + jj] = t;
+        taus[jj] = t;
+      }
     }
     __syncthreads();
+    const double beta = coef[0], scale = coef[1], t = coef[2];
+    // v: scaled below the pivot, the implicit 1 at the pivot
+    double vv[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int lr = tid + NT * i;
+      if (lr > jj && t != 0) pc[i] *= scale;
+      vv[i] = lr > jj ? pc[i] : (lr == jj ? 1.0 : 0.0);
+    }
     // H = I - t v v^T on the later panel columns; the pivot column holds v
     // below the pivot and beta at it
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-      const double f = (t != 0 && q > jj && q < nbp) ? t * vals[q] : 0.0;
+      const double f = q < nbp ? vals[q] : 0.0;
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
         const int lr = tid + NT * i;
