@@ -290,7 +290,7 @@ int bind(sk_batch* B, void* ws, hipStream_t st) {
     if (l.kind == 1) {
       B->sketch_workgroups += (int)l.grid;
       ++B->sketch_launches;
-    } else if (l.kind >= 2) {
+    } else if (l.kind == 2 || l.kind == 3) {
       B->reduce_blocks += (int)l.grid;
     }
   }
